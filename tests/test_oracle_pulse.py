@@ -1,0 +1,110 @@
+"""Pins of the oracle pulse spectrum and synthesis against the paper's printed
+values (Table 1, the epsilon column, the carrier index, the time origin)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import pulse, series
+from workloads import Pulse, paper_sphere_pulse
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+W, T = 20.1, 128
+DK = 2 * np.pi / W
+
+
+def test_paper_pulse_spectrum_carrier_parity_and_ratios():
+    g = json.load(open(os.path.join(GOLD, "paper_constants.json")))
+    t1 = json.load(open(os.path.join(GOLD, "table1.json")))
+    c = pulse.coefficients(paper_sphere_pulse(), 63, DK, T, 0.0)
+    # odd pulse -> purely imaginary DFT
+    assert np.max(np.abs(c.real)) < 1e-14 * np.max(np.abs(c))
+    assert int(np.argmax(np.abs(c))) + 1 == g["carrier_index"]
+    a = np.sort(np.abs(c))[::-1] / np.max(np.abs(c))
+    for n, eps in zip(t1["n_terms"], t1["epsilon_lower_bound"]):
+        # the n-th retained ratio, at the printed precision, reaches epsilon
+        assert round(100 * a[n - 1], 1) >= round(100 * eps, 1)
+    assert abs(a[4] - 0.2424) < 5e-4 and abs(a[9] - 0.0350) < 5e-4 and abs(a[19] - 0.0090) < 5e-4
+
+
+def test_phase_factor_beta_matches_time_origin():
+    # c_m with z_s = -(a + w/4) equals (DFT with index origin at tau = -4 pi N_c)
+    # times e^{i beta}, beta = -k_m a [w/(4a) - 1]  (Sec. IV A)
+    P = paper_sphere_pulse()
+    c = pulse.coefficients(P, 63, DK, T, pulse.paper_time_shift(1.0, W))
+    s = pulse.sample_points(W, T)
+    F = pulse.pulse_samples(P, s)
+    m = np.arange(1, 64)
+    X = np.array([np.sum(F * np.exp(-2j * np.pi * mm * np.arange(T) / T)) for mm in m]) / T
+    beta = -DK * m * (W / 4.0 - 1.0)
+    assert np.max(np.abs(c - X * np.exp(1j * beta))) < 1e-15
+
+
+def test_incident_reconstruction_and_time_origin():
+    g = json.load(open(os.path.join(GOLD, "paper_constants.json")))
+    P = paper_sphere_pulse()
+    zs = pulse.paper_time_shift(1.0, W)
+    c = pulse.coefficients(P, 63, DK, T, zs)
+    # at sample-aligned positions the inverse DFT returns the shifted samples
+    for j in (0, 5, 64, 100):
+        z = zs + j * W / T
+        xp = np.array([[0.0, 0.0, z]])
+        p = pulse.synthesize(np.zeros((1, 63)), c, T, xp, DK, add_incident=True)[0]
+        t = np.arange(T) * W / T
+        s = z - t - zs
+        s = (s + W / 2) % W - W / 2
+        assert np.max(np.abs(p - pulse.pulse_samples(P, s))) < 1e-13
+    # front at z = -a at t = 0; oscillation over the sphere until step 77 (1-based)
+    tt = np.arange(T) * W / T
+    back = (1.0 - tt - zs)          # travelling coordinate at z = +a
+    on = np.abs(8 * np.pi * 1.0 / W * back) < 2 * np.pi * 1.0
+    last = int(np.flatnonzero(on)[-1]) + 1
+    assert last == g["last_step_oscillatory_on_sphere_1based"]
+    front = (-1.0 - tt - zs)        # at z = -a
+    assert abs(front[0] - W / 4) < 1e-12
+
+
+def test_synthesis_equals_explicit_sum():
+    rng = np.random.default_rng(1)
+    U = rng.standard_normal((3, 16)) + 1j * rng.standard_normal((3, 16))
+    c = rng.standard_normal(16) + 1j * rng.standard_normal(16)
+    for TT in (32, 64):
+        assert np.allclose(pulse.synthesize(U, c, TT), pulse.synthesize_direct(U, c, TT), atol=1e-12)
+
+
+def test_table1_from_sphere_series():
+    t1 = json.load(open(os.path.join(GOLD, "table1.json")))
+    P = paper_sphere_pulse()
+    c = pulse.coefficients(P, 63, DK, T, pulse.paper_time_shift(1.0, W))
+    pts = np.array([[0.0, 0.0, -1.1], [0.0, 0.0, -4.0]])
+    U = np.stack([series.scattered(DK * m, 1.0, "soft", pts) for m in range(1, 64)], axis=1)
+    full = pulse.synthesize(U, c, T)
+    for n, e11, e4 in zip(t1["n_terms"], t1["rms_percent_at_z_minus_1p1"], t1["rms_percent_at_z_minus_4"]):
+        idx = pulse.dominant(c, n)
+        ct = np.zeros_like(c)
+        ct[idx] = c[idx]
+        tr = pulse.synthesize(U, ct, T)
+        assert abs(pulse.rms_error_percent(tr[0], full[0]) - e11) <= t1["printed_precision"] + 1e-9
+        assert abs(pulse.rms_error_percent(tr[1], full[1]) - e4) <= t1["printed_precision"] + 1e-9
+
+
+@pytest.mark.parametrize("kind,params", [("gauss", {"sigma": 0.8}), ("ricker", {"sigma": 1.1}),
+                                         ("gsine", {"k0": 6.0, "sigma": 1.5})])
+def test_smooth_pulse_coefficients_match_continuous_transform(kind, params):
+    # For a smooth pulse well inside the period, c_m -> (1/L) * FT(k_m)
+    dk, n_k, TT = 12.0 / 256, 256, 512
+    L = 2 * np.pi / dk
+    c = pulse.coefficients(Pulse(kind, params), n_k, dk, TT, 0.0)
+    k = dk * np.arange(1, n_k + 1)
+    if kind == "gauss":
+        sg = params["sigma"]
+        ft = sg * np.sqrt(2 * np.pi) * np.exp(-0.5 * (k * sg) ** 2)
+    elif kind == "ricker":
+        sg = params["sigma"]
+        ft = sg ** 3 * np.sqrt(2 * np.pi) * k ** 2 * np.exp(-0.5 * (k * sg) ** 2)
+    else:
+        k0, sg = params["k0"], params["sigma"]
+        a = lambda q: sg * np.sqrt(2 * np.pi) * np.exp(-0.5 * (q * sg) ** 2)
+        ft = (a(k - k0) - a(k + k0)) / 2j
+    assert np.max(np.abs(c - ft / L)) < 1e-12 * L
