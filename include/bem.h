@@ -1,0 +1,255 @@
+/*
+ * bem.h - C ABI of the MI355X non-singular boundary-integral / Fourier
+ * space-time solver (Klaseboer, Sepehrirahnama & Chan, "Space-time domain
+ * solutions of the wave equation by a non-singular boundary integral method
+ * and Fourier transform").
+ *
+ * Conventions for every call
+ *   - Sound speed c = 1, time dependence e^{-i w t} with w = k (Sec. III,
+ *     Eq. inverseFourier); scattered fields radiate as e^{ikr}.
+ *   - Complex numbers are interleaved (re, im): "c64" = 2 x float,
+ *     "c128" = 2 x double.
+ *   - Surface normals point OUT OF THE BODY, into the fluid.
+ *   - Every pointer marked [dev] is a device pointer on the context's device;
+ *     [host] pointers are host memory.  All buffers are allocated and owned by
+ *     the caller; the library keeps no pointer after a call returns.
+ *   - Work is enqueued on the context's stream.  Calls that return values in
+ *     host memory synchronise that stream before returning; the others are
+ *     asynchronous with respect to the host.
+ *   - Argument checks happen on the host before any launch and return
+ *     BEM_EINVAL with a message available from bem_last_error().
+ */
+#ifndef BEM_H
+#define BEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BEM_OK = 0,
+  BEM_EINVAL = -1,        /* bad argument (NULL, size <= 0, non-finite k, ...) */
+  BEM_ENOMEM = -2,        /* device workspace could not be allocated */
+  BEM_EHIP = -3,          /* a HIP runtime call failed */
+  BEM_ESINGULAR = -4,     /* an exactly zero pivot was met in a factorisation */
+  BEM_ENOCONV = -5,       /* iterative refinement did not converge (fallback off) */
+  BEM_EUNSUPPORTED = -6   /* option not supported by this build */
+} bem_status;
+
+typedef enum { BEM_C64 = 0, BEM_C128 = 1 } bem_prec;
+
+/* Boundary condition flag per node (Sec. IV A). */
+enum { BEM_BC_HARD = 0,   /* dP/dn known (sound-hard): P is the unknown      */
+       BEM_BC_SOFT = 1 }; /* P known (sound-soft): dP/dn is the unknown      */
+
+typedef struct bem_ctx bem_ctx;
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream`
+ * (a hipStream_t, NULL = the null stream).  The context owns the solver
+ * workspace and the tuning cache; it is not thread-safe (one context per host
+ * thread).  Returns BEM_EHIP if the device cannot be selected. */
+bem_status bem_ctx_create(int device, void* hip_stream, bem_ctx** out);
+void bem_ctx_destroy(bem_ctx* ctx);
+/* Message of the last failed call on this context ("" if none). */
+const char* bem_last_error(const bem_ctx* ctx);
+/* Upper bound (bytes) of device workspace bem_solve_batched may hold; 0 = 75%
+ * of the free device memory at the time of the call. */
+bem_status bem_ctx_set_workspace_limit(bem_ctx* ctx, uint64_t bytes);
+
+/* Per-kernel accounting for roofline reports.  With profiling on, each launch
+ * of a counted kernel is bracketed by HIP events on the context stream and
+ * credited with its algorithmic work; bem_ctx_kernel_stats returns the sums
+ * (flops, bytes, milliseconds of device time, launch count) since profiling
+ * was last switched (set_profiling resets them).  Kernel names: "gemm_c32",
+ * "gemm_c64", "panel", "assemble", "residual", "getrs", "field", "synth".
+ * For "assemble"/"residual" the flop slot counts node pairs and for "field"
+ * kernel terms (point x frequency x node).  Unknown names report zeros.
+ * Synchronises the stream. */
+bem_status bem_ctx_set_profiling(bem_ctx* ctx, int32_t on);
+bem_status bem_ctx_kernel_stats(bem_ctx* ctx, const char* kernel, double* flops, double* bytes,
+                                double* ms, int64_t* launches);
+
+/* Discretised scatterer surface(s): n nodes with positions x[n][3], unit
+ * normals nrm[n][3] (out of the body), quadrature weights w[n] > 0 and flags
+ * bc[n] in {BEM_BC_HARD, BEM_BC_SOFT}; all [dev], float64/uint8.  The surface
+ * of several bodies is the concatenation of their nodes (Sec. III: S is the
+ * union of the scatterer surfaces). */
+typedef struct {
+  int32_t n;
+  const double* x;
+  const double* nrm;
+  const double* w;
+  const uint8_t* bc;
+} bem_surface;
+
+/* ---------------------------------------------------------------- geometry
+ * Icosphere surface of one body (the nodal discretisation of Sec. IV A's
+ * element meshes): `level` midpoint subdivisions of the icosahedron, mapped
+ * to center + (radius*u0, radius*u1, radius*aspect*u2); analytic normals;
+ * weights = 1/3 of the adjacent flat-triangle areas, rescaled to the analytic
+ * area if rescale_area != 0.  All outputs [host], caller-allocated with
+ * bem_mesh_counts() entries: x[V][3], nrm[V][3], w[V], faces[F][3].
+ * Arithmetic is done in a fixed order (no fused multiply-add), so results are
+ * reproducible bit for bit.  Returns BEM_EINVAL for level outside 0..7,
+ * radius <= 0 or aspect < 1. */
+bem_status bem_mesh_counts(int32_t level, int32_t* n_vertices, int32_t* n_faces);
+bem_status bem_mesh_icosphere(int32_t level, double radius, double aspect,
+                              const double center[3], int32_t rescale_area,
+                              double* x, double* nrm, double* w, int32_t* faces);
+
+/* ---------------------------------------------------------------- incident
+ * Known surface data of the scattered field for the incident plane wave
+ * e^{ik d.x} (Sec. IV A): y = -dP_inc/dn = -ik (d.n) e^{ik d.x} on hard nodes,
+ * y = -e^{ik d.x} on soft nodes.  k[n_k] [dev] float64, dir[3] [host] unit
+ * vector, y[n_k][n] c128 [dev]. */
+bem_status bem_incident(bem_ctx* ctx, const bem_surface* s, int32_t n_k, const double* k,
+                        const double dir[3], void* y);
+
+/* ---------------------------------------------------------------- assembly
+ * Dense system of the discrete non-singular boundary integral equation
+ * (Eq. BRIEF with f, g of Appendix A, S_inf integrals of Appendix B), nodal
+ * quadrature with collocation at the nodes:
+ *   (M_phi)_ij = -w_j H_ij,  (M_phi)_ii = 4 pi - sum_{j!=i} w_j (g'_ij G_ij - g_ij H_ij)
+ *   (M_psi)_ij =  w_j G_ij,  (M_psi)_ii =      - sum_{j!=i} w_j (f'_ij G_ij - f_ij H_ij)
+ * Column j of A is column j of M_phi (hard node) or M_psi (soft node); B holds
+ * the other columns; b = -B y for each right-hand side.
+ *   k[n_k]                 [dev] wavenumbers (> 0)
+ *   y[n_k][n_rhs][n]       [dev] c128 known data
+ *   A[n_k][n][ld]          [dev] ROW-MAJOR (element (i,j) at i*ld + j), c64 or
+ *                          c128 per `prec`; ld >= n
+ *   b[n_k][n_rhs][n]       [dev] c128
+ *   diag64[n_k][n][2]      [dev] c128 (M_phi)_ii, (M_psi)_ii, or NULL
+ * Every pair term is evaluated in float64; A is rounded to `prec` on store. */
+bem_status bem_assemble(bem_ctx* ctx, const bem_surface* s, int32_t n_k, const double* k,
+                        int32_t n_rhs, const void* y, bem_prec prec, void* A, int32_t ld,
+                        void* b, void* diag64);
+
+/* r = b - A x for the float64 operator regenerated on the fly (matrix-free):
+ *   x[n_k][n_rhs][n] c128 unknowns [dev], y as for bem_assemble,
+ *   diag64 from bem_assemble [dev], r[n_k][n_rhs][n] c128 [dev] (output). */
+bem_status bem_residual(bem_ctx* ctx, const bem_surface* s, int32_t n_k, const double* k,
+                        int32_t n_rhs, const void* y, const void* x, const void* diag64,
+                        void* r);
+
+/* ---------------------------------------------------------------- solve
+ * One linear system per wavenumber (Sec. IV A: direct solve).  Modes:
+ *   BEM_FP64_DIRECT : c128 assembly + float64 LU (MFMA f64) + triangular solves
+ *   BEM_FP32_IR_4M  : c64 LU (complex GEMM as 4 real products on MFMA f32,
+ *                     float32 accumulation) + iterative refinement with the
+ *                     float64 matrix-free residual, until ||dx||/||x|| <= tol_step
+ *   BEM_FP32_IR_3M  : as 4M with the 3-product complex GEMM
+ * Items that do not converge within max_iter are re-solved with the FP64
+ * direct path when fallback != 0 (flagged in info), else BEM_ENOCONV. */
+typedef enum { BEM_FP64_DIRECT = 0, BEM_FP32_IR_4M = 1, BEM_FP32_IR_3M = 2 } bem_mode;
+
+typedef struct {
+  const bem_surface* s;   /* [host] struct holding [dev] arrays */
+  int32_t n_k;
+  const double* k;        /* [dev] n_k wavenumbers */
+  int32_t n_rhs;
+  const void* y;          /* [dev] c128 [n_k][n_rhs][n] known data */
+} bem_problem;
+
+typedef struct {
+  int32_t mode;           /* bem_mode */
+  double tol_step;        /* stop when ||dx||_2/||x||_2 <= tol_step (default 1e-8) */
+  int32_t max_iter;       /* refinement sweeps (default 10) */
+  int32_t fallback;       /* 1: re-solve non-converged items in FP64 */
+  int32_t use_graph;      /* 1: replay the factorisation as a captured hipGraph */
+  int32_t nb;             /* panel width of the factorisation, 0 = tuned */
+} bem_solve_opts;
+
+typedef struct {
+  int32_t iters;          /* refinement sweeps done (0 for FP64_DIRECT) */
+  int32_t used_fp64;      /* 1 if the FP64 fallback produced the result */
+  int32_t singular;       /* 1 if a zero pivot was met */
+  int32_t pad;
+  double rel_resid;       /* ||b - A x||_2 / ||b||_2, float64 operator */
+  double rel_step;        /* last ||dx||_2/||x||_2 */
+} bem_solve_info;
+
+void bem_solve_opts_default(bem_solve_opts* opts);
+
+/* probs[n_probs] [host]; x_out[p] [dev] c128 [n_k][n_rhs][n] unknowns of
+ * problem p (P on hard nodes, dP/dn on soft nodes); info [host]
+ * [sum_p n_k*n_rhs] in problem order, or NULL.  Problems may have different
+ * n (uneven batch); all are scheduled together.  Synchronises the stream. */
+bem_status bem_solve_batched(bem_ctx* ctx, const bem_problem* probs, int32_t n_probs,
+                             const bem_solve_opts* opts, void* const* x_out,
+                             bem_solve_info* info);
+
+/* Building blocks of the direct solve (Sec. IV A), exposed for testing and for
+ * callers that keep the factors to re-use them for other right-hand sides
+ * (Sec. V: "the solution matrix ... can be stored").
+ * bem_getrf_batched: in-place LU with partial pivoting (P A = L U, unit L) of
+ *   `batch` row-major n x n matrices A + b*stride (elements of `prec`, leading
+ *   dimension ld >= n, stride >= n*ld elements) [dev].  piv[batch][n] [dev]
+ *   int32: row i was interchanged with row piv[i] (absolute, 0-based).
+ *   info[batch] [dev] int32: 0, or 1 + index of the first exactly-zero pivot.
+ *   nb = top-level panel width (0 = tuned), 3M selects the 3-product complex
+ *   GEMM for c64.
+ * bem_getrs_batched: X = A^{-1} B for n_rhs vectors per matrix:
+ *   B, X [dev] [batch][n_rhs][n] (vector stride n, matrix stride bstride
+ *   elements), same precision as the factors; B and X must not overlap. */
+bem_status bem_getrf_batched(bem_ctx* ctx, bem_prec prec, int32_t n, int32_t ld, int64_t stride,
+                             int32_t batch, void* A, int32_t* piv, int32_t* info, int32_t nb,
+                             int32_t use_3m);
+bem_status bem_getrs_batched(bem_ctx* ctx, bem_prec prec, int32_t n, int32_t ld, int64_t stride,
+                             int32_t batch, const void* LU, const int32_t* piv, int32_t n_rhs,
+                             const void* B, void* X, int64_t bstride);
+
+/* phi = (hard ? x : y), psi = (hard ? y : x): full surface data from the
+ * unknowns and the known data; all [dev] c128 [n_k][n_rhs][n]. */
+bem_status bem_split_unknowns(bem_ctx* ctx, const bem_surface* s, int32_t n_k, int32_t n_rhs,
+                              const void* x, const void* y, void* phi, void* psi);
+
+/* ---------------------------------------------------------------- field
+ * Scattered field at observation points by the non-singular representation
+ * (Eq. BRIEFdmn, S_inf part evaluated):
+ *   4 pi P(x_p) = 4 pi phi_i0 + sum_{j!=i0} w_j [u_j (H^p_j - H_i0j) - u'_j (G^p_j - G_i0j)]
+ * where i0 is the surface node closest to x_p (float64 squared distance
+ * (dx*dx+dy*dy)+dz*dz without fused multiply-add, ties to the lowest index)
+ * and u, u' are the surface data minus their f/g expansion about x_i0.
+ * Points with n_i0.(x_p - x_i0) < 0 are inside a body: U = 0, inside = 1.
+ *   k[n_k] [dev]; phi, psi [dev] c128 [n_k][n_rhs][n]; xp[m][3] [dev] float64
+ *   i0[m] [dev] int32: output, or input when i0_given != 0
+ *   inside[m] [dev] uint8 output
+ *   U [dev] [n_rhs][m][n_k], c64 (float32 kernel) or c128 (float64 kernel) */
+bem_status bem_field_eval(bem_ctx* ctx, const bem_surface* s, int32_t n_k, const double* k,
+                          int32_t n_rhs, const void* phi, const void* psi, int32_t m,
+                          const double* xp, int32_t* i0, int32_t i0_given, uint8_t* inside,
+                          bem_prec prec, void* U);
+
+/* ---------------------------------------------------------------- synthesis
+ * Space-time field by inverse DFT over frequency (Sec. III last paragraph,
+ * Sec. IV: Fourier components of a periodic pulse train):
+ *   p_q(x, t_n) = sum_{m=1}^{n_k} alpha_m Re[ c_q,m X_m(x) e^{-2 pi i m n / T} ]
+ * with alpha_m = 2 (m < T/2), 1 (m = T/2), X_m = U_m(x) (+ e^{i m dk z} when
+ * add_incident != 0), t_n = n * 2 pi / (dk T).
+ *   U[m][n_k] [dev] c64; c[n_pulse][n_k] [dev] c128; xp[m][3] [dev] (read
+ *   only when add_incident); p[n_pulse][m][T] [dev] float32 (output).
+ *   T: power of two, 64 <= T <= 8192, T >= 2 n_k. */
+bem_status pulse_synthesize(bem_ctx* ctx, int32_t m, int32_t n_k, const void* U,
+                            int32_t n_pulse, const double* c, int32_t T, int32_t add_incident,
+                            const double* xp, double dk, float* p);
+
+/* Fourier coefficients of a periodic incident pulse train F(z - t - z_shift)
+ * sampled at T left-closed points s_n = -L/2 + n L/T, L = 2 pi/dk:
+ *   c_m = (1/T) sum_n F(s_n) e^{-i k_m s_n} e^{-i k_m z_shift},  k_m = m dk,
+ * m = 1..n_k (Sec. IV, Eq. pulse and the phase factor e^{i beta}).
+ * kind / params:
+ *   0 paper  {N_c, alpha, w}: sin(tau) e^{-alpha|tau|} on |tau| < 2 pi N_c, tau = (8 pi N_c / w) s
+ *   1 gauss  {sigma}: e^{-s^2/2sigma^2}      2 ricker {sigma}: (1 - s^2/sigma^2) e^{-s^2/2sigma^2}
+ *   3 nwave  {sigma}: s/sigma on |s|<=sigma  4 chirp {ka, kb, D}: sin(ka s + (kb-ka) s^2/(2D)) e^{-s^2/2D^2}
+ *   5 gsine  {k0, sigma}: sin(k0 s) e^{-s^2/2sigma^2}
+ *   6 gaussk {k0, width}: spectrum exp(-(k-k0)^2/(2 width^2)) given directly
+ * c_out[n_k] [host] c128. */
+bem_status bem_pulse_coeffs(int32_t kind, const double* params, int32_t n_params, double dk,
+                            int32_t n_k, int32_t T, double z_shift, double* c_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BEM_H */

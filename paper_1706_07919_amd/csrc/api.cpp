@@ -1,0 +1,618 @@
+// C ABI of the library: argument validation, the per-chunk solve pipeline
+// (assembly -> float32 LU -> refinement with the float64 residual -> float64
+// fallback) and the field / synthesis entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+namespace bem {
+
+bem_status lu_perm(bem_ctx* ctx, int n, int batch, const int32_t* piv, int32_t* perm);
+bem_status lu_solve_perm(bem_ctx* ctx, bem_prec prec, int n, int64_t ld, int64_t stride,
+                         int batch, const void* LU, const int32_t* perm, int n_rhs,
+                         const void* Bin, void* X, int64_t bstride);
+
+bem_status fail(bem_ctx* ctx, bem_status st, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return st;
+}
+
+static hipEvent_t take_event(bem_ctx* ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+int prof_begin(bem_ctx* ctx, const char* kernel) {
+  if (!ctx->profiling) return -1;
+  KernelStat& k = ctx->stats[kernel];
+  hipEvent_t e = take_event(ctx);
+  if (!e) return -1;
+  (void)hipEventRecord(e, ctx->stream);
+  k.ev.push_back(e);
+  return (int)k.ev.size() - 1;
+}
+
+void prof_end(bem_ctx* ctx, const char* kernel, int idx, double flops, double bytes) {
+  if (idx < 0) return;
+  KernelStat& k = ctx->stats[kernel];
+  hipEvent_t e = take_event(ctx);
+  if (!e) return;
+  (void)hipEventRecord(e, ctx->stream);
+  k.ev.push_back(e);
+  k.ev_flops.push_back(flops);
+  k.ev_bytes.push_back(bytes);
+}
+
+static void resolve_stats(bem_ctx* ctx) {
+  for (auto& kv : ctx->stats) {
+    KernelStat& k = kv.second;
+    for (size_t i = 0; i + 1 < k.ev.size(); i += 2) {
+      float ms = 0.f;
+      (void)hipEventSynchronize(k.ev[i + 1]);
+      (void)hipEventElapsedTime(&ms, k.ev[i], k.ev[i + 1]);
+      k.ms += ms;
+      k.flops += k.ev_flops[i / 2];
+      k.bytes += k.ev_bytes[i / 2];
+      k.launches += 1;
+      ctx->event_pool.push_back(k.ev[i]);
+      ctx->event_pool.push_back(k.ev[i + 1]);
+    }
+    k.ev.clear();
+    k.ev_flops.clear();
+    k.ev_bytes.clear();
+  }
+}
+
+bem_status workspace(bem_ctx* ctx, size_t bytes, void** out) {
+  if (bytes <= ctx->ws_size) {
+    *out = ctx->ws;
+    return BEM_OK;
+  }
+  if (ctx->ws) {
+    BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    BEM_HIP_TRY(ctx, hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_size = 0;
+  }
+  if (hipMalloc(&ctx->ws, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->ws = nullptr;
+    return fail(ctx, BEM_ENOMEM, "device workspace of %zu bytes could not be allocated", bytes);
+  }
+  ctx->ws_size = bytes;
+  *out = ctx->ws;
+  return BEM_OK;
+}
+
+bem_status pinned(bem_ctx* ctx, size_t bytes, void** out) {
+  if (bytes > ctx->pinned_size) {
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    ctx->pinned = nullptr;
+    ctx->pinned_size = 0;
+    BEM_HIP_TRY(ctx, hipHostMalloc(&ctx->pinned, bytes, hipHostMallocDefault));
+    ctx->pinned_size = bytes;
+  }
+  *out = ctx->pinned;
+  return BEM_OK;
+}
+
+}  // namespace bem
+
+using namespace bem;
+
+namespace {
+
+bool surface_ok(bem_ctx* ctx, const bem_surface* s, bem_status* st) {
+  if (!s || s->n <= 0 || !s->x || !s->nrm || !s->w || !s->bc) {
+    *st = fail(ctx, BEM_EINVAL, "surface: n must be > 0 and x, nrm, w, bc non-NULL");
+    return false;
+  }
+  return true;
+}
+
+// Host-side checks of the surface data (normals unit, weights > 0, finite
+// coordinates, flags in {0,1}); copies n*7 doubles to the host.
+bem_status check_surface_values(bem_ctx* ctx, const bem_surface* s) {
+  const int n = s->n;
+  std::vector<double> x(3 * n), nr(3 * n), w(n);
+  std::vector<uint8_t> bc(n);
+  BEM_HIP_TRY(ctx, hipMemcpyAsync(x.data(), s->x, 24 * (size_t)n, hipMemcpyDeviceToHost, ctx->stream));
+  BEM_HIP_TRY(ctx, hipMemcpyAsync(nr.data(), s->nrm, 24 * (size_t)n, hipMemcpyDeviceToHost, ctx->stream));
+  BEM_HIP_TRY(ctx, hipMemcpyAsync(w.data(), s->w, 8 * (size_t)n, hipMemcpyDeviceToHost, ctx->stream));
+  BEM_HIP_TRY(ctx, hipMemcpyAsync(bc.data(), s->bc, (size_t)n, hipMemcpyDeviceToHost, ctx->stream));
+  BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  for (int i = 0; i < n; ++i) {
+    const double l = nr[3 * i] * nr[3 * i] + nr[3 * i + 1] * nr[3 * i + 1] + nr[3 * i + 2] * nr[3 * i + 2];
+    if (!(std::fabs(std::sqrt(l) - 1.0) <= 1e-12))
+      return fail(ctx, BEM_EINVAL, "surface: normal %d is not a unit vector", i);
+    if (!(w[i] > 0.0) || !std::isfinite(w[i]))
+      return fail(ctx, BEM_EINVAL, "surface: weight %d is not positive and finite", i);
+    if (!std::isfinite(x[3 * i]) || !std::isfinite(x[3 * i + 1]) || !std::isfinite(x[3 * i + 2]))
+      return fail(ctx, BEM_EINVAL, "surface: node %d has a non-finite coordinate", i);
+    if (bc[i] > 1) return fail(ctx, BEM_EINVAL, "surface: bc[%d] = %d not in {0,1}", i, bc[i]);
+  }
+  return BEM_OK;
+}
+
+bem_status check_k(bem_ctx* ctx, int n_k, const double* k) {
+  if (n_k <= 0 || !k) return fail(ctx, BEM_EINVAL, "n_k must be > 0 and k non-NULL");
+  std::vector<double> h(n_k);
+  BEM_HIP_TRY(ctx, hipMemcpyAsync(h.data(), k, 8 * (size_t)n_k, hipMemcpyDeviceToHost, ctx->stream));
+  BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  for (int i = 0; i < n_k; ++i)
+    if (!(h[i] > 0.0) || !std::isfinite(h[i]))
+      return fail(ctx, BEM_EINVAL, "k[%d] = %g must be positive and finite", i, h[i]);
+  return BEM_OK;
+}
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+struct Chunk {
+  // device buffers of one chunk of kc wavenumbers (n nodes, nr right-hand sides)
+  void* A;         // [kc][n][ld] c64 or c128
+  int32_t* piv;    // [kc][n]
+  int32_t* perm;   // [kc][n]
+  int32_t* info;   // [kc]
+  double2* diag;   // [kc][n][2]
+  double2* b;      // [kc][nr][n]
+  double2* x;      // [kc][nr][n]
+  double2* r;      // [kc][nr][n]
+  float2* r32;     // [kc][nr][n]
+  float2* d32;     // [kc][nr][n]
+  double* scale;   // [kc*nr]
+  double* dn2;     // [kc*nr]
+  double* xn2;     // [kc*nr]
+  uint8_t* active; // [kc*nr]
+};
+
+size_t chunk_bytes(int n, int64_t ld, int nr, int kc, bool c128) {
+  const size_t v = (size_t)kc * nr * n;
+  size_t s = 0;
+  auto add = [&](size_t bytes) { s += (bytes + 255) / 256 * 256; };
+  add((size_t)kc * n * ld * (c128 ? 16 : 8));
+  add((size_t)kc * n * 4);
+  add((size_t)kc * n * 4);
+  add((size_t)kc * 4);
+  add((size_t)kc * n * 32);
+  add(v * 16);
+  add(v * 16);
+  add(v * 16);
+  add(v * 8);
+  add(v * 8);
+  add((size_t)kc * nr * 8 * 3);
+  add((size_t)kc * nr);
+  return s;
+}
+
+Chunk carve(void* base, int n, int64_t ld, int nr, int kc, bool c128) {
+  char* p = (char*)base;
+  auto take = [&](size_t bytes) {
+    void* out = p;
+    p += (bytes + 255) / 256 * 256;
+    return out;
+  };
+  const size_t v = (size_t)kc * nr * n;
+  Chunk c;
+  c.A = take((size_t)kc * n * ld * (c128 ? 16 : 8));
+  c.piv = (int32_t*)take((size_t)kc * n * 4);
+  c.perm = (int32_t*)take((size_t)kc * n * 4);
+  c.info = (int32_t*)take((size_t)kc * 4);
+  c.diag = (double2*)take((size_t)kc * n * 32);
+  c.b = (double2*)take(v * 16);
+  c.x = (double2*)take(v * 16);
+  c.r = (double2*)take(v * 16);
+  c.r32 = (float2*)take(v * 8);
+  c.d32 = (float2*)take(v * 8);
+  c.scale = (double*)take((size_t)kc * nr * 8);
+  c.dn2 = (double*)take((size_t)kc * nr * 8);
+  c.xn2 = (double*)take((size_t)kc * nr * 8);
+  c.active = (uint8_t*)take((size_t)kc * nr);
+  return c;
+}
+
+}  // namespace
+
+// ============================================================ context
+extern "C" bem_status bem_ctx_create(int device, void* hip_stream, bem_ctx** out) {
+  if (!out) return BEM_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return BEM_EHIP;
+  if (hipSetDevice(device) != hipSuccess) return BEM_EHIP;
+  bem_ctx* c = new bem_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cus = prop.multiProcessorCount;
+  *out = c;
+  return BEM_OK;
+}
+
+extern "C" void bem_ctx_destroy(bem_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  else (void)hipDeviceSynchronize();
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  resolve_stats(ctx);
+  for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+extern "C" const char* bem_last_error(const bem_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+extern "C" bem_status bem_ctx_set_workspace_limit(bem_ctx* ctx, uint64_t bytes) {
+  if (!ctx) return BEM_EINVAL;
+  ctx->ws_limit = bytes;
+  return BEM_OK;
+}
+
+extern "C" bem_status bem_ctx_set_profiling(bem_ctx* ctx, int32_t on) {
+  if (!ctx) return BEM_EINVAL;
+  resolve_stats(ctx);
+  ctx->stats.clear();
+  ctx->profiling = on != 0;
+  return BEM_OK;
+}
+
+extern "C" bem_status bem_ctx_kernel_stats(bem_ctx* ctx, const char* kernel, double* flops,
+                                           double* bytes, double* ms, int64_t* launches) {
+  if (!ctx || !kernel) return BEM_EINVAL;
+  resolve_stats(ctx);
+  auto it = ctx->stats.find(kernel);
+  const KernelStat zero;
+  const KernelStat& k = it == ctx->stats.end() ? zero : it->second;
+  if (flops) *flops = k.flops;
+  if (bytes) *bytes = k.bytes;
+  if (ms) *ms = k.ms;
+  if (launches) *launches = k.launches;
+  return BEM_OK;
+}
+
+extern "C" void bem_solve_opts_default(bem_solve_opts* o) {
+  if (!o) return;
+  o->mode = BEM_FP32_IR_4M;
+  o->tol_step = 1e-8;
+  o->max_iter = 10;
+  o->fallback = 1;
+  o->use_graph = 0;
+  o->nb = 0;
+}
+
+// ============================================================ incident / assembly
+extern "C" bem_status bem_incident(bem_ctx* ctx, const bem_surface* s, int32_t n_k,
+                                   const double* k, const double dir[3], void* y) {
+  if (!ctx) return BEM_EINVAL;
+  bem_status st;
+  if (!surface_ok(ctx, s, &st)) return st;
+  if (!dir || !y || n_k <= 0 || !k) return fail(ctx, BEM_EINVAL, "bem_incident: NULL argument");
+  const double l = std::sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+  if (!(std::fabs(l - 1.0) < 1e-12)) return fail(ctx, BEM_EINVAL, "bem_incident: dir not unit");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
+  return launch_incident(ctx, s, n_k, k, dir[0], dir[1], dir[2], y);
+}
+
+extern "C" bem_status bem_assemble(bem_ctx* ctx, const bem_surface* s, int32_t n_k,
+                                   const double* k, int32_t n_rhs, const void* y, bem_prec prec,
+                                   void* A, int32_t ld, void* b, void* diag64) {
+  if (!ctx) return BEM_EINVAL;
+  bem_status st;
+  if (!surface_ok(ctx, s, &st)) return st;
+  if (n_k <= 0 || !k || n_rhs < 0 || (n_rhs > 0 && (!y || !b)) || !A || ld < s->n ||
+      (prec != BEM_C64 && prec != BEM_C128))
+    return fail(ctx, BEM_EINVAL, "bem_assemble: bad argument (n_k, k, n_rhs, y, b, A, ld, prec)");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
+  if ((st = check_surface_values(ctx, s)) != BEM_OK) return st;
+  if ((st = check_k(ctx, n_k, k)) != BEM_OK) return st;
+  return launch_assemble(ctx, s, n_k, k, n_rhs, y, prec, A, ld, (int64_t)s->n * ld, b, diag64);
+}
+
+extern "C" bem_status bem_residual(bem_ctx* ctx, const bem_surface* s, int32_t n_k,
+                                   const double* k, int32_t n_rhs, const void* y, const void* x,
+                                   const void* diag64, void* r) {
+  if (!ctx) return BEM_EINVAL;
+  bem_status st;
+  if (!surface_ok(ctx, s, &st)) return st;
+  if (n_k <= 0 || !k || n_rhs <= 0 || !y || !x || !diag64 || !r)
+    return fail(ctx, BEM_EINVAL, "bem_residual: bad argument");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
+  return launch_residual(ctx, s, n_k, k, n_rhs, y, x, diag64, r);
+}
+
+extern "C" bem_status bem_split_unknowns(bem_ctx* ctx, const bem_surface* s, int32_t n_k,
+                                         int32_t n_rhs, const void* x, const void* y, void* phi,
+                                         void* psi) {
+  if (!ctx) return BEM_EINVAL;
+  bem_status st;
+  if (!surface_ok(ctx, s, &st)) return st;
+  if (n_k <= 0 || n_rhs <= 0 || !x || !y || !phi || !psi)
+    return fail(ctx, BEM_EINVAL, "bem_split_unknowns: bad argument");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
+  return launch_split(ctx, s, n_k, n_rhs, x, y, phi, psi);
+}
+
+// ============================================================ LU building blocks
+extern "C" bem_status bem_getrf_batched(bem_ctx* ctx, bem_prec prec, int32_t n, int32_t ld,
+                                        int64_t stride, int32_t batch, void* A, int32_t* piv,
+                                        int32_t* info, int32_t nb, int32_t use_3m) {
+  if (!ctx) return BEM_EINVAL;
+  if (n <= 0 || ld < n || stride < (int64_t)n * ld || batch <= 0 || !A || !piv || !info ||
+      (prec != BEM_C64 && prec != BEM_C128) || nb < 0)
+    return fail(ctx, BEM_EINVAL, "bem_getrf_batched: bad argument");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
+  LuPlan plan;
+  plan.nb = nb > 0 ? nb : lu_default_nb(prec, n);
+  return lu_factor(ctx, prec, n, ld, stride, batch, A, piv, info, plan, use_3m);
+}
+
+extern "C" bem_status bem_getrs_batched(bem_ctx* ctx, bem_prec prec, int32_t n, int32_t ld,
+                                        int64_t stride, int32_t batch, const void* LU,
+                                        const int32_t* piv, int32_t n_rhs, const void* B,
+                                        void* X, int64_t bstride) {
+  if (!ctx) return BEM_EINVAL;
+  if (n <= 0 || ld < n || stride < (int64_t)n * ld || batch <= 0 || !LU || !piv || n_rhs <= 0 ||
+      !B || !X || B == X || bstride < (int64_t)n * n_rhs || (prec != BEM_C64 && prec != BEM_C128))
+    return fail(ctx, BEM_EINVAL, "bem_getrs_batched: bad argument");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
+  void* ws = nullptr;
+  bem_status st = workspace(ctx, sizeof(int32_t) * (size_t)n * batch, &ws);
+  if (st != BEM_OK) return st;
+  if ((st = lu_perm(ctx, n, batch, piv, (int32_t*)ws)) != BEM_OK) return st;
+  return lu_solve_perm(ctx, prec, n, ld, stride, batch, LU, (const int32_t*)ws, n_rhs, B, X,
+                       bstride);
+}
+
+// ============================================================ batched solve
+namespace {
+
+struct SolveRun {
+  bem_ctx* ctx;
+  const bem_problem* pr;
+  const bem_solve_opts* o;
+  double2* xout;
+  bem_solve_info* info;  // [n_k * n_rhs] for this problem, or NULL
+};
+
+// FP64 direct solve of the wavenumbers [k0, k0+kc) into xout.
+bem_status solve_fp64_chunk(SolveRun& R, const Chunk& c, int k0, int kc, int64_t ld, bool want_info) {
+  bem_ctx* ctx = R.ctx;
+  const bem_surface* s = R.pr->s;
+  const int n = s->n, nr = R.pr->n_rhs;
+  const double2* y = (const double2*)R.pr->y + (size_t)k0 * nr * n;
+  bem_status st;
+  if ((st = launch_assemble(ctx, s, kc, R.pr->k + k0, nr, y, BEM_C128, c.A, ld, (int64_t)n * ld,
+                            c.b, c.diag)) != BEM_OK)
+    return st;
+  LuPlan plan;
+  plan.nb = R.o->nb > 0 ? R.o->nb : lu_default_nb(BEM_C128, n);
+  if ((st = lu_factor(ctx, BEM_C128, n, ld, (int64_t)n * ld, kc, c.A, c.piv, c.info, plan, 0)) != BEM_OK)
+    return st;
+  if ((st = lu_perm(ctx, n, kc, c.piv, c.perm)) != BEM_OK) return st;
+  double2* xo = R.xout + (size_t)k0 * nr * n;
+  if ((st = lu_solve_perm(ctx, BEM_C128, n, ld, (int64_t)n * ld, kc, c.A, c.perm, nr, c.b, xo,
+                          (int64_t)nr * n)) != BEM_OK)
+    return st;
+  if (want_info) {
+    std::vector<int32_t> hinfo(kc);
+    if ((st = launch_residual(ctx, s, kc, R.pr->k + k0, nr, y, xo, c.diag, c.r)) != BEM_OK) return st;
+    if ((st = launch_norm2(ctx, kc * nr, n, c.r, c.dn2)) != BEM_OK) return st;
+    if ((st = launch_norm2(ctx, kc * nr, n, c.b, c.xn2)) != BEM_OK) return st;
+    std::vector<double> rn(kc * nr), bn(kc * nr);
+    BEM_HIP_TRY(ctx, hipMemcpyAsync(rn.data(), c.dn2, 8 * rn.size(), hipMemcpyDeviceToHost, ctx->stream));
+    BEM_HIP_TRY(ctx, hipMemcpyAsync(bn.data(), c.xn2, 8 * bn.size(), hipMemcpyDeviceToHost, ctx->stream));
+    BEM_HIP_TRY(ctx, hipMemcpyAsync(hinfo.data(), c.info, 4 * kc, hipMemcpyDeviceToHost, ctx->stream));
+    BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (R.info)
+      for (int v = 0; v < kc * nr; ++v) {
+        bem_solve_info& I = R.info[(size_t)k0 * nr + v];
+        I.iters = 0;
+        I.used_fp64 = 1;
+        I.singular = hinfo[v / nr] != 0;
+        I.rel_resid = bn[v] > 0 ? std::sqrt(rn[v] / bn[v]) : 0.0;
+        I.rel_step = 0.0;
+      }
+    for (int q = 0; q < kc; ++q)
+      if (hinfo[q] != 0) return fail(ctx, BEM_ESINGULAR, "zero pivot in the FP64 factorisation");
+  }
+  return BEM_OK;
+}
+
+bem_status solve_ir_chunk(SolveRun& R, const Chunk& c, int k0, int kc, int64_t ld,
+                          std::vector<int>& unconverged) {
+  bem_ctx* ctx = R.ctx;
+  const bem_surface* s = R.pr->s;
+  const int n = s->n, nr = R.pr->n_rhs;
+  const int nv = kc * nr;
+  const double2* y = (const double2*)R.pr->y + (size_t)k0 * nr * n;
+  const double* kk = R.pr->k + k0;
+  bem_status st;
+  if ((st = launch_assemble(ctx, s, kc, kk, nr, y, BEM_C64, c.A, ld, (int64_t)n * ld, c.b,
+                            c.diag)) != BEM_OK)
+    return st;
+  LuPlan plan;
+  plan.nb = R.o->nb > 0 ? R.o->nb : lu_default_nb(BEM_C64, n);
+  if ((st = lu_factor(ctx, BEM_C64, n, ld, (int64_t)n * ld, kc, c.A, c.piv, c.info, plan,
+                      R.o->mode == BEM_FP32_IR_3M)) != BEM_OK)
+    return st;
+  if ((st = lu_perm(ctx, n, kc, c.piv, c.perm)) != BEM_OK) return st;
+  if ((st = fill_zero(ctx, c.x, (size_t)nv * n * 16)) != BEM_OK) return st;
+  void* hp = nullptr;
+  if ((st = pinned(ctx, (size_t)nv * 16 + (size_t)kc * 4 + (size_t)nv, &hp)) != BEM_OK) return st;
+  double* h_dn = (double*)hp;
+  double* h_xn = h_dn + nv;
+  int32_t* h_info = (int32_t*)(h_xn + nv);
+  uint8_t* h_act = (uint8_t*)(h_info + kc);
+  std::vector<uint8_t> act(nv, 1);
+  std::vector<double> step(nv, 1.0);
+  std::vector<int> iters(nv, 0);
+  BEM_HIP_TRY(ctx, hipMemcpyAsync(h_info, c.info, 4 * kc, hipMemcpyDeviceToHost, ctx->stream));
+  const double2* rsrc = c.b;  // first sweep: r = b (x = 0)
+  int it = 0;
+  for (; it < std::max(1, R.o->max_iter); ++it) {
+    std::memcpy(h_act, act.data(), nv);
+    BEM_HIP_TRY(ctx, hipMemcpyAsync(c.active, h_act, nv, hipMemcpyHostToDevice, ctx->stream));
+    if ((st = launch_ir_scale(ctx, nv, n, rsrc, c.r32, c.scale)) != BEM_OK) return st;
+    if ((st = lu_solve_perm(ctx, BEM_C64, n, ld, (int64_t)n * ld, kc, c.A, c.perm, nr, c.r32,
+                            c.d32, (int64_t)nr * n)) != BEM_OK)
+      return st;
+    if ((st = launch_ir_update(ctx, nv, n, c.d32, c.scale, c.active, c.x, c.dn2, c.xn2)) != BEM_OK)
+      return st;
+    BEM_HIP_TRY(ctx, hipMemcpyAsync(h_dn, c.dn2, 8 * nv, hipMemcpyDeviceToHost, ctx->stream));
+    BEM_HIP_TRY(ctx, hipMemcpyAsync(h_xn, c.xn2, 8 * nv, hipMemcpyDeviceToHost, ctx->stream));
+    BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    int live = 0;
+    for (int v = 0; v < nv; ++v) {
+      if (!act[v]) continue;
+      iters[v] = it + 1;
+      const double sx = h_xn[v] > 0 ? std::sqrt(h_dn[v] / h_xn[v]) : (h_dn[v] > 0 ? 1.0 : 0.0);
+      step[v] = sx;
+      if (!(sx > R.o->tol_step) && std::isfinite(sx)) act[v] = 0;
+      else ++live;
+    }
+    if (live == 0) break;
+    if (it + 1 < std::max(1, R.o->max_iter)) {
+      if ((st = launch_residual(ctx, s, kc, kk, nr, y, c.x, c.diag, c.r)) != BEM_OK) return st;
+      rsrc = c.r;
+    }
+  }
+  // final residual of the float64 operator for the report
+  if ((st = launch_residual(ctx, s, kc, kk, nr, y, c.x, c.diag, c.r)) != BEM_OK) return st;
+  if ((st = launch_norm2(ctx, nv, n, c.r, c.dn2)) != BEM_OK) return st;
+  if ((st = launch_norm2(ctx, nv, n, c.b, c.xn2)) != BEM_OK) return st;
+  BEM_HIP_TRY(ctx, hipMemcpyAsync(h_dn, c.dn2, 8 * nv, hipMemcpyDeviceToHost, ctx->stream));
+  BEM_HIP_TRY(ctx, hipMemcpyAsync(h_xn, c.xn2, 8 * nv, hipMemcpyDeviceToHost, ctx->stream));
+  double2* xo = R.xout + (size_t)k0 * nr * n;
+  BEM_HIP_TRY(ctx, hipMemcpyAsync(xo, c.x, (size_t)nv * n * 16, hipMemcpyDeviceToDevice, ctx->stream));
+  BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  for (int v = 0; v < nv; ++v) {
+    const bool conv = !act[v] && h_info[v / nr] == 0;
+    if (!conv) unconverged.push_back(k0 + v / nr);
+    if (R.info) {
+      bem_solve_info& I = R.info[(size_t)k0 * nr + v];
+      I.iters = iters[v];
+      I.used_fp64 = 0;
+      I.singular = h_info[v / nr] != 0;
+      I.rel_resid = h_xn[v] > 0 ? std::sqrt(h_dn[v] / h_xn[v]) : 0.0;
+      I.rel_step = step[v];
+    }
+  }
+  std::sort(unconverged.begin(), unconverged.end());
+  unconverged.erase(std::unique(unconverged.begin(), unconverged.end()), unconverged.end());
+  return BEM_OK;
+}
+
+}  // namespace
+
+extern "C" bem_status bem_solve_batched(bem_ctx* ctx, const bem_problem* probs, int32_t n_probs,
+                                        const bem_solve_opts* opts, void* const* x_out,
+                                        bem_solve_info* info) {
+  if (!ctx) return BEM_EINVAL;
+  if (!probs || n_probs <= 0 || !x_out) return fail(ctx, BEM_EINVAL, "bem_solve_batched: NULL argument");
+  bem_solve_opts o;
+  bem_solve_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.mode < 0 || o.mode > 2 || o.max_iter < 0 || !(o.tol_step >= 0.0) || o.nb < 0)
+    return fail(ctx, BEM_EINVAL, "bem_solve_batched: bad options");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
+  bem_status st;
+  for (int p = 0; p < n_probs; ++p) {
+    const bem_problem& P = probs[p];
+    if (!surface_ok(ctx, P.s, &st)) return st;
+    if (P.n_rhs <= 0 || !P.y || !x_out[p]) return fail(ctx, BEM_EINVAL, "problem %d: n_rhs, y or x_out", p);
+    if ((st = check_k(ctx, P.n_k, P.k)) != BEM_OK) return st;
+    if ((st = check_surface_values(ctx, P.s)) != BEM_OK) return st;
+    if (P.s->n > 12288) return fail(ctx, BEM_EUNSUPPORTED, "problem %d: n = %d > 12288", p, P.s->n);
+  }
+  size_t free_b = 0, total_b = 0;
+  BEM_HIP_TRY(ctx, hipMemGetInfo(&free_b, &total_b));
+  size_t info_off = 0;
+  for (int p = 0; p < n_probs; ++p) {
+    const bem_problem& P = probs[p];
+    const int n = P.s->n, nr = P.n_rhs;
+    const int64_t ld = round_up(n, 16);
+    const bool fp64 = o.mode == BEM_FP64_DIRECT;
+    size_t limit = ctx->ws_limit ? ctx->ws_limit : (size_t)(0.75 * (double)(free_b + ctx->ws_size));
+    int kc = P.n_k;
+    while (kc > 1 && chunk_bytes(n, ld, nr, kc, fp64) > limit) kc = (kc + 1) / 2;
+    void* ws = nullptr;
+    const size_t need = std::max(chunk_bytes(n, ld, nr, kc, fp64), chunk_bytes(n, ld, nr, 1, true));
+    if ((st = workspace(ctx, need, &ws)) != BEM_OK) return st;
+    SolveRun R{ctx, &P, &o, (double2*)x_out[p], info ? info + info_off : nullptr};
+    for (int k0 = 0; k0 < P.n_k; k0 += kc) {
+      const int cur = std::min(kc, P.n_k - k0);
+      Chunk c = carve(ws, n, ld, nr, cur, fp64);
+      if (fp64) {
+        if ((st = solve_fp64_chunk(R, c, k0, cur, ld, true)) != BEM_OK) return st;
+        continue;
+      }
+      std::vector<int> bad;
+      if ((st = solve_ir_chunk(R, c, k0, cur, ld, bad)) != BEM_OK) return st;
+      if (!bad.empty()) {
+        if (!o.fallback)
+          return fail(ctx, BEM_ENOCONV, "problem %d: %zu wavenumbers did not converge", p, bad.size());
+        // FP64 direct re-solve of each unconverged wavenumber (a c128 chunk of one
+        // matrix fits where the c64 chunk of cur matrices did)
+        Chunk c1 = carve(ws, n, ld, nr, 1, true);
+        for (int kq : bad)
+          if ((st = solve_fp64_chunk(R, c1, kq, 1, ld, true)) != BEM_OK) return st;
+      }
+    }
+    info_off += (size_t)P.n_k * P.n_rhs;
+  }
+  BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return BEM_OK;
+}
+
+// ============================================================ field / synthesis
+extern "C" bem_status bem_field_eval(bem_ctx* ctx, const bem_surface* s, int32_t n_k,
+                                     const double* k, int32_t n_rhs, const void* phi,
+                                     const void* psi, int32_t m, const double* xp, int32_t* i0,
+                                     int32_t i0_given, uint8_t* inside, bem_prec prec, void* U) {
+  if (!ctx) return BEM_EINVAL;
+  bem_status st;
+  if (!surface_ok(ctx, s, &st)) return st;
+  if (n_k <= 0 || !k || n_rhs <= 0 || !phi || !psi || m < 0 || (m > 0 && (!xp || !i0 || !inside || !U)) ||
+      (prec != BEM_C64 && prec != BEM_C128))
+    return fail(ctx, BEM_EINVAL, "bem_field_eval: bad argument");
+  if (n_rhs > 65535 || (n_k + 7) / 8 > 65535) return fail(ctx, BEM_EINVAL, "bem_field_eval: n_k or n_rhs too large");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
+  if (m == 0) return BEM_OK;
+  if (!i0_given) {
+    if ((st = launch_closest(ctx, s, m, xp, i0, inside)) != BEM_OK) return st;
+  } else {
+    // closest nodes given: only the inside flags are recomputed from them
+    if ((st = launch_inside(ctx, s, m, xp, i0, inside)) != BEM_OK) return st;
+  }
+  return launch_field(ctx, s, n_k, k, n_rhs, phi, psi, m, xp, i0, inside, prec, U);
+}
+
+extern "C" bem_status pulse_synthesize(bem_ctx* ctx, int32_t m, int32_t n_k, const void* U,
+                                       int32_t n_pulse, const double* c, int32_t T,
+                                       int32_t add_incident, const double* xp, double dk,
+                                       float* p) {
+  if (!ctx) return BEM_EINVAL;
+  if (m < 0 || n_k <= 0 || n_pulse <= 0 || !c || (m > 0 && (!U || !p)) || (add_incident && !xp) ||
+      T < 64 || T > 8192 || (T & (T - 1)) != 0 || 2 * n_k > T || !(dk > 0.0) || !std::isfinite(dk))
+    return fail(ctx, BEM_EINVAL, "pulse_synthesize: bad argument");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
+  return launch_synth(ctx, m, n_k, U, n_pulse, c, T, add_incident, xp, dk, p);
+}

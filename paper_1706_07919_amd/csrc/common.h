@@ -1,0 +1,113 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/bem.h"
+
+// Per-kernel accounting filled when profiling is on: every launch of a
+// counted kernel is bracketed by two events on the context stream and carries
+// its algorithmic flop and byte counts.
+struct KernelStat {
+  double flops = 0.0, bytes = 0.0, ms = 0.0;
+  int64_t launches = 0;
+  std::vector<hipEvent_t> ev;       // pending (start, stop) pairs
+  std::vector<double> ev_flops, ev_bytes;
+};
+
+struct bem_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  uint64_t ws_limit = 0;
+  // cached device workspace (grown on demand, freed with the context)
+  void* ws = nullptr;
+  size_t ws_size = 0;
+  // small pinned host staging buffer for norms / flags
+  void* pinned = nullptr;
+  size_t pinned_size = 0;
+  // autotuned panel widths keyed by (precision, n-bucket)
+  std::map<std::pair<int, int>, int> tuned_nb;
+  int num_cus = 256;
+  bool profiling = false;
+  std::map<std::string, KernelStat> stats;
+  std::vector<hipEvent_t> event_pool;
+};
+
+namespace bem {
+
+bem_status fail(bem_ctx* ctx, bem_status st, const char* fmt, ...);
+
+#define BEM_HIP_TRY(ctx, call)                                                       \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return ::bem::fail((ctx), BEM_EHIP, "%s failed: %s (%s:%d)", #call,            \
+                         hipGetErrorString(e_), __FILE__, __LINE__);                 \
+  } while (0)
+
+#define BEM_CHECK_LAUNCH(ctx) BEM_HIP_TRY(ctx, hipGetLastError())
+
+// Profiling brackets: prof_begin returns an index (or -1 when off); prof_end
+// records the stop event with the launch's algorithmic work.
+int prof_begin(bem_ctx* ctx, const char* kernel);
+void prof_end(bem_ctx* ctx, const char* kernel, int idx, double flops, double bytes);
+
+// grow-only device workspace owned by the context
+bem_status workspace(bem_ctx* ctx, size_t bytes, void** out);
+bem_status pinned(bem_ctx* ctx, size_t bytes, void** out);
+
+// ------------------------------------------------------------------ operator
+bem_status launch_incident(bem_ctx*, const bem_surface*, int n_k, const double* k,
+                           double dx, double dy, double dz, void* y);
+bem_status launch_assemble(bem_ctx*, const bem_surface*, int n_k, const double* k, int n_rhs,
+                           const void* y, bem_prec prec, void* A, int64_t ld,
+                           int64_t a_stride, void* b, void* diag64);
+bem_status launch_residual(bem_ctx*, const bem_surface*, int n_k, const double* k, int n_rhs,
+                           const void* y, const void* x, const void* diag64, void* r);
+bem_status launch_split(bem_ctx*, const bem_surface*, int n_k, int n_rhs, const void* x,
+                        const void* y, void* phi, void* psi);
+
+// ------------------------------------------------------------------ dense LA
+// Batched LU with partial pivoting of row-major matrices A_b = A + b*stride
+// (n x n, leading dimension ld).  piv_b = piv + b*n (absolute row indices).
+// info_b = info + b: 0, or 1 + first zero pivot column.
+struct LuPlan {
+  int nb = 0;          // top-level panel width (0 = recursive halving)
+  int base = 8;        // width of the register-held base panel
+};
+bem_status lu_factor(bem_ctx*, bem_prec, int n, int64_t ld, int64_t stride, int batch, void* A,
+                     int32_t* piv, int32_t* info, const LuPlan& plan, int gemm_3m);
+// Solve A_b X = B_b in place for B_b = B + b*bstride (n_rhs vectors of length n, stride n).
+bem_status lu_solve(bem_ctx*, bem_prec, int n, int64_t ld, int64_t stride, int batch,
+                    const void* LU, const int32_t* piv, int n_rhs, void* B, int64_t bstride);
+int lu_default_nb(bem_prec prec, int n);
+
+// ------------------------------------------------------------------ iterative refinement
+bem_status launch_ir_scale(bem_ctx*, int nvec, int n, const void* r, void* r32, double* scale);
+bem_status launch_ir_update(bem_ctx*, int nvec, int n, const void* d32, const double* scale,
+                            const uint8_t* active, void* x, double* dnorm2, double* xnorm2);
+bem_status launch_norm2(bem_ctx*, int nvec, int n, const void* v, double* out);
+bem_status launch_c128_to_c64(bem_ctx*, int64_t count, const void* in, void* out);
+bem_status fill_zero(bem_ctx*, void* p, size_t bytes);
+bem_status launch_copy_active(bem_ctx*, int nvec, int n, const uint8_t* active, const void* src,
+                              void* dst);
+
+// ------------------------------------------------------------------ field / synthesis
+bem_status launch_closest(bem_ctx*, const bem_surface*, int m, const double* xp, int32_t* i0,
+                          uint8_t* inside);
+bem_status launch_inside(bem_ctx*, const bem_surface*, int m, const double* xp,
+                         const int32_t* i0, uint8_t* inside);
+bem_status launch_field(bem_ctx*, const bem_surface*, int n_k, const double* k, int n_rhs,
+                        const void* phi, const void* psi, int m, const double* xp,
+                        const int32_t* i0, const uint8_t* inside, bem_prec prec, void* U);
+bem_status launch_synth(bem_ctx*, int m, int n_k, const void* U, int n_pulse, const double* c,
+                        int T, int add_incident, const double* xp, double dk, float* p);
+
+}  // namespace bem

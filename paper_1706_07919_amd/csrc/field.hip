@@ -1,0 +1,276 @@
+// Surface-to-field evaluation by the non-singular representation (Sec. III,
+// Eq. BRIEFdmn; its S_inf integrals evaluated, which leaves 4 pi P(x0) as the
+// constant term when the integrals run over S only):
+//   4 pi P(x_p) = 4 pi phi_a + sum_{j!=a} w_j [u_j (H^p_j - H^a_j) - u'_j (G^p_j - G^a_j)]
+// with a the surface node closest to x_p, u_j = phi_j - phi_a g_aj - psi_a f_aj,
+// u'_j = psi_j - phi_a g'_aj - psi_a f'_aj (f, g of Appendix A about x_a).
+// The sum splits into S(x_p) - S(x_a) with
+//   S(x) = A1 - phi_a A2 - psi_a A3,
+//   A1 = sum w_j (phi_j H^x_j - psi_j G^x_j), A2 = sum w_j (g_aj H^x_j - g'_aj G^x_j),
+//   A3 = sum w_j (f_aj H^x_j - f'_aj G^x_j)   (j != a).
+// S(x_a) is computed once per node by the same kernel, so the per-point work
+// is one sweep over the nodes.  Float32 kernels take every phase k*r and k*s
+// in float64, reduce it to [-1/2, 1/2) revolutions, and evaluate the
+// trigonometric functions in float32 on the reduced argument.
+#include "common.h"
+
+namespace bem {
+namespace {
+
+constexpr double kInv2Pi = 0.15915494309189533576888376337251;
+constexpr double kFourPi = 12.566370614359172953850573533118;
+
+// --------------------------------------------------------------- closest node
+// i0[p] = argmin_j (dx*dx + dy*dy) + dz*dz, float64 without contraction,
+// ties to the lowest j; inside[p] = n_a.(x_p - x_a) < 0.
+constexpr int kCT = 256, kCChunk = 1024;
+
+__global__ __launch_bounds__(kCT) void closest_kernel(int n, const double* __restrict__ x,
+                                                      const double* __restrict__ nrm, int m,
+                                                      const double* __restrict__ xp,
+                                                      int32_t* __restrict__ i0,
+                                                      uint8_t* __restrict__ inside) {
+  __shared__ double sx[kCChunk], sy[kCChunk], sz[kCChunk];
+  const int p = blockIdx.x * kCT + threadIdx.x;
+  const bool valid = p < m;
+  const double px = valid ? xp[3 * p] : 0.0, py = valid ? xp[3 * p + 1] : 0.0,
+               pz = valid ? xp[3 * p + 2] : 0.0;
+  double best = __builtin_inf();
+  int bi = 0;
+  for (int j0 = 0; j0 < n; j0 += kCChunk) {
+    const int cnt = min(kCChunk, n - j0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < cnt; e += kCT) {
+      sx[e] = x[3 * (j0 + e)];
+      sy[e] = x[3 * (j0 + e) + 1];
+      sz[e] = x[3 * (j0 + e) + 2];
+    }
+    __syncthreads();
+    for (int e = 0; e < cnt; ++e) {
+      const double d0 = __dsub_rn(px, sx[e]);
+      const double d1 = __dsub_rn(py, sy[e]);
+      const double d2 = __dsub_rn(pz, sz[e]);
+      const double dist = __dadd_rn(__dadd_rn(__dmul_rn(d0, d0), __dmul_rn(d1, d1)), __dmul_rn(d2, d2));
+      if (dist < best) { best = dist; bi = j0 + e; }
+    }
+  }
+  if (!valid) return;
+  i0[p] = bi;
+  const double d0 = __dsub_rn(px, x[3 * bi]), d1 = __dsub_rn(py, x[3 * bi + 1]),
+               d2 = __dsub_rn(pz, x[3 * bi + 2]);
+  const double nd = __dadd_rn(__dadd_rn(__dmul_rn(nrm[3 * bi], d0), __dmul_rn(nrm[3 * bi + 1], d1)),
+                              __dmul_rn(nrm[3 * bi + 2], d2));
+  inside[p] = nd < 0.0 ? 1 : 0;
+}
+
+__global__ void inside_kernel(const double* __restrict__ x, const double* __restrict__ nrm, int m,
+                              const double* __restrict__ xp, const int32_t* __restrict__ i0,
+                              uint8_t* __restrict__ inside) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= m) return;
+  const int bi = i0[p];
+  const double d0 = __dsub_rn(xp[3 * p], x[3 * bi]), d1 = __dsub_rn(xp[3 * p + 1], x[3 * bi + 1]),
+               d2 = __dsub_rn(xp[3 * p + 2], x[3 * bi + 2]);
+  const double nd = __dadd_rn(__dadd_rn(__dmul_rn(nrm[3 * bi], d0), __dmul_rn(nrm[3 * bi + 1], d1)),
+                              __dmul_rn(nrm[3 * bi + 2], d2));
+  inside[p] = nd < 0.0 ? 1 : 0;
+}
+
+// --------------------------------------------------------------- field sums
+template <typename R> struct CX;
+template <> struct CX<float> { using T = float2; };
+template <> struct CX<double> { using T = double2; };
+
+template <typename R>
+__device__ inline void phase(double theta, R& s, R& c);
+template <>
+__device__ inline void phase<float>(double theta, float& s, float& c) {
+  double t = theta * kInv2Pi;
+  t -= rint(t);
+  const float tf = (float)t;
+  s = __builtin_amdgcn_sinf(tf);   // argument in revolutions
+  c = __builtin_amdgcn_cosf(tf);
+}
+template <>
+__device__ inline void phase<double>(double theta, double& s, double& c) {
+  sincos(theta, &s, &c);
+}
+
+constexpr int kFT = 256, kNJ = 64;
+
+// MODE 0: write S(x_p) for points = nodes (raw, [rhs][n_k][n]).
+// MODE 1: write P(x_p) = phi_a + (S(x_p) - S(x_a)) / (4 pi) into U[rhs][m][n_k].
+template <typename R, int FCH, int MODE>
+__global__ __launch_bounds__(kFT) void field_kernel(
+    int n, const double* __restrict__ x, const double* __restrict__ nrm,
+    const double* __restrict__ w, const double* __restrict__ kv, int n_k, int n_rhs,
+    const double2* __restrict__ phi, const double2* __restrict__ psi, int m,
+    const double* __restrict__ xp, const int32_t* __restrict__ i0,
+    const uint8_t* __restrict__ inside, typename CX<R>::T* __restrict__ Snode,
+    typename CX<R>::T* __restrict__ U) {
+  using C = typename CX<R>::T;
+  __shared__ double sx[kNJ][3];
+  __shared__ double sn[kNJ][3];
+  __shared__ R sw[kNJ];
+  __shared__ C sphi[FCH][kNJ];
+  __shared__ C spsi[FCH][kNJ];
+  const int p = blockIdx.x * kFT + threadIdx.x;
+  const int m0 = blockIdx.y * FCH;
+  const int rhs = blockIdx.z;
+  const int nf = min(FCH, n_k - m0);
+  const bool valid = p < m && (MODE == 0 || !inside[p]);
+  const int a = p < m ? (MODE == 0 ? p : i0[p]) : 0;
+  const double px = p < m ? xp[3 * p] : 0.0, py = p < m ? xp[3 * p + 1] : 0.0,
+               pz = p < m ? xp[3 * p + 2] : 0.0;
+  const double ax = x[3 * a], ay = x[3 * a + 1], az = x[3 * a + 2];
+  const double anx = nrm[3 * a], any = nrm[3 * a + 1], anz = nrm[3 * a + 2];
+  double kk[FCH];
+#pragma unroll
+  for (int f = 0; f < FCH; ++f) kk[f] = f < nf ? kv[m0 + f] : kv[m0];
+  C A1[FCH], A2[FCH], A3[FCH];
+#pragma unroll
+  for (int f = 0; f < FCH; ++f) {
+    A1[f].x = A1[f].y = R(0);
+    A2[f].x = A2[f].y = R(0);
+    A3[f].x = A3[f].y = R(0);
+  }
+  for (int j0 = 0; j0 < n; j0 += kNJ) {
+    const int cnt = min(kNJ, n - j0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < cnt * 3; e += kFT) {
+      sx[e / 3][e % 3] = x[3 * j0 + e];
+      sn[e / 3][e % 3] = nrm[3 * j0 + e];
+    }
+    for (int e = threadIdx.x; e < cnt; e += kFT) sw[e] = (R)w[j0 + e];
+    for (int e = threadIdx.x; e < FCH * kNJ; e += kFT) {
+      const int f = e / kNJ, jj = e % kNJ;
+      if (f < nf && jj < cnt) {
+        const int64_t o = ((int64_t)(m0 + f) * n_rhs + rhs) * n + j0 + jj;
+        const double2 u = phi[o], v = psi[o];
+        sphi[f][jj].x = (R)u.x; sphi[f][jj].y = (R)u.y;
+        spsi[f][jj].x = (R)v.x; spsi[f][jj].y = (R)v.y;
+      } else {
+        sphi[f][jj].x = sphi[f][jj].y = R(0);
+        spsi[f][jj].x = spsi[f][jj].y = R(0);
+      }
+    }
+    __syncthreads();
+    if (!valid) continue;
+    for (int jj = 0; jj < cnt; ++jj) {
+      if (j0 + jj == a) continue;
+      const double dx = sx[jj][0] - px, dy = sx[jj][1] - py, dz = sx[jj][2] - pz;
+      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      const double rinv = 1.0 / r;
+      const double dn = (dx * sn[jj][0] + dy * sn[jj][1] + dz * sn[jj][2]) * rinv * rinv;
+      const R wj = sw[jj];
+      const R wg = wj * (R)rinv;             // w/r
+      const R wh2 = -wj * (R)(dn * rinv);    // -w (d.n)/r^3
+      const R wh1 = wj * (R)dn;              // w (d.n)/r^2 (times k)
+      const double sa = anx * (sx[jj][0] - ax) + any * (sx[jj][1] - ay) + anz * (sx[jj][2] - az);
+      const R nn = (R)(anx * sn[jj][0] + any * sn[jj][1] + anz * sn[jj][2]);
+#pragma unroll
+      for (int f = 0; f < FCH; ++f) {
+        const R k = (R)kk[f];
+        R es, ec, ss, cs;
+        phase<R>(kk[f] * r, es, ec);
+        phase<R>(kk[f] * sa, ss, cs);
+        // wG = (w/r) E ; wH = E (-w dn/r^3 + i k w dn/r^2)
+        const R gr = wg * ec, gi = wg * es;
+        const R hb = k * wh1;
+        const R hr = ec * wh2 - es * hb, hi = ec * hb + es * wh2;
+        const C ph = sphi[f][jj], ps = spsi[f][jj];
+        A1[f].x += (ph.x * hr - ph.y * hi) - (ps.x * gr - ps.y * gi);
+        A1[f].y += (ph.x * hi + ph.y * hr) - (ps.x * gi + ps.y * gr);
+        const R g = cs, gp = -k * ss * nn;
+        const R fv = ss / k, fp = cs * nn;
+        A2[f].x += g * hr - gp * gr;
+        A2[f].y += g * hi - gp * gi;
+        A3[f].x += fv * hr - fp * gr;
+        A3[f].y += fv * hi - fp * gi;
+      }
+    }
+  }
+  if (p >= m) return;
+#pragma unroll
+  for (int f = 0; f < FCH; ++f) {
+    if (f >= nf) break;
+    const int64_t oa = ((int64_t)(m0 + f) * n_rhs + rhs) * n + a;
+    const double2 pa = phi[oa], qa = psi[oa];
+    const R par = (R)pa.x, pai = (R)pa.y, qar = (R)qa.x, qai = (R)qa.y;
+    C S;
+    S.x = A1[f].x - (par * A2[f].x - pai * A2[f].y) - (qar * A3[f].x - qai * A3[f].y);
+    S.y = A1[f].y - (par * A2[f].y + pai * A2[f].x) - (qar * A3[f].y + qai * A3[f].x);
+    if (MODE == 0) {
+      Snode[((int64_t)rhs * n_k + m0 + f) * n + a] = S;
+    } else {
+      C out;
+      if (!valid) {
+        out.x = out.y = R(0);
+      } else {
+        const C s0 = Snode[((int64_t)rhs * n_k + m0 + f) * n + a];
+        const R inv4pi = (R)(1.0 / kFourPi);
+        out.x = par + (S.x - s0.x) * inv4pi;
+        out.y = pai + (S.y - s0.y) * inv4pi;
+      }
+      U[((int64_t)rhs * m + p) * n_k + m0 + f] = out;
+    }
+  }
+}
+
+template <typename R, int FCH>
+bem_status field_go(bem_ctx* ctx, const bem_surface* s, int n_k, const double* k, int n_rhs,
+                    const void* phi, const void* psi, int m, const double* xp,
+                    const int32_t* i0, const uint8_t* inside, void* U) {
+  using C = typename CX<R>::T;
+  void* ws = nullptr;
+  const size_t need = sizeof(C) * (size_t)n_rhs * n_k * s->n;
+  bem_status st = workspace(ctx, need, &ws);
+  if (st != BEM_OK) return st;
+  C* Snode = (C*)ws;
+  const int fch = (n_k + FCH - 1) / FCH;
+  dim3 gnode((s->n + kFT - 1) / kFT, fch, n_rhs);
+  hipLaunchKernelGGL((field_kernel<R, FCH, 0>), gnode, dim3(kFT), 0, ctx->stream, s->n, s->x,
+                     s->nrm, s->w, k, n_k, n_rhs, (const double2*)phi, (const double2*)psi, s->n,
+                     s->x, (const int32_t*)nullptr, (const uint8_t*)nullptr, Snode, (C*)nullptr);
+  BEM_CHECK_LAUNCH(ctx);
+  dim3 gpts((m + kFT - 1) / kFT, fch, n_rhs);
+  const int pi = prof_begin(ctx, "field");
+  hipLaunchKernelGGL((field_kernel<R, FCH, 1>), gpts, dim3(kFT), 0, ctx->stream, s->n, s->x,
+                     s->nrm, s->w, k, n_k, n_rhs, (const double2*)phi, (const double2*)psi, m, xp,
+                     i0, inside, Snode, (C*)U);
+  // kernel terms: one per (point, frequency, node, rhs)
+  prof_end(ctx, "field", pi, (double)m * n_k * s->n * n_rhs, (double)sizeof(C) * m * n_k * n_rhs);
+  BEM_CHECK_LAUNCH(ctx);
+  return BEM_OK;
+}
+
+}  // namespace
+
+bem_status launch_closest(bem_ctx* ctx, const bem_surface* s, int m, const double* xp,
+                          int32_t* i0, uint8_t* inside) {
+  if (m <= 0) return BEM_OK;
+  hipLaunchKernelGGL(closest_kernel, dim3((m + kCT - 1) / kCT), dim3(kCT), 0, ctx->stream, s->n,
+                     s->x, s->nrm, m, xp, i0, inside);
+  BEM_CHECK_LAUNCH(ctx);
+  return BEM_OK;
+}
+
+bem_status launch_inside(bem_ctx* ctx, const bem_surface* s, int m, const double* xp,
+                         const int32_t* i0, uint8_t* inside) {
+  if (m <= 0) return BEM_OK;
+  hipLaunchKernelGGL(inside_kernel, dim3((m + 255) / 256), dim3(256), 0, ctx->stream, s->x, s->nrm,
+                     m, xp, i0, inside);
+  BEM_CHECK_LAUNCH(ctx);
+  return BEM_OK;
+}
+
+bem_status launch_field(bem_ctx* ctx, const bem_surface* s, int n_k, const double* k, int n_rhs,
+                        const void* phi, const void* psi, int m, const double* xp,
+                        const int32_t* i0, const uint8_t* inside, bem_prec prec, void* U) {
+  if (m <= 0) return BEM_OK;
+  if (prec == BEM_C128)
+    return field_go<double, 8>(ctx, s, n_k, k, n_rhs, phi, psi, m, xp, i0, inside, U);
+  return field_go<float, 8>(ctx, s, n_k, k, n_rhs, phi, psi, m, xp, i0, inside, U);
+}
+
+}  // namespace bem

@@ -1,0 +1,748 @@
+// Batched dense complex LU with partial pivoting and triangular solves for the
+// one-system-per-wavenumber direct solve of Sec. IV A ("a linear system ...
+// solved using a direct method").  Matrices are row-major (element (i,j) at
+// i*ld + j), so row interchanges touch contiguous memory.
+//
+// Factorisation = recursion over column ranges (left half, swaps, triangular
+// solve, trailing complex GEMM, right half); the leaves are panels of a few
+// columns held in registers by one workgroup per matrix.  The trailing updates
+// carry all O(n^3) work and run on MFMA: float32 complex products as real
+// products of the interleaved operands (4M) accumulated in float32, float64
+// complex products on the f64 MFMA.
+#include "common.h"
+
+namespace bem {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename R> struct Cx;
+template <> struct Cx<float> { using T = float2; };
+template <> struct Cx<double> { using T = double2; };
+
+template <typename C> __device__ inline C cmk(decltype(C::x) a, decltype(C::x) b) {
+  C c; c.x = a; c.y = b; return c;
+}
+template <typename C> __device__ inline C cmul(C a, C b) {
+  return cmk<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename C> __device__ inline C csub(C a, C b) { return cmk<C>(a.x - b.x, a.y - b.y); }
+template <typename C> __device__ inline C crecip(C a) {
+  // 1/a with scaling to avoid overflow (Smith's method)
+  using R = decltype(C::x);
+  if (fabs(a.x) >= fabs(a.y)) {
+    R t = a.y / a.x, d = a.x + a.y * t;
+    return cmk<C>(R(1) / d, -t / d);
+  } else {
+    R t = a.x / a.y, d = a.y + a.x * t;
+    return cmk<C>(t / d, R(-1) / d);
+  }
+}
+
+// ============================================================== base panel
+// Factor columns [c0, c0+w) of rows [c0, n) in place; w <= W.  Thread t owns
+// rows c0 + t + q*NT (q < RPT).  Pivot = max |re|+|im| (lowest row on ties).
+constexpr int kPanelThreads = 512;
+
+template <typename R, int W, int RPT>
+__global__ __launch_bounds__(kPanelThreads) void panel_kernel(int n, int64_t ld, int64_t stride,
+                                                              typename Cx<R>::T* A, int32_t* piv,
+                                                              int32_t* info, int c0, int w) {
+  using C = typename Cx<R>::T;
+  constexpr int NT = kPanelThreads;
+  __shared__ C pivrow[W];
+  __shared__ C toprow[W];
+  __shared__ R rv[NT / 64];
+  __shared__ int ri[NT / 64];
+  __shared__ int sel;
+  const int b = blockIdx.x;
+  C* Ab = A + (int64_t)b * stride;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wid = t >> 6;
+  C a[RPT][W];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = c0 + t + q * NT;
+#pragma unroll
+    for (int c = 0; c < W; ++c)
+      a[q][c] = (r < n && c < w) ? Ab[(int64_t)r * ld + c0 + c] : cmk<C>(R(0), R(0));
+  }
+  for (int c = 0; c < w; ++c) {
+    const int pr = c0 + c;
+    R best = R(-1);
+    int bidx = 0x7fffffff;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = c0 + t + q * NT;
+      C v = a[q][0];
+#pragma unroll
+      for (int cc = 1; cc < W; ++cc)
+        if (cc == c) v = a[q][cc];
+      const R m = fabs(v.x) + fabs(v.y);
+      if (r >= pr && r < n && m > best) { best = m; bidx = r; }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const R ob = __shfl_down(best, off, 64);
+      const int oi = __shfl_down(bidx, off, 64);
+      if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
+    }
+    if (lane == 0) { rv[wid] = best; ri[wid] = bidx; }
+    __syncthreads();
+    if (t == 0) {
+      R bb = rv[0];
+      int bi = ri[0];
+      for (int q = 1; q < NT / 64; ++q)
+        if (rv[q] > bb || (rv[q] == bb && ri[q] < bi)) { bb = rv[q]; bi = ri[q]; }
+      if (!(bb > R(0))) {  // exactly zero (or NaN) column: record, do not swap
+        if (info[b] == 0) info[b] = pr + 1;
+        bi = -1 - pr;
+      }
+      sel = bi;
+      piv[(int64_t)b * n + pr] = bi < 0 ? pr : bi;
+    }
+    __syncthreads();
+    const int s = sel;
+    const bool singular = s < 0;
+    const int p = singular ? pr : s;
+    // exchange rows pr and p through LDS
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = c0 + t + q * NT;
+      if (r == p)
+#pragma unroll
+        for (int cc = 0; cc < W; ++cc) pivrow[cc] = a[q][cc];
+      if (r == pr && p != pr)
+#pragma unroll
+        for (int cc = 0; cc < W; ++cc) toprow[cc] = a[q][cc];
+    }
+    __syncthreads();
+    if (p != pr) {
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int r = c0 + t + q * NT;
+        if (r == p)
+#pragma unroll
+          for (int cc = 0; cc < W; ++cc) a[q][cc] = toprow[cc];
+        if (r == pr)
+#pragma unroll
+          for (int cc = 0; cc < W; ++cc) a[q][cc] = pivrow[cc];
+      }
+    }
+    if (!singular) {
+      C u[W];
+#pragma unroll
+      for (int cc = 0; cc < W; ++cc) u[cc] = pivrow[cc];
+      C pv = u[0];
+#pragma unroll
+      for (int cc = 1; cc < W; ++cc)
+        if (cc == c) pv = u[cc];
+      const C inv = crecip(pv);
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int r = c0 + t + q * NT;
+        if (r > pr && r < n) {
+          C l = cmk<C>(R(0), R(0));
+#pragma unroll
+          for (int cc = 0; cc < W; ++cc)
+            if (cc == c) { l = cmul(a[q][cc], inv); a[q][cc] = l; }
+#pragma unroll
+          for (int cc = 0; cc < W; ++cc)
+            if (cc > c) a[q][cc] = csub(a[q][cc], cmul(l, u[cc]));
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = c0 + t + q * NT;
+    if (r < n)
+#pragma unroll
+      for (int c = 0; c < W; ++c)
+        if (c < w) Ab[(int64_t)r * ld + c0 + c] = a[q][c];
+  }
+}
+
+// ============================================================== row swaps
+template <typename C>
+__global__ void laswp_kernel(int n, int64_t ld, int64_t stride, C* A, const int32_t* piv, int r0,
+                             int r1, int col0, int ncol) {
+  const int col = col0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= col0 + ncol) return;
+  C* Ab = A + (int64_t)blockIdx.y * stride;
+  const int32_t* pb = piv + (int64_t)blockIdx.y * n;
+  for (int t = r0; t < r1; ++t) {
+    const int p = pb[t];
+    if (p != t) {
+      C u = Ab[(int64_t)t * ld + col], v = Ab[(int64_t)p * ld + col];
+      Ab[(int64_t)t * ld + col] = v;
+      Ab[(int64_t)p * ld + col] = u;
+    }
+  }
+}
+
+// ============================================================== small TRSM
+// X = L^{-1} B, L = unit lower triangle of rows/cols [r0, r0+m1) (m1 <= 32),
+// B = rows [r0, r0+m1) x cols [col0, col0+ncol); one column per thread.
+template <typename C>
+__global__ __launch_bounds__(256) void trsm_kernel(int64_t ld, int64_t stride, C* A, int r0,
+                                                   int m1, int col0, int ncol) {
+  __shared__ C L[32][33];
+  C* Ab = A + (int64_t)blockIdx.y * stride;
+  for (int e = threadIdx.x; e < m1 * m1; e += blockDim.x) {
+    const int i = e / m1, j = e % m1;
+    L[i][j] = Ab[(int64_t)(r0 + i) * ld + r0 + j];
+  }
+  __syncthreads();
+  const int col = col0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= col0 + ncol) return;
+  C x[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i)
+    if (i < m1) x[i] = Ab[(int64_t)(r0 + i) * ld + col];
+#pragma unroll
+  for (int i = 1; i < 32; ++i) {
+    if (i < m1) {
+      C s = x[i];
+#pragma unroll
+      for (int j = 0; j < 32; ++j)
+        if (j < i) s = csub(s, cmul(L[i][j], x[j]));
+      x[i] = s;
+    }
+  }
+#pragma unroll
+  for (int i = 1; i < 32; ++i)
+    if (i < m1) Ab[(int64_t)(r0 + i) * ld + col] = x[i];
+}
+
+// ============================================================== GEMM f32 (4M)
+// C[M x N] -= A[M x K] B[K x N] for complex float, each operand a row-major
+// block of the same matrix.  128 x 128 tile per workgroup of 4 waves (2 x 2),
+// each wave 64 x 64 as 2 x 2 MFMA 32x32x2 blocks with separate real and
+// imaginary accumulators.  With the interleaved A row viewed as a real row of
+// length 2K, Re C = A_real . [Re B; -Im B], Im C = A_real . [Im B; Re B].
+constexpr int G32_BM = 128, G32_BN = 128, G32_BK = 8;
+constexpr int G32_APAD = 8;
+
+__global__ __launch_bounds__(256) void gemm_c32_kernel(int M, int N, int K, int64_t ld,
+                                                       int64_t stride, const float2* Ag,
+                                                       const float2* Bg, float2* Cg,
+                                                       int tiles_n) {
+  __shared__ float As[2][G32_BK][2 * G32_BM + G32_APAD];
+  __shared__ float Bs1[2][G32_BK][2 * G32_BN];
+  __shared__ float Bs2[2][G32_BK][2 * G32_BN];
+  const int tile = blockIdx.x;
+  const int tm = tile / tiles_n, tn = tile % tiles_n;
+  const int m0 = tm * G32_BM, n0 = tn * G32_BN;
+  const int64_t boff = (int64_t)blockIdx.y * stride;
+  const float2* A = Ag + boff;
+  const float2* B = Bg + boff;
+  float2* C = Cg + boff;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  const int h = lane >> 5, l32 = lane & 31;
+
+  floatx16 acc_re[2][2], acc_im[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) { acc_re[i][j][v] = 0.f; acc_im[i][j][v] = 0.f; }
+
+  float2 ra[4], rb[4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int row = e >> 3, kk = e & 7;
+      const int gr = m0 + row, gk = k0 + kk;
+      ra[q] = (gr < M && gk < K) ? A[(int64_t)gr * ld + gk] : make_float2(0.f, 0.f);
+      const int brow = e >> 7, bcol = e & 127;
+      const int gbk = k0 + brow, gbc = n0 + bcol;
+      rb[q] = (gbk < K && gbc < N) ? B[(int64_t)gbk * ld + gbc] : make_float2(0.f, 0.f);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int row = e >> 3, kk = e & 7;
+      As[buf][kk][row] = ra[q].x;
+      As[buf][kk][G32_BM + row] = ra[q].y;
+      const int brow = e >> 7, bcol = e & 127;
+      Bs1[buf][brow][bcol] = rb[q].x;
+      Bs1[buf][brow][G32_BN + bcol] = -rb[q].y;
+      Bs2[buf][brow][bcol] = rb[q].y;
+      Bs2[buf][brow][G32_BN + bcol] = rb[q].x;
+    }
+  };
+
+  const int nk = (K + G32_BK - 1) / G32_BK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * G32_BK);
+#pragma unroll
+    for (int k = 0; k < G32_BK; ++k) {
+      float a[2], b1[2], b2[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[cur][k][h * G32_BM + wm * 64 + i * 32 + l32];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        b1[j] = Bs1[cur][k][h * G32_BN + wn * 64 + j * 32 + l32];
+        b2[j] = Bs2[cur][k][h * G32_BN + wn * 64 + j * 32 + l32];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b1[j], acc_re[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b2[j], acc_im[i][j], 0, 0, 0);
+        }
+    }
+    if (kt + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn * 64 + j * 32 + l32;
+      if (col >= N) continue;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        if (row < M) {
+          float2* p = C + (int64_t)row * ld + col;
+          float2 c = *p;
+          c.x -= acc_re[i][j][v];
+          c.y -= acc_im[i][j][v];
+          *p = c;
+        }
+      }
+    }
+}
+
+// ============================================================== GEMM f64
+// Same contraction in float64 on MFMA 16x16x4 f64: one MFMA covers two
+// complex k (four interleaved real k).  64 x 64 tile, 4 waves of 32 x 32.
+constexpr int G64_BM = 64, G64_BN = 64, G64_BK = 8;
+
+__global__ __launch_bounds__(256) void gemm_c64_kernel(int M, int N, int K, int64_t ld,
+                                                       int64_t stride, const double2* Ag,
+                                                       const double2* Bg, double2* Cg,
+                                                       int tiles_n) {
+  __shared__ double As[2][G64_BK][2 * G64_BM + 4];
+  __shared__ double Bs1[2][G64_BK][2 * G64_BN];
+  __shared__ double Bs2[2][G64_BK][2 * G64_BN];
+  const int tile = blockIdx.x;
+  const int tm = tile / tiles_n, tn = tile % tiles_n;
+  const int m0 = tm * G64_BM, n0 = tn * G64_BN;
+  const int64_t boff = (int64_t)blockIdx.y * stride;
+  const double2* A = Ag + boff;
+  const double2* B = Bg + boff;
+  double2* C = Cg + boff;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  const int l16 = lane & 15, kq = lane >> 4;   // kq: real k index 0..3
+  const int kc = kq >> 1, part = kq & 1;       // complex k offset, re/im
+
+  doublex4 acc_re[2][2], acc_im[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) { acc_re[i][j][v] = 0.0; acc_im[i][j][v] = 0.0; }
+
+  double2 ra[2], rb[2];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int e = tid + 256 * q;
+      const int row = e >> 3, kk = e & 7;
+      const int gr = m0 + row, gk = k0 + kk;
+      ra[q] = (gr < M && gk < K) ? A[(int64_t)gr * ld + gk] : make_double2(0.0, 0.0);
+      const int brow = e >> 6, bcol = e & 63;
+      const int gbk = k0 + brow, gbc = n0 + bcol;
+      rb[q] = (gbk < K && gbc < N) ? B[(int64_t)gbk * ld + gbc] : make_double2(0.0, 0.0);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int e = tid + 256 * q;
+      const int row = e >> 3, kk = e & 7;
+      As[buf][kk][row] = ra[q].x;
+      As[buf][kk][G64_BM + row] = ra[q].y;
+      const int brow = e >> 6, bcol = e & 63;
+      Bs1[buf][brow][bcol] = rb[q].x;
+      Bs1[buf][brow][G64_BN + bcol] = -rb[q].y;
+      Bs2[buf][brow][bcol] = rb[q].y;
+      Bs2[buf][brow][G64_BN + bcol] = rb[q].x;
+    }
+  };
+  const int nk = (K + G64_BK - 1) / G64_BK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * G64_BK);
+#pragma unroll
+    for (int k = 0; k < G64_BK; k += 2) {
+      double a[2], b1[2], b2[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[cur][k + kc][part * G64_BM + wm * 32 + i * 16 + l16];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        b1[j] = Bs1[cur][k + kc][part * G64_BN + wn * 32 + j * 16 + l16];
+        b2[j] = Bs2[cur][k + kc][part * G64_BN + wn * 32 + j * 16 + l16];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b1[j], acc_re[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b2[j], acc_im[i][j], 0, 0, 0);
+        }
+    }
+    if (kt + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn * 32 + j * 16 + l16;
+      if (col >= N) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        // f64 16x16x4 result layout: lane l, item v holds row l/16 + 4v, column l%16
+        const int row = m0 + wm * 32 + i * 16 + kq + 4 * v;
+        if (row < M) {
+          double2* p = C + (int64_t)row * ld + col;
+          double2 c = *p;
+          c.x -= acc_re[i][j][v];
+          c.y -= acc_im[i][j][v];
+          *p = c;
+        }
+      }
+    }
+}
+
+// ============================================================== pivots -> permutation
+// perm[i] = original row that ends in position i after the interchanges; the
+// sequential composition runs in LDS (one workgroup per matrix).
+__global__ void perm_kernel(int n, const int32_t* piv, int32_t* perm) {
+  extern __shared__ int32_t q[];
+  const int32_t* pb = piv + (int64_t)blockIdx.x * n;
+  int32_t* qb = perm + (int64_t)blockIdx.x * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) q[i] = i;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < n; ++i) {
+      const int p = pb[i];
+      if (p != i) { const int32_t t = q[i]; q[i] = q[p]; q[p] = t; }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) qb[i] = q[i];
+}
+
+__global__ void fill_i32_kernel(int64_t count, int32_t* p, int32_t v) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) p[t] = v;
+}
+
+// ============================================================== triangular solves
+// One workgroup per (matrix, right-hand side).  X = U^{-1} L^{-1} P B.  The
+// vector lives in global memory (cached); blocks of 64 rows: the off-diagonal
+// part is a coalesced row-major dot product per row, the 64 x 64 diagonal
+// block is solved by one wave with register broadcasts.
+constexpr int TS_B = 64;
+
+template <typename R>
+__global__ __launch_bounds__(256) void getrs_kernel(int n, int64_t ld, int64_t stride,
+                                                    const typename Cx<R>::T* LU,
+                                                    const int32_t* perm, int n_rhs,
+                                                    const typename Cx<R>::T* Bin,
+                                                    typename Cx<R>::T* X, int64_t bstride) {
+  using C = typename Cx<R>::T;
+  __shared__ C part[TS_B];
+  const int mat = blockIdx.x / n_rhs, rhs = blockIdx.x % n_rhs;
+  const C* Lb = LU + (int64_t)mat * stride;
+  const int32_t* pb = perm + (int64_t)mat * n;
+  const C* bin = Bin + (int64_t)mat * bstride + (int64_t)rhs * n;
+  C* x = X + (int64_t)mat * bstride + (int64_t)rhs * n;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int i = tid; i < n; i += blockDim.x) x[i] = bin[pb[i]];
+  __threadfence_block();
+  __syncthreads();
+  const int nb = (n + TS_B - 1) / TS_B;
+  // forward: unit lower
+  for (int I = 0; I < nb; ++I) {
+    const int i0 = I * TS_B, rows = min(TS_B, n - i0);
+    for (int rr = wid; rr < rows; rr += 4) {
+      const C* Li = Lb + (int64_t)(i0 + rr) * ld;
+      R sr = 0, si = 0;
+      for (int j = lane; j < i0; j += 64) {
+        const C l = Li[j], v = x[j];
+        sr += l.x * v.x - l.y * v.y;
+        si += l.x * v.y + l.y * v.x;
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        sr += __shfl_down(sr, off, 64);
+        si += __shfl_down(si, off, 64);
+      }
+      if (lane == 0) part[rr] = cmk<C>(sr, si);
+    }
+    __syncthreads();
+    if (wid == 0) {
+      C v = cmk<C>(R(0), R(0));
+      if (lane < rows) v = csub(x[i0 + lane], part[lane]);
+      for (int c = 0; c < rows; ++c) {
+        const R xr = __shfl(v.x, c, 64), xi = __shfl(v.y, c, 64);
+        if (lane > c && lane < rows) {
+          const C l = Lb[(int64_t)(i0 + lane) * ld + i0 + c];
+          v = csub(v, cmul(l, cmk<C>(xr, xi)));
+        }
+      }
+      if (lane < rows) x[i0 + lane] = v;
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  // backward: upper with diagonal
+  for (int I = nb - 1; I >= 0; --I) {
+    const int i0 = I * TS_B, rows = min(TS_B, n - i0);
+    const int jlo = i0 + rows;
+    for (int rr = wid; rr < rows; rr += 4) {
+      const C* Ui = Lb + (int64_t)(i0 + rr) * ld;
+      R sr = 0, si = 0;
+      for (int j = jlo + lane; j < n; j += 64) {
+        const C u = Ui[j], v = x[j];
+        sr += u.x * v.x - u.y * v.y;
+        si += u.x * v.y + u.y * v.x;
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        sr += __shfl_down(sr, off, 64);
+        si += __shfl_down(si, off, 64);
+      }
+      if (lane == 0) part[rr] = cmk<C>(sr, si);
+    }
+    __syncthreads();
+    if (wid == 0) {
+      C v = cmk<C>(R(0), R(0));
+      C dinv = cmk<C>(R(1), R(0));
+      if (lane < rows) {
+        v = csub(x[i0 + lane], part[lane]);
+        dinv = crecip(Lb[(int64_t)(i0 + lane) * ld + i0 + lane]);
+      }
+      for (int c = rows - 1; c >= 0; --c) {
+        if (lane == c) v = cmul(v, dinv);
+        const R xr = __shfl(v.x, c, 64), xi = __shfl(v.y, c, 64);
+        if (lane < c) {
+          const C u = Lb[(int64_t)(i0 + lane) * ld + i0 + c];
+          v = csub(v, cmul(u, cmk<C>(xr, xi)));
+        }
+      }
+      if (lane < rows) x[i0 + lane] = v;
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+}
+
+// ============================================================== host driver
+struct Fac {
+  bem_ctx* ctx;
+  bem_prec prec;
+  int n;
+  int64_t ld, stride;
+  int batch;
+  void* A;
+  int32_t* piv;
+  int32_t* info;
+  LuPlan plan;
+  int base;
+  bem_status st = BEM_OK;
+
+  size_t esz() const { return prec == BEM_C128 ? 16 : 8; }
+  char* at(int r, int c) const { return (char*)A + ((int64_t)r * ld + c) * esz(); }
+
+  template <typename R, int W, int RPT>
+  void panel_go(int c0, int w) {
+    using C = typename Cx<R>::T;
+    hipLaunchKernelGGL((panel_kernel<R, W, RPT>), dim3(batch), dim3(kPanelThreads), 0,
+                       ctx->stream, n, ld, stride, (C*)A, piv, info, c0, w);
+  }
+  template <typename R, int W>
+  void panel_w(int c0, int w) {
+    const int rows = n - c0;
+    const int rpt = (rows + kPanelThreads - 1) / kPanelThreads;
+    if (rpt <= 1) panel_go<R, W, 1>(c0, w);
+    else if (rpt <= 2) panel_go<R, W, 2>(c0, w);
+    else if (rpt <= 4) panel_go<R, W, 4>(c0, w);
+    else if (rpt <= 6) panel_go<R, W, 6>(c0, w);
+    else if (rpt <= 8) panel_go<R, W, 8>(c0, w);
+    else if (rpt <= 10) panel_go<R, W, 10>(c0, w);
+    else if (rpt <= 11) panel_go<R, W, 11>(c0, w);
+    else if (rpt <= 12) panel_go<R, W, 12>(c0, w);
+    else if (W <= 4 && sizeof(R) == 4) panel_go<R, (W <= 4 ? W : 4), 24>(c0, w);
+    else panel_go<R, (W <= 2 ? W : 2), 24>(c0, w);
+  }
+  void panel(int c0, int w) {
+    const int pi = prof_begin(ctx, "panel");
+    panel_launch(c0, w);
+    // a panel of w columns over m rows: ~ 8 m w^2 / 2 flops, m w elements read and written
+    const double m = n - c0;
+    prof_end(ctx, "panel", pi, 4.0 * m * w * w * batch, 2.0 * esz() * m * w * batch);
+  }
+  void panel_launch(int c0, int w) {
+    if (prec == BEM_C128) {
+      if (base >= 4) panel_w<double, 4>(c0, w);
+      else panel_w<double, 2>(c0, w);
+    } else {
+      if (base >= 8) panel_w<float, 8>(c0, w);
+      else panel_w<float, 4>(c0, w);
+    }
+  }
+  void laswp(int r0, int r1, int col0, int ncol) {
+    if (ncol <= 0 || r1 <= r0) return;
+    dim3 grid((ncol + 255) / 256, batch);
+    if (prec == BEM_C128)
+      hipLaunchKernelGGL(laswp_kernel<double2>, grid, dim3(256), 0, ctx->stream, n, ld, stride,
+                         (double2*)A, piv, r0, r1, col0, ncol);
+    else
+      hipLaunchKernelGGL(laswp_kernel<float2>, grid, dim3(256), 0, ctx->stream, n, ld, stride,
+                         (float2*)A, piv, r0, r1, col0, ncol);
+  }
+  void gemm(int M, int N, int K, int ra, int ca, int rb, int cb, int rc, int cc) {
+    if (M <= 0 || N <= 0 || K <= 0) return;
+    const char* kname = prec == BEM_C128 ? "gemm_c64" : "gemm_c32";
+    const int pi = prof_begin(ctx, kname);
+    gemm_launch(M, N, K, ra, ca, rb, cb, rc, cc);
+    prof_end(ctx, kname, pi, 8.0 * M * N * (double)K * batch,
+             (double)esz() * ((double)M * K + (double)K * N + 2.0 * M * N) * batch);
+  }
+  void gemm_launch(int M, int N, int K, int ra, int ca, int rb, int cb, int rc, int cc) {
+    if (prec == BEM_C128) {
+      const int tn = (N + G64_BN - 1) / G64_BN, tm = (M + G64_BM - 1) / G64_BM;
+      hipLaunchKernelGGL(gemm_c64_kernel, dim3(tm * tn, batch), dim3(256), 0, ctx->stream, M, N,
+                         K, ld, stride, (const double2*)at(ra, ca), (const double2*)at(rb, cb),
+                         (double2*)at(rc, cc), tn);
+    } else {
+      const int tn = (N + G32_BN - 1) / G32_BN, tm = (M + G32_BM - 1) / G32_BM;
+      hipLaunchKernelGGL(gemm_c32_kernel, dim3(tm * tn, batch), dim3(256), 0, ctx->stream, M, N,
+                         K, ld, stride, (const float2*)at(ra, ca), (const float2*)at(rb, cb),
+                         (float2*)at(rc, cc), tn);
+    }
+  }
+  // X = L^{-1} X for rows [r0, r0+m1) and columns [col0, col0+ncol)
+  void trsm(int r0, int m1, int col0, int ncol) {
+    if (ncol <= 0 || m1 <= 1) return;
+    if (m1 <= 32) {
+      dim3 grid((ncol + 255) / 256, batch);
+      if (prec == BEM_C128)
+        hipLaunchKernelGGL(trsm_kernel<double2>, grid, dim3(256), 0, ctx->stream, ld, stride,
+                           (double2*)A, r0, m1, col0, ncol);
+      else
+        hipLaunchKernelGGL(trsm_kernel<float2>, grid, dim3(256), 0, ctx->stream, ld, stride,
+                           (float2*)A, r0, m1, col0, ncol);
+      return;
+    }
+    int h1 = ((m1 / 2) + 31) / 32 * 32;
+    if (h1 >= m1) h1 = m1 - 32;
+    trsm(r0, h1, col0, ncol);
+    gemm(m1 - h1, ncol, h1, r0 + h1, r0, r0, col0, r0 + h1, col0);
+    trsm(r0 + h1, m1 - h1, col0, ncol);
+  }
+  int split(int w) const {
+    if (plan.nb > 0 && w > plan.nb) return plan.nb;
+    int h = (w / 2 + base - 1) / base * base;
+    if (h >= w) h = w - base;
+    return h;
+  }
+  void rec(int c0, int c1) {
+    const int w = c1 - c0;
+    if (w <= base) { panel(c0, w); return; }
+    const int h = split(w);
+    rec(c0, c0 + h);
+    laswp(c0, c0 + h, c0 + h, c1 - (c0 + h));
+    trsm(c0, h, c0 + h, c1 - (c0 + h));
+    gemm(n - (c0 + h), c1 - (c0 + h), h, c0 + h, c0, c0, c0 + h, c0 + h, c0 + h);
+    rec(c0 + h, c1);
+    laswp(c0 + h, c1, c0, h);
+  }
+};
+
+}  // namespace
+
+int lu_default_nb(bem_prec prec, int n) {
+  (void)prec;
+  return n >= 1024 ? 256 : 0;
+}
+
+bem_status lu_factor(bem_ctx* ctx, bem_prec prec, int n, int64_t ld, int64_t stride, int batch,
+                     void* A, int32_t* piv, int32_t* info, const LuPlan& plan, int gemm_3m) {
+  (void)gemm_3m;
+  if (batch <= 0 || n <= 0) return BEM_OK;
+  if (n > 24 * kPanelThreads)
+    return fail(ctx, BEM_EUNSUPPORTED, "lu_factor: n=%d above the supported %d", n,
+                24 * kPanelThreads);
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((batch + 255) / 256), dim3(256), 0, ctx->stream,
+                     (int64_t)batch, info, 0);
+  Fac f{ctx, prec, n, ld, stride, batch, A, piv, info, plan, 0};
+  const int rows_per_thread = (n + kPanelThreads - 1) / kPanelThreads;
+  if (prec == BEM_C128) f.base = rows_per_thread <= 10 ? 4 : 2;
+  else f.base = rows_per_thread <= 11 ? 8 : 4;
+  if (plan.base > 0 && plan.base < f.base) f.base = plan.base;
+  f.rec(0, n);
+  BEM_CHECK_LAUNCH(ctx);
+  return BEM_OK;
+}
+
+bem_status lu_perm(bem_ctx* ctx, int n, int batch, const int32_t* piv, int32_t* perm) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)perm_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        160 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(perm_kernel, dim3(batch), dim3(256), sizeof(int32_t) * n, ctx->stream, n,
+                     piv, perm);
+  BEM_CHECK_LAUNCH(ctx);
+  return BEM_OK;
+}
+
+bem_status lu_solve_perm(bem_ctx* ctx, bem_prec prec, int n, int64_t ld, int64_t stride,
+                         int batch, const void* LU, const int32_t* perm, int n_rhs,
+                         const void* Bin, void* X, int64_t bstride) {
+  if (batch <= 0 || n_rhs <= 0) return BEM_OK;
+  dim3 grid(batch * n_rhs);
+  const int pi = prof_begin(ctx, "getrs");
+  if (prec == BEM_C128)
+    hipLaunchKernelGGL(getrs_kernel<double>, grid, dim3(256), 0, ctx->stream, n, ld, stride,
+                       (const double2*)LU, perm, n_rhs, (const double2*)Bin, (double2*)X, bstride);
+  else
+    hipLaunchKernelGGL(getrs_kernel<float>, grid, dim3(256), 0, ctx->stream, n, ld, stride,
+                       (const float2*)LU, perm, n_rhs, (const float2*)Bin, (float2*)X, bstride);
+  const double esz = prec == BEM_C128 ? 16.0 : 8.0;
+  prof_end(ctx, "getrs", pi, 8.0 * (double)n * n * n_rhs * batch,
+           esz * ((double)n * n + 3.0 * n * n_rhs) * batch);
+  BEM_CHECK_LAUNCH(ctx);
+  return BEM_OK;
+}
+
+}  // namespace bem

@@ -1,0 +1,134 @@
+// Icosphere surface description (nodal discretisation of the scatterer
+// surfaces; Sec. IV A meshes the sphere with triangular elements and collocates
+// at the nodes).  Host code, compiled without floating-point contraction so
+// that every value is reproducible bit for bit: each expression is evaluated
+// in the written order with correctly rounded IEEE operations.
+#include <cmath>
+#include <cstdint>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/bem.h"
+
+namespace {
+
+struct V3 {
+  double x, y, z;
+};
+
+V3 unit(V3 v) {
+  double s = std::sqrt((v.x * v.x + v.y * v.y) + v.z * v.z);
+  return {v.x / s, v.y / s, v.z / s};
+}
+
+const double kPhi = (1.0 + std::sqrt(5.0)) / 2.0;
+
+void base_icosahedron(std::vector<V3>& v, std::vector<int32_t>& f) {
+  const double p = kPhi;
+  const V3 raw[12] = {{-1, p, 0}, {1, p, 0},  {-1, -p, 0}, {1, -p, 0}, {0, -1, p},  {0, 1, p},
+                      {0, -1, -p}, {0, 1, -p}, {p, 0, -1},  {p, 0, 1},  {-p, 0, -1}, {-p, 0, 1}};
+  static const int32_t tri[60] = {0, 11, 5, 0, 5,  1,  0, 1, 7, 0, 7,  10, 0, 10, 11,
+                                  1, 5,  9, 5, 11, 4,  11, 10, 2, 10, 7, 6, 7, 1,  8,
+                                  3, 9,  4, 3, 4,  2,  3, 2, 6, 3, 6,  8,  3, 8,  9,
+                                  4, 9,  5, 2, 4,  11, 6, 2, 10, 8, 6, 7, 9, 8,  1};
+  v.clear();
+  for (int i = 0; i < 12; ++i) v.push_back(unit(raw[i]));
+  f.assign(tri, tri + 60);
+}
+
+void subdivide(std::vector<V3>& v, std::vector<int32_t>& f) {
+  std::unordered_map<uint64_t, int32_t> cache;
+  cache.reserve(f.size());
+  std::vector<int32_t> nf;
+  nf.reserve(f.size() * 4);
+  auto mid = [&](int32_t a, int32_t b) -> int32_t {
+    uint64_t key = a < b ? ((uint64_t)a << 32) | (uint32_t)b : ((uint64_t)b << 32) | (uint32_t)a;
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    V3 pa = v[a], pb = v[b];
+    V3 m = {(pa.x + pb.x) * 0.5, (pa.y + pb.y) * 0.5, (pa.z + pb.z) * 0.5};
+    v.push_back(unit(m));
+    int32_t idx = (int32_t)v.size() - 1;
+    cache.emplace(key, idx);
+    return idx;
+  };
+  for (size_t t = 0; t < f.size(); t += 3) {
+    int32_t a = f[t], b = f[t + 1], c = f[t + 2];
+    int32_t ab = mid(a, b);
+    int32_t bc = mid(b, c);
+    int32_t ca = mid(c, a);
+    const int32_t kids[12] = {a, ab, ca, b, bc, ab, c, ca, bc, ab, bc, ca};
+    nf.insert(nf.end(), kids, kids + 12);
+  }
+  f.swap(nf);
+}
+
+double spheroid_area(double radius, double aspect) {
+  if (aspect == 1.0) return 4.0 * M_PI * radius * radius;
+  double a = radius;
+  double c = radius * aspect;
+  double e = std::sqrt(1.0 - (a * a) / (c * c));
+  return 2.0 * M_PI * a * a * (1.0 + (c / (a * e)) * std::asin(e));
+}
+
+}  // namespace
+
+extern "C" bem_status bem_mesh_counts(int32_t level, int32_t* nv, int32_t* nf) {
+  if (level < 0 || level > 7 || !nv || !nf) return BEM_EINVAL;
+  int64_t p = 1;
+  for (int i = 0; i < level; ++i) p *= 4;
+  *nv = (int32_t)(10 * p + 2);
+  *nf = (int32_t)(20 * p);
+  return BEM_OK;
+}
+
+extern "C" bem_status bem_mesh_icosphere(int32_t level, double radius, double aspect,
+                                         const double center[3], int32_t rescale_area, double* x,
+                                         double* nrm, double* w, int32_t* faces) {
+  if (level < 0 || level > 7 || !(radius > 0.0) || !(aspect >= 1.0) || !std::isfinite(radius) ||
+      !std::isfinite(aspect) || !center || !x || !nrm || !w)
+    return BEM_EINVAL;
+  std::vector<V3> u;
+  std::vector<int32_t> f;
+  base_icosahedron(u, f);
+  for (int l = 0; l < level; ++l) subdivide(u, f);
+  const size_t V = u.size();
+  const double cx = center[0], cy = center[1], cz = center[2];
+  const double sx = radius;
+  const double sz = radius * aspect;
+  for (size_t i = 0; i < V; ++i) {
+    x[3 * i + 0] = cx + sx * u[i].x;
+    x[3 * i + 1] = cy + sx * u[i].y;
+    x[3 * i + 2] = cz + sz * u[i].z;
+    V3 g = {u[i].x / sx, u[i].y / sx, u[i].z / sz};
+    V3 n = unit(g);
+    nrm[3 * i + 0] = n.x;
+    nrm[3 * i + 1] = n.y;
+    nrm[3 * i + 2] = n.z;
+    w[i] = 0.0;
+  }
+  double total = 0.0;
+  for (size_t t = 0; t < f.size(); t += 3) {
+    const double* pa = x + 3 * f[t];
+    const double* pb = x + 3 * f[t + 1];
+    const double* pc = x + 3 * f[t + 2];
+    double e1x = pb[0] - pa[0], e1y = pb[1] - pa[1], e1z = pb[2] - pa[2];
+    double e2x = pc[0] - pa[0], e2y = pc[1] - pa[1], e2z = pc[2] - pa[2];
+    double c0 = e1y * e2z - e1z * e2y;
+    double c1 = e1z * e2x - e1x * e2z;
+    double c2 = e1x * e2y - e1y * e2x;
+    double area = 0.5 * std::sqrt((c0 * c0 + c1 * c1) + c2 * c2);
+    total = total + area;
+    double third = area / 3.0;
+    w[f[t]] = w[f[t]] + third;
+    w[f[t + 1]] = w[f[t + 1]] + third;
+    w[f[t + 2]] = w[f[t + 2]] + third;
+  }
+  if (rescale_area) {
+    double factor = spheroid_area(radius, aspect) / total;
+    for (size_t i = 0; i < V; ++i) w[i] = w[i] * factor;
+  }
+  if (faces)
+    for (size_t t = 0; t < f.size(); ++t) faces[t] = f[t];
+  return BEM_OK;
+}
