@@ -121,7 +121,8 @@ bem_status bem_incident(bem_ctx* ctx, const bem_surface* s, int32_t n_k, const d
  *                          c128 per `prec`; ld >= n
  *   b[n_k][n_rhs][n]       [dev] c128
  *   diag64[n_k][n][2]      [dev] c128 (M_phi)_ii, (M_psi)_ii, or NULL
- * Every pair term is evaluated in float64; A is rounded to `prec` on store. */
+ * Every pair term is evaluated in float64; A is rounded to `prec` on store.
+ * A may be NULL (ld ignored): then only diag64 and b are produced. */
 bem_status bem_assemble(bem_ctx* ctx, const bem_surface* s, int32_t n_k, const double* k,
                         int32_t n_rhs, const void* y, bem_prec prec, void* A, int32_t ld,
                         void* b, void* diag64);
@@ -132,6 +133,13 @@ bem_status bem_assemble(bem_ctx* ctx, const bem_surface* s, int32_t n_k, const d
 bem_status bem_residual(bem_ctx* ctx, const bem_surface* s, int32_t n_k, const double* k,
                         int32_t n_rhs, const void* y, const void* x, const void* diag64,
                         void* r);
+
+/* Relative residual of given unknowns: rel[q] = ||b - A x||_2 / ||b||_2 per
+ * (wavenumber, rhs) with the float64 operator (the acceptance test of
+ * predicted solutions).  x, y [dev] c128 [n_k][n_rhs][n]; rel [host]
+ * double[n_k*n_rhs].  Synchronises the stream. */
+bem_status bem_residual_check(bem_ctx* ctx, const bem_surface* s, int32_t n_k, const double* k,
+                              int32_t n_rhs, const void* y, const void* x, double* rel);
 
 /* ---------------------------------------------------------------- solve
  * One linear system per wavenumber (Sec. IV A: direct solve).  Modes:
@@ -165,7 +173,7 @@ typedef struct {
   int32_t iters;          /* refinement sweeps done (0 for FP64_DIRECT) */
   int32_t used_fp64;      /* 1 if the FP64 fallback produced the result */
   int32_t singular;       /* 1 if a zero pivot was met */
-  int32_t pad;
+  int32_t converged;      /* 1 if the step tolerance was reached (or FP64 direct) */
   double rel_resid;       /* ||b - A x||_2 / ||b||_2, float64 operator */
   double rel_step;        /* last ||dx||_2/||x||_2 */
 } bem_solve_info;
@@ -199,6 +207,22 @@ bem_status bem_getrf_batched(bem_ctx* ctx, bem_prec prec, int32_t n, int32_t ld,
 bem_status bem_getrs_batched(bem_ctx* ctx, bem_prec prec, int32_t n, int32_t ld, int64_t stride,
                              int32_t batch, const void* LU, const int32_t* piv, int32_t n_rhs,
                              const void* B, void* X, int64_t bstride);
+
+/* Iterative refinement of given unknowns with stored float32 factors of
+ * other (nearby) wavenumbers: x <- x + LU_f^{-1} (b - A(k) x), residual in
+ * float64 with the exact operator of each k, until ||dx||/||x|| <= tol_step or
+ * max_iter sweeps (converged = 0 in info then).  Used to re-use the factors of
+ * neighbouring frequencies (Sec. V: the solution matrix can be stored) for a
+ * dense frequency grid, starting from a predicted solution.
+ *   LU [dev] c64 factors from bem_getrf_batched, n_fac sets of [n][ld] with
+ *   stride; piv [dev] [n_fac][n]; fac_index [dev] int32[n_k] factor set used
+ *   for each wavenumber; x [dev] c128 [n_k][n_rhs][n] initial guess, refined
+ *   in place; info [host] [n_k*n_rhs] or NULL.  Synchronises the stream. */
+bem_status bem_refine_batched(bem_ctx* ctx, const bem_surface* s, int32_t n_k, const double* k,
+                              int32_t n_rhs, const void* y, const void* LU, int32_t ld,
+                              int64_t stride, const int32_t* piv, int32_t n_fac,
+                              const int32_t* fac_index, double tol_step, int32_t max_iter,
+                              void* x, bem_solve_info* info);
 
 /* phi = (hard ? x : y), psi = (hard ? y : x): full surface data from the
  * unknowns and the known data; all [dev] c128 [n_k][n_rhs][n]. */
@@ -248,6 +272,40 @@ bem_status pulse_synthesize(bem_ctx* ctx, int32_t m, int32_t n_k, const void* U,
  * c_out[n_k] [host] c128. */
 bem_status bem_pulse_coeffs(int32_t kind, const double* params, int32_t n_params, double dk,
                             int32_t n_k, int32_t T, double z_shift, double* c_out);
+
+/* ---------------------------------------------------------------- surrogate
+ * A small network mapping a wavenumber to the surface unknowns of a fixed
+ * geometry (not part of the paper; its predictions are only used after
+ * bem_residual_check accepts them, else the direct solve is used).
+ * All arrays [dev] float32 row-major unless stated; W is [in][out].
+ * bem_mlp_features: x[B][2 n_oct] = sin / cos(2^l pi k_b / kscale), l < n_oct
+ *   (k [dev] float64[B]).
+ * bem_mlp_dense_fwd: y = act(x W + b) for x[B][in]; act 0 identity, 1 SiLU
+ *   (then z[B][out] receives the pre-activation x W + b).
+ * bem_mlp_dense_bwd: given dy[B][out]: dW = x^T dz, db = column sums of dz,
+ *   dx = dz W^T (dx may be NULL), dz = dy * silu'(z) (act 1; dz is caller
+ *   scratch [B][out]) or dy (act 0).
+ * bem_mlp_mse_grad: dy = 2 (y - t) / count and loss_partial[n_partial] [dev]
+ *   float64 partial sums of (y - t)^2 over `count` elements.
+ * bem_mlp_adam: one Adam step (Kingma & Ba 2015, Algorithm 1) on n params.
+ * bem_mlp_pack: t[B][2n] = (Re x, Im x) / scale_j from c128 x[B][n]; with
+ *   compute_scale the per-node RMS of |x| over the batch is first stored in
+ *   scale[n] [dev] float64.  bem_mlp_unpack is the inverse. */
+bem_status bem_mlp_features(bem_ctx* ctx, int32_t B, const double* k, int32_t n_oct,
+                            double kscale, float* x);
+bem_status bem_mlp_dense_fwd(bem_ctx* ctx, int32_t B, int32_t in, int32_t out, const float* x,
+                             const float* W, const float* b, int32_t act, float* z, float* y);
+bem_status bem_mlp_dense_bwd(bem_ctx* ctx, int32_t B, int32_t in, int32_t out, const float* x,
+                             const float* W, const float* z, int32_t act, const float* dy,
+                             float* dW, float* db, float* dx, float* dz);
+bem_status bem_mlp_mse_grad(bem_ctx* ctx, int64_t count, const float* y, const float* t,
+                            float* dy, double* loss_partial, int32_t n_partial);
+bem_status bem_mlp_adam(bem_ctx* ctx, int64_t n, float* p, const float* g, float* m, float* v,
+                        int32_t step, float lr, float b1, float b2, float eps);
+bem_status bem_mlp_pack(bem_ctx* ctx, int32_t B, int32_t n, const void* x, double* scale,
+                        int32_t compute_scale, float* t);
+bem_status bem_mlp_unpack(bem_ctx* ctx, int32_t B, int32_t n, const float* t,
+                          const double* scale, void* x);
 
 #ifdef __cplusplus
 }

@@ -16,7 +16,7 @@ namespace bem {
 bem_status lu_perm(bem_ctx* ctx, int n, int batch, const int32_t* piv, int32_t* perm);
 bem_status lu_solve_perm(bem_ctx* ctx, bem_prec prec, int n, int64_t ld, int64_t stride,
                          int batch, const void* LU, const int32_t* perm, int n_rhs,
-                         const void* Bin, void* X, int64_t bstride);
+                         const void* Bin, void* X, int64_t bstride, const int32_t* fac_index = nullptr);
 
 bem_status fail(bem_ctx* ctx, bem_status st, const char* fmt, ...) {
   if (ctx) {
@@ -317,7 +317,8 @@ extern "C" bem_status bem_assemble(bem_ctx* ctx, const bem_surface* s, int32_t n
   if (!ctx) return BEM_EINVAL;
   bem_status st;
   if (!surface_ok(ctx, s, &st)) return st;
-  if (n_k <= 0 || !k || n_rhs < 0 || (n_rhs > 0 && (!y || !b)) || !A || ld < s->n ||
+  if (n_k <= 0 || !k || n_rhs < 0 || (n_rhs > 0 && (!y || !b)) || (A && ld < s->n) ||
+      (!A && !diag64 && n_rhs == 0) ||
       (prec != BEM_C64 && prec != BEM_C128))
     return fail(ctx, BEM_EINVAL, "bem_assemble: bad argument (n_k, k, n_rhs, y, b, A, ld, prec)");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
@@ -336,6 +337,46 @@ extern "C" bem_status bem_residual(bem_ctx* ctx, const bem_surface* s, int32_t n
     return fail(ctx, BEM_EINVAL, "bem_residual: bad argument");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
   return launch_residual(ctx, s, n_k, k, n_rhs, y, x, diag64, r);
+}
+
+extern "C" bem_status bem_residual_check(bem_ctx* ctx, const bem_surface* s, int32_t n_k,
+                                         const double* k, int32_t n_rhs, const void* y,
+                                         const void* x, double* rel) {
+  if (!ctx) return BEM_EINVAL;
+  bem_status st;
+  if (!surface_ok(ctx, s, &st)) return st;
+  if (n_k <= 0 || !k || n_rhs <= 0 || !y || !x || !rel)
+    return fail(ctx, BEM_EINVAL, "bem_residual_check: bad argument");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
+  const int n = s->n;
+  const int kc = std::min(n_k, 1024);
+  const size_t v = (size_t)kc * n_rhs * n;
+  const size_t need = (size_t)kc * n * 32 + 2 * v * 16 + (size_t)kc * n_rhs * 16 + 1024;
+  void* ws = nullptr;
+  if ((st = workspace(ctx, need, &ws)) != BEM_OK) return st;
+  char* p = (char*)ws;
+  double2* diag = (double2*)p; p += (size_t)kc * n * 32;
+  double2* b = (double2*)p; p += v * 16;
+  double2* r = (double2*)p; p += v * 16;
+  double* rn = (double*)p; p += (size_t)kc * n_rhs * 8;
+  double* bn = (double*)p;
+  std::vector<double> hr(kc * n_rhs), hb(kc * n_rhs);
+  for (int k0 = 0; k0 < n_k; k0 += kc) {
+    const int cur = std::min(kc, n_k - k0);
+    const double2* yk = (const double2*)y + (size_t)k0 * n_rhs * n;
+    const double2* xk = (const double2*)x + (size_t)k0 * n_rhs * n;
+    if ((st = launch_assemble(ctx, s, cur, k + k0, n_rhs, yk, BEM_C128, nullptr, n, 0, b, diag)) != BEM_OK)
+      return st;
+    if ((st = launch_residual(ctx, s, cur, k + k0, n_rhs, yk, xk, diag, r)) != BEM_OK) return st;
+    if ((st = launch_norm2(ctx, cur * n_rhs, n, r, rn)) != BEM_OK) return st;
+    if ((st = launch_norm2(ctx, cur * n_rhs, n, b, bn)) != BEM_OK) return st;
+    BEM_HIP_TRY(ctx, hipMemcpyAsync(hr.data(), rn, 8 * (size_t)cur * n_rhs, hipMemcpyDeviceToHost, ctx->stream));
+    BEM_HIP_TRY(ctx, hipMemcpyAsync(hb.data(), bn, 8 * (size_t)cur * n_rhs, hipMemcpyDeviceToHost, ctx->stream));
+    BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (int q = 0; q < cur * n_rhs; ++q)
+      rel[(size_t)k0 * n_rhs + q] = hb[q] > 0 ? std::sqrt(hr[q] / hb[q]) : std::sqrt(hr[q]);
+  }
+  return BEM_OK;
 }
 
 extern "C" bem_status bem_split_unknowns(bem_ctx* ctx, const bem_surface* s, int32_t n_k,
@@ -427,6 +468,7 @@ bem_status solve_fp64_chunk(SolveRun& R, const Chunk& c, int k0, int kc, int64_t
         I.iters = 0;
         I.used_fp64 = 1;
         I.singular = hinfo[v / nr] != 0;
+        I.converged = hinfo[v / nr] == 0;
         I.rel_resid = bn[v] > 0 ? std::sqrt(rn[v] / bn[v]) : 0.0;
         I.rel_step = 0.0;
       }
@@ -511,6 +553,7 @@ bem_status solve_ir_chunk(SolveRun& R, const Chunk& c, int k0, int kc, int64_t l
       I.iters = iters[v];
       I.used_fp64 = 0;
       I.singular = h_info[v / nr] != 0;
+      I.converged = conv ? 1 : 0;
       I.rel_resid = h_xn[v] > 0 ? std::sqrt(h_dn[v] / h_xn[v]) : 0.0;
       I.rel_step = step[v];
     }
@@ -577,6 +620,113 @@ extern "C" bem_status bem_solve_batched(bem_ctx* ctx, const bem_problem* probs, 
       }
     }
     info_off += (size_t)P.n_k * P.n_rhs;
+  }
+  BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return BEM_OK;
+}
+
+// ============================================================ refinement with given factors
+extern "C" bem_status bem_refine_batched(bem_ctx* ctx, const bem_surface* s, int32_t n_k,
+                                         const double* k, int32_t n_rhs, const void* y,
+                                         const void* LU, int32_t ld, int64_t stride,
+                                         const int32_t* piv, int32_t n_fac,
+                                         const int32_t* fac_index, double tol_step,
+                                         int32_t max_iter, void* x, bem_solve_info* info) {
+  if (!ctx) return BEM_EINVAL;
+  bem_status st;
+  if (!surface_ok(ctx, s, &st)) return st;
+  const int n = s->n;
+  if (n_k <= 0 || !k || n_rhs <= 0 || !y || !LU || ld < n || stride < (int64_t)n * ld || !piv ||
+      n_fac <= 0 || !fac_index || !(tol_step >= 0.0) || max_iter < 1 || !x)
+    return fail(ctx, BEM_EINVAL, "bem_refine_batched: bad argument");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
+  {
+    std::vector<int32_t> fi(n_k);
+    BEM_HIP_TRY(ctx, hipMemcpyAsync(fi.data(), fac_index, 4 * (size_t)n_k, hipMemcpyDeviceToHost, ctx->stream));
+    BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (int q = 0; q < n_k; ++q)
+      if (fi[q] < 0 || fi[q] >= n_fac)
+        return fail(ctx, BEM_EINVAL, "bem_refine_batched: fac_index[%d] = %d out of range", q, fi[q]);
+  }
+  const int kc = std::min(n_k, 512);
+  const size_t v = (size_t)kc * n_rhs * n;
+  size_t need = 0;
+  auto sz = [&](size_t b) { return (b + 255) / 256 * 256; };
+  need += sz((size_t)n_fac * n * 4) + sz((size_t)kc * n * 32) + 2 * sz(v * 16) + 2 * sz(v * 8) +
+          3 * sz((size_t)kc * n_rhs * 8) + sz((size_t)kc * n_rhs) + sz((size_t)kc * 4);
+  void* ws = nullptr;
+  if ((st = workspace(ctx, need, &ws)) != BEM_OK) return st;
+  char* p = (char*)ws;
+  auto take = [&](size_t b) { void* o = p; p += sz(b); return o; };
+  int32_t* perm = (int32_t*)take((size_t)n_fac * n * 4);
+  double2* diag = (double2*)take((size_t)kc * n * 32);
+  double2* b = (double2*)take(v * 16);
+  double2* r = (double2*)take(v * 16);
+  float2* r32 = (float2*)take(v * 8);
+  float2* d32 = (float2*)take(v * 8);
+  double* scale = (double*)take((size_t)kc * n_rhs * 8);
+  double* dn2 = (double*)take((size_t)kc * n_rhs * 8);
+  double* xn2 = (double*)take((size_t)kc * n_rhs * 8);
+  uint8_t* active = (uint8_t*)take((size_t)kc * n_rhs);
+  int32_t* fidx = (int32_t*)take((size_t)kc * 4);
+  (void)fidx;
+  if ((st = lu_perm(ctx, n, n_fac, piv, perm)) != BEM_OK) return st;
+  void* hp = nullptr;
+  const int nvmax = kc * n_rhs;
+  if ((st = pinned(ctx, (size_t)nvmax * 17, &hp)) != BEM_OK) return st;
+  double* h_dn = (double*)hp;
+  double* h_xn = h_dn + nvmax;
+  uint8_t* h_act = (uint8_t*)(h_xn + nvmax);
+  for (int k0 = 0; k0 < n_k; k0 += kc) {
+    const int cur = std::min(kc, n_k - k0);
+    const int nv = cur * n_rhs;
+    const double2* yk = (const double2*)y + (size_t)k0 * n_rhs * n;
+    double2* xk = (double2*)x + (size_t)k0 * n_rhs * n;
+    if ((st = launch_assemble(ctx, s, cur, k + k0, n_rhs, yk, BEM_C128, nullptr, n, 0, b, diag)) != BEM_OK)
+      return st;
+    std::vector<uint8_t> act(nv, 1);
+    std::vector<double> step(nv, 1.0);
+    std::vector<int> iters(nv, 0);
+    for (int it = 0; it < max_iter; ++it) {
+      if ((st = launch_residual(ctx, s, cur, k + k0, n_rhs, yk, xk, diag, r)) != BEM_OK) return st;
+      std::memcpy(h_act, act.data(), nv);
+      BEM_HIP_TRY(ctx, hipMemcpyAsync(active, h_act, nv, hipMemcpyHostToDevice, ctx->stream));
+      if ((st = launch_ir_scale(ctx, nv, n, r, r32, scale)) != BEM_OK) return st;
+      if ((st = lu_solve_perm(ctx, BEM_C64, n, ld, stride, cur, LU, perm, n_rhs, r32, d32,
+                              (int64_t)n_rhs * n, fac_index + k0)) != BEM_OK)
+        return st;
+      if ((st = launch_ir_update(ctx, nv, n, d32, scale, active, xk, dn2, xn2)) != BEM_OK) return st;
+      BEM_HIP_TRY(ctx, hipMemcpyAsync(h_dn, dn2, 8 * nv, hipMemcpyDeviceToHost, ctx->stream));
+      BEM_HIP_TRY(ctx, hipMemcpyAsync(h_xn, xn2, 8 * nv, hipMemcpyDeviceToHost, ctx->stream));
+      BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      int live = 0;
+      for (int q = 0; q < nv; ++q) {
+        if (!act[q]) continue;
+        iters[q] = it + 1;
+        const double sx = h_xn[q] > 0 ? std::sqrt(h_dn[q] / h_xn[q]) : (h_dn[q] > 0 ? 1.0 : 0.0);
+        step[q] = sx;
+        if (!(sx > tol_step) && std::isfinite(sx)) act[q] = 0;
+        else ++live;
+      }
+      if (live == 0) break;
+    }
+    if (info) {
+      if ((st = launch_residual(ctx, s, cur, k + k0, n_rhs, yk, xk, diag, r)) != BEM_OK) return st;
+      if ((st = launch_norm2(ctx, nv, n, r, dn2)) != BEM_OK) return st;
+      if ((st = launch_norm2(ctx, nv, n, b, xn2)) != BEM_OK) return st;
+      BEM_HIP_TRY(ctx, hipMemcpyAsync(h_dn, dn2, 8 * nv, hipMemcpyDeviceToHost, ctx->stream));
+      BEM_HIP_TRY(ctx, hipMemcpyAsync(h_xn, xn2, 8 * nv, hipMemcpyDeviceToHost, ctx->stream));
+      BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      for (int q = 0; q < nv; ++q) {
+        bem_solve_info& I = info[(size_t)k0 * n_rhs + q];
+        I.iters = iters[q];
+        I.used_fp64 = 0;
+        I.singular = 0;
+        I.rel_resid = h_xn[q] > 0 ? std::sqrt(h_dn[q] / h_xn[q]) : 0.0;
+        I.rel_step = step[q];
+        I.converged = act[q] ? 0 : 1;
+      }
+    }
   }
   BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   return BEM_OK;

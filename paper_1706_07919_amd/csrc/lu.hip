@@ -330,6 +330,116 @@ __global__ __launch_bounds__(256) void gemm_c32_kernel(int M, int N, int K, int6
     }
 }
 
+// ============================================================== GEMM f32 (3M)
+// The same update with three real products per complex product:
+//   T1 = Ar Br, T2 = Ai Bi, T3 = (Ar + Ai)(Br + Bi);  Re C -= T1 - T2,
+//   Im C -= T3 - T1 - T2.
+// Each MFMA 32x32x2 covers two complex k of one product, so a complex k costs
+// 1.5 MFMA per 32x32 block instead of 2 (4M).  The operand sums are formed
+// once while staging the tiles in LDS.
+__global__ __launch_bounds__(256) void gemm_c32_3m_kernel(int M, int N, int K, int64_t ld,
+                                                          int64_t stride, const float2* Ag,
+                                                          const float2* Bg, float2* Cg,
+                                                          int tiles_n) {
+  __shared__ float As[2][3][G32_BK][G32_BM + 4];
+  __shared__ float Bs[2][3][G32_BK][G32_BN + 4];
+  const int tile = blockIdx.x;
+  const int tm = tile / tiles_n, tn = tile % tiles_n;
+  const int m0 = tm * G32_BM, n0 = tn * G32_BN;
+  const int64_t boff = (int64_t)blockIdx.y * stride;
+  const float2* A = Ag + boff;
+  const float2* B = Bg + boff;
+  float2* C = Cg + boff;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  const int h = lane >> 5, l32 = lane & 31;
+
+  floatx16 acc[3][2][2];
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[p][i][j][v] = 0.f;
+
+  float2 ra[4], rb[4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int row = e >> 3, kk = e & 7;
+      const int gr = m0 + row, gk = k0 + kk;
+      ra[q] = (gr < M && gk < K) ? A[(int64_t)gr * ld + gk] : make_float2(0.f, 0.f);
+      const int brow = e >> 7, bcol = e & 127;
+      const int gbk = k0 + brow, gbc = n0 + bcol;
+      rb[q] = (gbk < K && gbc < N) ? B[(int64_t)gbk * ld + gbc] : make_float2(0.f, 0.f);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int row = e >> 3, kk = e & 7;
+      As[buf][0][kk][row] = ra[q].x;
+      As[buf][1][kk][row] = ra[q].y;
+      As[buf][2][kk][row] = ra[q].x + ra[q].y;
+      const int brow = e >> 7, bcol = e & 127;
+      Bs[buf][0][brow][bcol] = rb[q].x;
+      Bs[buf][1][brow][bcol] = rb[q].y;
+      Bs[buf][2][brow][bcol] = rb[q].x + rb[q].y;
+    }
+  };
+
+  const int nk = (K + G32_BK - 1) / G32_BK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * G32_BK);
+#pragma unroll
+    for (int k = 0; k < G32_BK; k += 2) {
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        float a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = As[cur][p][k + h][wm * 64 + i * 32 + l32];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = Bs[cur][p][k + h][wn * 64 + j * 32 + l32];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[p][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[p][i][j], 0, 0, 0);
+      }
+    }
+    if (kt + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn * 64 + j * 32 + l32;
+      if (col >= N) continue;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        if (row < M) {
+          float2* p = C + (int64_t)row * ld + col;
+          float2 c = *p;
+          const float t1 = acc[0][i][j][v], t2 = acc[1][i][j][v], t3 = acc[2][i][j][v];
+          c.x -= t1 - t2;
+          c.y -= t3 - t1 - t2;
+          *p = c;
+        }
+      }
+    }
+}
+
 // ============================================================== GEMM f64
 // Same contraction in float64 on MFMA 16x16x4 f64: one MFMA covers two
 // complex k (four interleaved real k).  64 x 64 tile, 4 waves of 32 x 32.
@@ -475,12 +585,15 @@ __global__ __launch_bounds__(256) void getrs_kernel(int n, int64_t ld, int64_t s
                                                     const typename Cx<R>::T* LU,
                                                     const int32_t* perm, int n_rhs,
                                                     const typename Cx<R>::T* Bin,
-                                                    typename Cx<R>::T* X, int64_t bstride) {
+                                                    typename Cx<R>::T* X, int64_t bstride,
+                                                    const int32_t* fac_index) {
   using C = typename Cx<R>::T;
   __shared__ C part[TS_B];
   const int mat = blockIdx.x / n_rhs, rhs = blockIdx.x % n_rhs;
-  const C* Lb = LU + (int64_t)mat * stride;
-  const int32_t* pb = perm + (int64_t)mat * n;
+  // vector group `mat` is solved with factor set fac_index[mat] (identity if NULL)
+  const int fac = fac_index ? fac_index[mat] : mat;
+  const C* Lb = LU + (int64_t)fac * stride;
+  const int32_t* pb = perm + (int64_t)fac * n;
   const C* bin = Bin + (int64_t)mat * bstride + (int64_t)rhs * n;
   C* x = X + (int64_t)mat * bstride + (int64_t)rhs * n;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -576,6 +689,7 @@ struct Fac {
   int32_t* info;
   LuPlan plan;
   int base;
+  int g3m = 0;     // 3-product complex GEMM for c64
   bem_status st = BEM_OK;
 
   size_t esz() const { return prec == BEM_C128 ? 16 : 8; }
@@ -644,9 +758,14 @@ struct Fac {
                          (double2*)at(rc, cc), tn);
     } else {
       const int tn = (N + G32_BN - 1) / G32_BN, tm = (M + G32_BM - 1) / G32_BM;
-      hipLaunchKernelGGL(gemm_c32_kernel, dim3(tm * tn, batch), dim3(256), 0, ctx->stream, M, N,
-                         K, ld, stride, (const float2*)at(ra, ca), (const float2*)at(rb, cb),
-                         (float2*)at(rc, cc), tn);
+      if (g3m)
+        hipLaunchKernelGGL(gemm_c32_3m_kernel, dim3(tm * tn, batch), dim3(256), 0, ctx->stream, M,
+                           N, K, ld, stride, (const float2*)at(ra, ca), (const float2*)at(rb, cb),
+                           (float2*)at(rc, cc), tn);
+      else
+        hipLaunchKernelGGL(gemm_c32_kernel, dim3(tm * tn, batch), dim3(256), 0, ctx->stream, M, N,
+                           K, ld, stride, (const float2*)at(ra, ca), (const float2*)at(rb, cb),
+                           (float2*)at(rc, cc), tn);
     }
   }
   // X = L^{-1} X for rows [r0, r0+m1) and columns [col0, col0+ncol)
@@ -696,7 +815,6 @@ int lu_default_nb(bem_prec prec, int n) {
 
 bem_status lu_factor(bem_ctx* ctx, bem_prec prec, int n, int64_t ld, int64_t stride, int batch,
                      void* A, int32_t* piv, int32_t* info, const LuPlan& plan, int gemm_3m) {
-  (void)gemm_3m;
   if (batch <= 0 || n <= 0) return BEM_OK;
   if (n > 24 * kPanelThreads)
     return fail(ctx, BEM_EUNSUPPORTED, "lu_factor: n=%d above the supported %d", n,
@@ -704,6 +822,7 @@ bem_status lu_factor(bem_ctx* ctx, bem_prec prec, int n, int64_t ld, int64_t str
   hipLaunchKernelGGL(fill_i32_kernel, dim3((batch + 255) / 256), dim3(256), 0, ctx->stream,
                      (int64_t)batch, info, 0);
   Fac f{ctx, prec, n, ld, stride, batch, A, piv, info, plan, 0};
+  f.g3m = (gemm_3m && prec == BEM_C64) ? 1 : 0;
   const int rows_per_thread = (n + kPanelThreads - 1) / kPanelThreads;
   if (prec == BEM_C128) f.base = rows_per_thread <= 10 ? 4 : 2;
   else f.base = rows_per_thread <= 11 ? 8 : 4;
@@ -728,16 +847,18 @@ bem_status lu_perm(bem_ctx* ctx, int n, int batch, const int32_t* piv, int32_t* 
 
 bem_status lu_solve_perm(bem_ctx* ctx, bem_prec prec, int n, int64_t ld, int64_t stride,
                          int batch, const void* LU, const int32_t* perm, int n_rhs,
-                         const void* Bin, void* X, int64_t bstride) {
+                         const void* Bin, void* X, int64_t bstride, const int32_t* fac_index) {
   if (batch <= 0 || n_rhs <= 0) return BEM_OK;
   dim3 grid(batch * n_rhs);
   const int pi = prof_begin(ctx, "getrs");
   if (prec == BEM_C128)
     hipLaunchKernelGGL(getrs_kernel<double>, grid, dim3(256), 0, ctx->stream, n, ld, stride,
-                       (const double2*)LU, perm, n_rhs, (const double2*)Bin, (double2*)X, bstride);
+                       (const double2*)LU, perm, n_rhs, (const double2*)Bin, (double2*)X, bstride,
+                       fac_index);
   else
     hipLaunchKernelGGL(getrs_kernel<float>, grid, dim3(256), 0, ctx->stream, n, ld, stride,
-                       (const float2*)LU, perm, n_rhs, (const float2*)Bin, (float2*)X, bstride);
+                       (const float2*)LU, perm, n_rhs, (const float2*)Bin, (float2*)X, bstride,
+                       fac_index);
   const double esz = prec == BEM_C128 ? 16.0 : 8.0;
   prof_end(ctx, "getrs", pi, 8.0 * (double)n * n * n_rhs * batch,
            esz * ((double)n * n + 3.0 * n * n_rhs) * batch);

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kThreads) void assemble_kernel(
     const double2 mpsi = make_double2(wj * p.G.x, wj * p.G.y);
     const double2 a = hard ? mphi : mpsi;
     const double2 bb = hard ? mpsi : mphi;
-    if (WRITE_A) {
+    if (WRITE_A && A) {
       if (OUT128)
         A64[j] = a;
       else
@@ -135,10 +135,12 @@ __global__ __launch_bounds__(kThreads) void assemble_kernel(
     const double2 a = hard ? mphi : mpsi;
     const double2 bb = hard ? mpsi : mphi;
     if (WRITE_A) {
-      if (OUT128)
-        A64[i] = a;
-      else
-        A32[i] = make_float2((float)a.x, (float)a.y);
+      if (A) {
+        if (OUT128)
+          A64[i] = a;
+        else
+          A32[i] = make_float2((float)a.x, (float)a.y);
+      }
       if (diag64) {
         diag64[((int64_t)kq * n + i) * 2] = mphi;
         diag64[((int64_t)kq * n + i) * 2 + 1] = mpsi;

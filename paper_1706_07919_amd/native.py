@@ -27,6 +27,8 @@ EXPORTED = [
     "bem_mesh_counts", "bem_mesh_icosphere", "bem_incident", "bem_assemble", "bem_residual",
     "bem_solve_opts_default", "bem_solve_batched", "bem_getrf_batched", "bem_getrs_batched",
     "bem_split_unknowns", "bem_field_eval", "pulse_synthesize", "bem_pulse_coeffs",
+    "bem_residual_check", "bem_refine_batched", "bem_mlp_features", "bem_mlp_dense_fwd", "bem_mlp_dense_bwd",
+    "bem_mlp_mse_grad", "bem_mlp_adam", "bem_mlp_pack", "bem_mlp_unpack",
 ]
 
 
@@ -53,7 +55,7 @@ class bem_solve_opts(C.Structure):
 
 class bem_solve_info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("used_fp64", C.c_int32), ("singular", C.c_int32),
-                ("pad", C.c_int32), ("rel_resid", C.c_double), ("rel_step", C.c_double)]
+                ("converged", C.c_int32), ("rel_resid", C.c_double), ("rel_step", C.c_double)]
 
 
 _lib = None
@@ -92,6 +94,16 @@ def load(path: str = LIB_PATH):
                             C.c_int, vp], C.c_int),
         "pulse_synthesize": ([vp, i32, i32, vp, i32, vp, i32, i32, vp, dbl, vp], C.c_int),
         "bem_pulse_coeffs": ([i32, vp, i32, dbl, i32, i32, dbl, vp], C.c_int),
+        "bem_residual_check": ([vp, C.POINTER(bem_surface), i32, vp, i32, vp, vp, vp], C.c_int),
+        "bem_refine_batched": ([vp, C.POINTER(bem_surface), i32, vp, i32, vp, vp, i32, i64, vp, i32,
+                                vp, dbl, i32, vp, C.POINTER(bem_solve_info)], C.c_int),
+        "bem_mlp_features": ([vp, i32, vp, i32, dbl, vp], C.c_int),
+        "bem_mlp_dense_fwd": ([vp, i32, i32, i32, vp, vp, vp, i32, vp, vp], C.c_int),
+        "bem_mlp_dense_bwd": ([vp, i32, i32, i32, vp, vp, vp, i32, vp, vp, vp, vp, vp], C.c_int),
+        "bem_mlp_mse_grad": ([vp, i64, vp, vp, vp, vp, i32], C.c_int),
+        "bem_mlp_adam": ([vp, i64, vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float], C.c_int),
+        "bem_mlp_pack": ([vp, i32, i32, vp, vp, i32, vp], C.c_int),
+        "bem_mlp_unpack": ([vp, i32, i32, vp, vp, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -250,3 +262,52 @@ def bem_field_eval(ctx, surf, n_k, k, n_rhs, phi, psi, m, xp, i0, i0_given, insi
 def pulse_synthesize(ctx, m, n_k, U, n_pulse, c, T, add_incident, xp, dk, p):
     _check(load().pulse_synthesize(ctx.handle, m, n_k, _ptr(U), n_pulse, _ptr(c), T,
                                    int(add_incident), _ptr(xp), float(dk), _ptr(p)), ctx)
+
+
+def bem_residual_check(ctx, surf, n_k, k, n_rhs, y, x):
+    rel = np.empty(n_k * n_rhs)
+    _check(load().bem_residual_check(ctx.handle, C.byref(surf), n_k, _ptr(k), n_rhs, _ptr(y),
+                                     _ptr(x), rel.ctypes.data), ctx)
+    return rel
+
+
+def bem_mlp_features(ctx, B, k, n_oct, kscale, x):
+    _check(load().bem_mlp_features(ctx.handle, B, _ptr(k), n_oct, float(kscale), _ptr(x)), ctx)
+
+
+def bem_mlp_dense_fwd(ctx, B, n_in, n_out, x, W, b, act, z, y):
+    _check(load().bem_mlp_dense_fwd(ctx.handle, B, n_in, n_out, _ptr(x), _ptr(W), _ptr(b),
+                                    int(act), _ptr(z), _ptr(y)), ctx)
+
+
+def bem_mlp_dense_bwd(ctx, B, n_in, n_out, x, W, z, act, dy, dW, db, dx, dz):
+    _check(load().bem_mlp_dense_bwd(ctx.handle, B, n_in, n_out, _ptr(x), _ptr(W), _ptr(z),
+                                    int(act), _ptr(dy), _ptr(dW), _ptr(db), _ptr(dx), _ptr(dz)), ctx)
+
+
+def bem_mlp_mse_grad(ctx, count, y, t, dy, partial, n_partial):
+    _check(load().bem_mlp_mse_grad(ctx.handle, int(count), _ptr(y), _ptr(t), _ptr(dy),
+                                   _ptr(partial), int(n_partial)), ctx)
+
+
+def bem_mlp_adam(ctx, n, p, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
+    _check(load().bem_mlp_adam(ctx.handle, int(n), _ptr(p), _ptr(g), _ptr(m), _ptr(v), int(step),
+                               float(lr), float(b1), float(b2), float(eps)), ctx)
+
+
+def bem_mlp_pack(ctx, B, n, x, scale, compute_scale, t):
+    _check(load().bem_mlp_pack(ctx.handle, B, n, _ptr(x), _ptr(scale), int(compute_scale),
+                               _ptr(t)), ctx)
+
+
+def bem_mlp_unpack(ctx, B, n, t, scale, x):
+    _check(load().bem_mlp_unpack(ctx.handle, B, n, _ptr(t), _ptr(scale), _ptr(x)), ctx)
+
+
+def bem_refine_batched(ctx, surf, n_k, k, n_rhs, y, LU, ld, stride, piv, n_fac, fac_index,
+                       tol_step, max_iter, x, want_info=True):
+    info = (bem_solve_info * (n_k * n_rhs))() if want_info else None
+    _check(load().bem_refine_batched(ctx.handle, C.byref(surf), n_k, _ptr(k), n_rhs, _ptr(y),
+                                     _ptr(LU), ld, stride, _ptr(piv), n_fac, _ptr(fac_index),
+                                     float(tol_step), int(max_iter), _ptr(x), info), ctx)
+    return info

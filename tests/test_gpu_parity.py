@@ -162,6 +162,22 @@ def test_getrf_getrs_random(ctx, prec, n, nb):
             assert np.max(np.abs(L @ U - PA)) < (1e-12 if prec == native.BEM_C128 else 1e-4) * np.sqrt(n) * 4
 
 
+@pytest.mark.parametrize("n", [130, 777])
+def test_getrf_3m_gemm(ctx, n):
+    rng = np.random.default_rng(n + 1)
+    M = seeded_complex(rng, (2, n, n)) + 0.5 * np.sqrt(n) * np.eye(n)[None]
+    A = dev(M, torch.complex64)
+    piv = torch.zeros((2, n), dtype=torch.int32, device="cuda")
+    info = torch.ones(2, dtype=torch.int32, device="cuda")
+    native.bem_getrf_batched(ctx, native.BEM_C64, n, n, n * n, 2, A, piv, info, 64, 1)
+    B = seeded_complex(rng, (2, 1, n))
+    X = torch.zeros((2, 1, n), dtype=torch.complex64, device="cuda")
+    native.bem_getrs_batched(ctx, native.BEM_C64, n, n, n * n, 2, A, piv, 1, dev(B, torch.complex64), X, n)
+    X = X.cpu().numpy().astype(np.complex128)
+    for b_ in range(2):
+        assert rel(X[b_, 0], np.linalg.solve(M[b_], B[b_, 0])) < 3e-4
+
+
 def test_getrf_reports_singular(ctx):
     n = 40
     M = seeded_complex(np.random.default_rng(9), (1, n, n))
@@ -190,7 +206,7 @@ def _solve(ctx, bodies, k, mode, n_rhs=1, rng=None):
     return ds, kd, y, x, info
 
 
-@pytest.mark.parametrize("mode", [native.BEM_FP64_DIRECT, native.BEM_FP32_IR_4M])
+@pytest.mark.parametrize("mode", [native.BEM_FP64_DIRECT, native.BEM_FP32_IR_4M, native.BEM_FP32_IR_3M])
 def test_solve_config1_vs_oracle(ctx, mode):
     w = config1()
     s = Surface(w.bodies)
@@ -205,7 +221,7 @@ def test_solve_config1_vs_oracle(ctx, mode):
     assert max(errs) < 1e-6, max(errs)
     for q in range(len(w.k)):
         assert info[q].rel_resid < 1e-9
-        if mode == native.BEM_FP32_IR_4M:
+        if mode != native.BEM_FP64_DIRECT:
             assert info[q].used_fp64 == 0 and 2 <= info[q].iters <= 6
 
 

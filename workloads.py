@@ -165,3 +165,19 @@ def paper_sphere_pulse(n_cycles2: int = 4, alpha: float = 0.1, w: float = 20.1):
 
 def seeded_complex(rng: np.random.Generator, shape) -> np.ndarray:
     return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def mlp_initial_weights(sizes, seed: int = 0):
+    """Seeded initial weights of the surrogate network, an input shared by the
+    GPU trainer and the reference: W_i ~ U(-sqrt(6/in), sqrt(6/in)) [in, out]
+    float32, b_i = 0."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for a, b in zip(sizes[:-1], sizes[1:]):
+        lim = np.sqrt(6.0 / a)
+        out.append((rng.uniform(-lim, lim, (a, b)).astype(np.float32), np.zeros(b, np.float32)))
+    return out
+
+
+SURROGATE_OCTAVES = 8      # Fourier features sin/cos(2^l pi k / 12), l = 0..7
+SURROGATE_HIDDEN = (512, 512, 512, 512)
