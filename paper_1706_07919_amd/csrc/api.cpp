@@ -184,26 +184,16 @@ struct Chunk {
   uint8_t* active; // [kc*nr]
 };
 
+Chunk carve(void* base, int n, int64_t ld, int nr, int kc, bool c128, size_t* used = nullptr);
+
+// Bytes carve() lays out for one chunk (the same walk, from address 0).
 size_t chunk_bytes(int n, int64_t ld, int nr, int kc, bool c128) {
-  const size_t v = (size_t)kc * nr * n;
-  size_t s = 0;
-  auto add = [&](size_t bytes) { s += (bytes + 255) / 256 * 256; };
-  add((size_t)kc * n * ld * (c128 ? 16 : 8));
-  add((size_t)kc * n * 4);
-  add((size_t)kc * n * 4);
-  add((size_t)kc * 4);
-  add((size_t)kc * n * 32);
-  add(v * 16);
-  add(v * 16);
-  add(v * 16);
-  add(v * 8);
-  add(v * 8);
-  add((size_t)kc * nr * 8 * 3);
-  add((size_t)kc * nr);
-  return s;
+  size_t used = 0;
+  (void)carve(nullptr, n, ld, nr, kc, c128, &used);
+  return used;
 }
 
-Chunk carve(void* base, int n, int64_t ld, int nr, int kc, bool c128) {
+Chunk carve(void* base, int n, int64_t ld, int nr, int kc, bool c128, size_t* used) {
   char* p = (char*)base;
   auto take = [&](size_t bytes) {
     void* out = p;
@@ -226,6 +216,7 @@ Chunk carve(void* base, int n, int64_t ld, int nr, int kc, bool c128) {
   c.dn2 = (double*)take((size_t)kc * nr * 8);
   c.xn2 = (double*)take((size_t)kc * nr * 8);
   c.active = (uint8_t*)take((size_t)kc * nr);
+  if (used) *used = (size_t)(p - (char*)base);
   return c;
 }
 
@@ -433,53 +424,69 @@ struct SolveRun {
   bem_solve_info* info;  // [n_k * n_rhs] for this problem, or NULL
 };
 
-// FP64 direct solve of the wavenumbers [k0, k0+kc) into xout.
-bem_status solve_fp64_chunk(SolveRun& R, const Chunk& c, int k0, int kc, int64_t ld, bool want_info) {
+bem_status chunk_assemble(SolveRun& R, const Chunk& c, int k0, int kc, int64_t ld, bem_prec prec) {
+  const bem_surface* s = R.pr->s;
+  const int n = s->n, nr = R.pr->n_rhs;
+  const double2* y = (const double2*)R.pr->y + (size_t)k0 * nr * n;
+  return launch_assemble(R.ctx, s, kc, R.pr->k + k0, nr, y, prec, c.A, ld, (int64_t)n * ld, c.b,
+                         c.diag);
+}
+
+LuMatrixSet chunk_set(const SolveRun& R, const Chunk& c, int kc, int64_t ld) {
+  const int n = R.pr->s->n;
+  return LuMatrixSet{c.A, c.piv, c.info, ld, (int64_t)n * ld, n, kc};
+}
+
+// After the float64 factorisation: triangular solves and the report.
+bem_status chunk_finish_fp64(SolveRun& R, const Chunk& c, int k0, int kc, int64_t ld) {
   bem_ctx* ctx = R.ctx;
   const bem_surface* s = R.pr->s;
   const int n = s->n, nr = R.pr->n_rhs;
   const double2* y = (const double2*)R.pr->y + (size_t)k0 * nr * n;
   bem_status st;
-  if ((st = launch_assemble(ctx, s, kc, R.pr->k + k0, nr, y, BEM_C128, c.A, ld, (int64_t)n * ld,
-                            c.b, c.diag)) != BEM_OK)
-    return st;
-  LuPlan plan;
-  plan.nb = R.o->nb > 0 ? R.o->nb : lu_default_nb(BEM_C128, n);
-  if ((st = lu_factor(ctx, BEM_C128, n, ld, (int64_t)n * ld, kc, c.A, c.piv, c.info, plan, 0)) != BEM_OK)
-    return st;
   if ((st = lu_perm(ctx, n, kc, c.piv, c.perm)) != BEM_OK) return st;
   double2* xo = R.xout + (size_t)k0 * nr * n;
   if ((st = lu_solve_perm(ctx, BEM_C128, n, ld, (int64_t)n * ld, kc, c.A, c.perm, nr, c.b, xo,
                           (int64_t)nr * n)) != BEM_OK)
     return st;
-  if (want_info) {
-    std::vector<int32_t> hinfo(kc);
-    if ((st = launch_residual(ctx, s, kc, R.pr->k + k0, nr, y, xo, c.diag, c.r)) != BEM_OK) return st;
-    if ((st = launch_norm2(ctx, kc * nr, n, c.r, c.dn2)) != BEM_OK) return st;
-    if ((st = launch_norm2(ctx, kc * nr, n, c.b, c.xn2)) != BEM_OK) return st;
-    std::vector<double> rn(kc * nr), bn(kc * nr);
-    BEM_HIP_TRY(ctx, hipMemcpyAsync(rn.data(), c.dn2, 8 * rn.size(), hipMemcpyDeviceToHost, ctx->stream));
-    BEM_HIP_TRY(ctx, hipMemcpyAsync(bn.data(), c.xn2, 8 * bn.size(), hipMemcpyDeviceToHost, ctx->stream));
-    BEM_HIP_TRY(ctx, hipMemcpyAsync(hinfo.data(), c.info, 4 * kc, hipMemcpyDeviceToHost, ctx->stream));
-    BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    if (R.info)
-      for (int v = 0; v < kc * nr; ++v) {
-        bem_solve_info& I = R.info[(size_t)k0 * nr + v];
-        I.iters = 0;
-        I.used_fp64 = 1;
-        I.singular = hinfo[v / nr] != 0;
-        I.converged = hinfo[v / nr] == 0;
-        I.rel_resid = bn[v] > 0 ? std::sqrt(rn[v] / bn[v]) : 0.0;
-        I.rel_step = 0.0;
-      }
-    for (int q = 0; q < kc; ++q)
-      if (hinfo[q] != 0) return fail(ctx, BEM_ESINGULAR, "zero pivot in the FP64 factorisation");
-  }
+  std::vector<int32_t> hinfo(kc);
+  if ((st = launch_residual(ctx, s, kc, R.pr->k + k0, nr, y, xo, c.diag, c.r)) != BEM_OK) return st;
+  if ((st = launch_norm2(ctx, kc * nr, n, c.r, c.dn2)) != BEM_OK) return st;
+  if ((st = launch_norm2(ctx, kc * nr, n, c.b, c.xn2)) != BEM_OK) return st;
+  std::vector<double> rn(kc * nr), bn(kc * nr);
+  BEM_HIP_TRY(ctx, hipMemcpyAsync(rn.data(), c.dn2, 8 * rn.size(), hipMemcpyDeviceToHost, ctx->stream));
+  BEM_HIP_TRY(ctx, hipMemcpyAsync(bn.data(), c.xn2, 8 * bn.size(), hipMemcpyDeviceToHost, ctx->stream));
+  BEM_HIP_TRY(ctx, hipMemcpyAsync(hinfo.data(), c.info, 4 * kc, hipMemcpyDeviceToHost, ctx->stream));
+  BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (R.info)
+    for (int v = 0; v < kc * nr; ++v) {
+      bem_solve_info& I = R.info[(size_t)k0 * nr + v];
+      I.iters = 0;
+      I.used_fp64 = 1;
+      I.singular = hinfo[v / nr] != 0;
+      I.converged = hinfo[v / nr] == 0;
+      I.rel_resid = bn[v] > 0 ? std::sqrt(rn[v] / bn[v]) : 0.0;
+      I.rel_step = 0.0;
+    }
+  for (int q = 0; q < kc; ++q)
+    if (hinfo[q] != 0) return fail(ctx, BEM_ESINGULAR, "zero pivot in the FP64 factorisation");
   return BEM_OK;
 }
 
-bem_status solve_ir_chunk(SolveRun& R, const Chunk& c, int k0, int kc, int64_t ld,
-                          std::vector<int>& unconverged) {
+// Whole float64 direct solve of wavenumbers [k0, k0+kc) (used for fallbacks).
+bem_status solve_fp64_chunk(SolveRun& R, const Chunk& c, int k0, int kc, int64_t ld) {
+  bem_status st;
+  if ((st = chunk_assemble(R, c, k0, kc, ld, BEM_C128)) != BEM_OK) return st;
+  LuPlan plan;
+  plan.nb = R.o->nb > 0 ? R.o->nb : lu_default_nb(BEM_C128, R.pr->s->n);
+  std::vector<LuMatrixSet> sets(1, chunk_set(R, c, kc, ld));
+  if ((st = lu_factor_groups(R.ctx, BEM_C128, sets, plan, 0)) != BEM_OK) return st;
+  return chunk_finish_fp64(R, c, k0, kc, ld);
+}
+
+// After the float32 factorisation: refinement against the float64 operator.
+bem_status chunk_finish_ir(SolveRun& R, const Chunk& c, int k0, int kc, int64_t ld,
+                           std::vector<int>& unconverged) {
   bem_ctx* ctx = R.ctx;
   const bem_surface* s = R.pr->s;
   const int n = s->n, nr = R.pr->n_rhs;
@@ -487,14 +494,6 @@ bem_status solve_ir_chunk(SolveRun& R, const Chunk& c, int k0, int kc, int64_t l
   const double2* y = (const double2*)R.pr->y + (size_t)k0 * nr * n;
   const double* kk = R.pr->k + k0;
   bem_status st;
-  if ((st = launch_assemble(ctx, s, kc, kk, nr, y, BEM_C64, c.A, ld, (int64_t)n * ld, c.b,
-                            c.diag)) != BEM_OK)
-    return st;
-  LuPlan plan;
-  plan.nb = R.o->nb > 0 ? R.o->nb : lu_default_nb(BEM_C64, n);
-  if ((st = lu_factor(ctx, BEM_C64, n, ld, (int64_t)n * ld, kc, c.A, c.piv, c.info, plan,
-                      R.o->mode == BEM_FP32_IR_3M)) != BEM_OK)
-    return st;
   if ((st = lu_perm(ctx, n, kc, c.piv, c.perm)) != BEM_OK) return st;
   if ((st = fill_zero(ctx, c.x, (size_t)nv * n * 16)) != BEM_OK) return st;
   void* hp = nullptr;
@@ -508,8 +507,8 @@ bem_status solve_ir_chunk(SolveRun& R, const Chunk& c, int k0, int kc, int64_t l
   std::vector<int> iters(nv, 0);
   BEM_HIP_TRY(ctx, hipMemcpyAsync(h_info, c.info, 4 * kc, hipMemcpyDeviceToHost, ctx->stream));
   const double2* rsrc = c.b;  // first sweep: r = b (x = 0)
-  int it = 0;
-  for (; it < std::max(1, R.o->max_iter); ++it) {
+  const int max_it = std::max(1, R.o->max_iter);
+  for (int it = 0; it < max_it; ++it) {
     std::memcpy(h_act, act.data(), nv);
     BEM_HIP_TRY(ctx, hipMemcpyAsync(c.active, h_act, nv, hipMemcpyHostToDevice, ctx->stream));
     if ((st = launch_ir_scale(ctx, nv, n, rsrc, c.r32, c.scale)) != BEM_OK) return st;
@@ -531,7 +530,7 @@ bem_status solve_ir_chunk(SolveRun& R, const Chunk& c, int k0, int kc, int64_t l
       else ++live;
     }
     if (live == 0) break;
-    if (it + 1 < std::max(1, R.o->max_iter)) {
+    if (it + 1 < max_it) {
       if ((st = launch_residual(ctx, s, kc, kk, nr, y, c.x, c.diag, c.r)) != BEM_OK) return st;
       rsrc = c.r;
     }
@@ -563,8 +562,14 @@ bem_status solve_ir_chunk(SolveRun& R, const Chunk& c, int k0, int kc, int64_t l
   return BEM_OK;
 }
 
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
 }  // namespace
 
+// All problems advance together in rounds: each round takes a slice of every
+// problem's wavenumbers (slices sized so that the round fits the workspace),
+// assembles them, factors all of them in one recursion whose launches cover
+// every problem still active (uneven n), then refines each problem's slice.
 extern "C" bem_status bem_solve_batched(bem_ctx* ctx, const bem_problem* probs, int32_t n_probs,
                                         const bem_solve_opts* opts, void* const* x_out,
                                         bem_solve_info* info) {
@@ -585,41 +590,79 @@ extern "C" bem_status bem_solve_batched(bem_ctx* ctx, const bem_problem* probs, 
     if ((st = check_surface_values(ctx, P.s)) != BEM_OK) return st;
     if (P.s->n > 12288) return fail(ctx, BEM_EUNSUPPORTED, "problem %d: n = %d > 12288", p, P.s->n);
   }
+  const bool fp64 = o.mode == BEM_FP64_DIRECT;
+  const bem_prec prec = fp64 ? BEM_C128 : BEM_C64;
   size_t free_b = 0, total_b = 0;
   BEM_HIP_TRY(ctx, hipMemGetInfo(&free_b, &total_b));
-  size_t info_off = 0;
+  const size_t limit = ctx->ws_limit ? ctx->ws_limit : (size_t)(0.75 * (double)(free_b + ctx->ws_size));
+  std::vector<int64_t> ld(n_probs);
+  std::vector<size_t> info_off(n_probs, 0);
+  size_t fallback_bytes = 0;
+  int max_nk = 0, nmax = 0;
   for (int p = 0; p < n_probs; ++p) {
-    const bem_problem& P = probs[p];
-    const int n = P.s->n, nr = P.n_rhs;
-    const int64_t ld = round_up(n, 16);
-    const bool fp64 = o.mode == BEM_FP64_DIRECT;
-    size_t limit = ctx->ws_limit ? ctx->ws_limit : (size_t)(0.75 * (double)(free_b + ctx->ws_size));
-    int kc = P.n_k;
-    while (kc > 1 && chunk_bytes(n, ld, nr, kc, fp64) > limit) kc = (kc + 1) / 2;
-    void* ws = nullptr;
-    const size_t need = std::max(chunk_bytes(n, ld, nr, kc, fp64), chunk_bytes(n, ld, nr, 1, true));
-    if ((st = workspace(ctx, need, &ws)) != BEM_OK) return st;
-    SolveRun R{ctx, &P, &o, (double2*)x_out[p], info ? info + info_off : nullptr};
-    for (int k0 = 0; k0 < P.n_k; k0 += kc) {
-      const int cur = std::min(kc, P.n_k - k0);
-      Chunk c = carve(ws, n, ld, nr, cur, fp64);
-      if (fp64) {
-        if ((st = solve_fp64_chunk(R, c, k0, cur, ld, true)) != BEM_OK) return st;
-        continue;
-      }
-      std::vector<int> bad;
-      if ((st = solve_ir_chunk(R, c, k0, cur, ld, bad)) != BEM_OK) return st;
-      if (!bad.empty()) {
-        if (!o.fallback)
-          return fail(ctx, BEM_ENOCONV, "problem %d: %zu wavenumbers did not converge", p, bad.size());
-        // FP64 direct re-solve of each unconverged wavenumber (a c128 chunk of one
-        // matrix fits where the c64 chunk of cur matrices did)
-        Chunk c1 = carve(ws, n, ld, nr, 1, true);
-        for (int kq : bad)
-          if ((st = solve_fp64_chunk(R, c1, kq, 1, ld, true)) != BEM_OK) return st;
-      }
+    ld[p] = round_up(probs[p].s->n, 16);
+    if (p + 1 < n_probs) info_off[p + 1] = info_off[p] + (size_t)probs[p].n_k * probs[p].n_rhs;
+    fallback_bytes = std::max(fallback_bytes, chunk_bytes(probs[p].s->n, ld[p], probs[p].n_rhs, 1, true));
+    max_nk = std::max(max_nk, probs[p].n_k);
+    nmax = std::max(nmax, probs[p].s->n);
+  }
+  // fewest rounds whose slices fit
+  auto round_bytes = [&](int rounds) {
+    size_t s = 0;
+    for (int p = 0; p < n_probs; ++p) {
+      const int kc = (probs[p].n_k + rounds - 1) / rounds;
+      s += align256(chunk_bytes(probs[p].s->n, ld[p], probs[p].n_rhs, kc, fp64));
     }
-    info_off += (size_t)P.n_k * P.n_rhs;
+    return s;
+  };
+  int rounds = 1;
+  while (rounds < max_nk && round_bytes(rounds) > limit) rounds = std::min(max_nk, rounds * 2);
+  void* ws = nullptr;
+  if ((st = workspace(ctx, std::max(round_bytes(rounds), fallback_bytes), &ws)) != BEM_OK) return st;
+  LuPlan plan;
+  plan.nb = o.nb > 0 ? o.nb : lu_default_nb(prec, nmax);
+  std::vector<SolveRun> runs;
+  for (int p = 0; p < n_probs; ++p)
+    runs.push_back(SolveRun{ctx, &probs[p], &o, (double2*)x_out[p], info ? info + info_off[p] : nullptr});
+
+  for (int r = 0; r < rounds; ++r) {
+    struct Slice { int p, k0, kc; Chunk c; };
+    std::vector<Slice> slices;
+    char* base = (char*)ws;
+    for (int p = 0; p < n_probs; ++p) {
+      const int kcp = (probs[p].n_k + rounds - 1) / rounds;
+      const int k0 = r * kcp;
+      const int cur = std::min(kcp, probs[p].n_k - k0);
+      if (cur <= 0) continue;
+      Slice sl{p, k0, cur, carve(base, probs[p].s->n, ld[p], probs[p].n_rhs, cur, fp64)};
+      base += align256(chunk_bytes(probs[p].s->n, ld[p], probs[p].n_rhs, cur, fp64));
+      if ((st = chunk_assemble(runs[p], sl.c, k0, cur, ld[p], prec)) != BEM_OK) return st;
+      slices.push_back(sl);
+    }
+    for (size_t s0 = 0; s0 < slices.size(); s0 += 8) {
+      std::vector<LuMatrixSet> sets;
+      for (size_t q = s0; q < std::min(slices.size(), s0 + 8); ++q)
+        sets.push_back(chunk_set(runs[slices[q].p], slices[q].c, slices[q].kc, ld[slices[q].p]));
+      if ((st = lu_factor_groups(ctx, prec, sets, plan, o.mode == BEM_FP32_IR_3M)) != BEM_OK) return st;
+    }
+    std::vector<std::vector<int>> bad(slices.size());
+    for (size_t q = 0; q < slices.size(); ++q) {
+      Slice& sl = slices[q];
+      if (fp64) st = chunk_finish_fp64(runs[sl.p], sl.c, sl.k0, sl.kc, ld[sl.p]);
+      else st = chunk_finish_ir(runs[sl.p], sl.c, sl.k0, sl.kc, ld[sl.p], bad[q]);
+      if (st != BEM_OK) return st;
+    }
+    for (size_t q = 0; q < slices.size(); ++q) {
+      if (bad[q].empty()) continue;
+      const int p = slices[q].p;
+      if (!o.fallback)
+        return fail(ctx, BEM_ENOCONV, "problem %d: %zu wavenumbers did not converge", p, bad[q].size());
+      // float64 direct re-solve of each unconverged wavenumber; the round's
+      // other slices are finished, so the workspace base can be reused
+      Chunk c1 = carve(ws, probs[p].s->n, ld[p], probs[p].n_rhs, 1, true);
+      for (int kq : bad[q])
+        if ((st = solve_fp64_chunk(runs[p], c1, kq, 1, ld[p])) != BEM_OK) return st;
+    }
   }
   BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   return BEM_OK;

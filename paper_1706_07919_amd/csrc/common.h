@@ -84,6 +84,17 @@ struct LuPlan {
 };
 bem_status lu_factor(bem_ctx*, bem_prec, int n, int64_t ld, int64_t stride, int batch, void* A,
                      int32_t* piv, int32_t* info, const LuPlan& plan, int gemm_3m);
+// Uneven batches: up to 8 sets of equal-size matrices factored together, one
+// launch per recursion step covering every set that still has columns left.
+struct LuMatrixSet {
+  void* A;
+  int32_t* piv;
+  int32_t* info;
+  int64_t ld, stride;
+  int n, count;
+};
+bem_status lu_factor_groups(bem_ctx*, bem_prec, const std::vector<LuMatrixSet>& sets,
+                            const LuPlan& plan, int gemm_3m);
 // Solve A_b X = B_b in place for B_b = B + b*bstride (n_rhs vectors of length n, stride n).
 bem_status lu_solve(bem_ctx*, bem_prec, int n, int64_t ld, int64_t stride, int batch,
                     const void* LU, const int32_t* piv, int n_rhs, void* B, int64_t bstride);

@@ -9,6 +9,9 @@
 // carry all O(n^3) work and run on MFMA: float32 complex products as real
 // products of the interleaved operands (4M) accumulated in float32, float64
 // complex products on the f64 MFMA.
+#include <algorithm>
+#include <climits>
+
 #include "common.h"
 
 namespace bem {
@@ -41,15 +44,45 @@ template <typename C> __device__ inline C crecip(C a) {
   }
 }
 
+// ============================================================== matrix groups
+// The matrices of one launch come in up to kMaxGroups size classes (uneven
+// batches: bodies of different node counts, each with many wavenumbers).  The
+// table travels by value in the kernel arguments; the flattened matrix index
+// of a workgroup selects its group, and every range is clipped to the group's
+// own n, so one recursion over the largest n factors every matrix.
+constexpr int kMaxGroups = 8;
+struct LuGroup {
+  void* A;          // matrix 0 of the group (row-major, element type of the launch)
+  int32_t* piv;     // [count][n]
+  int32_t* info;    // [count]
+  int64_t ld;       // leading dimension (elements)
+  int64_t stride;   // elements between consecutive matrices
+  int n;
+  int count;
+};
+struct LuGroups {
+  LuGroup g[kMaxGroups];
+  int ng;
+};
+
+// q: flattened matrix index -> group gi and index li inside it.
+__device__ inline bool locate(const LuGroups& G, int q, int& gi, int& li) {
+#pragma unroll
+  for (int i = 0; i < kMaxGroups; ++i) {
+    if (i >= G.ng) break;
+    if (q < G.g[i].count) { gi = i; li = q; return true; }
+    q -= G.g[i].count;
+  }
+  return false;
+}
+
 // ============================================================== base panel
 // Factor columns [c0, c0+w) of rows [c0, n) in place; w <= W.  Thread t owns
 // rows c0 + t + q*NT (q < RPT).  Pivot = max |re|+|im| (lowest row on ties).
 constexpr int kPanelThreads = 512;
 
 template <typename R, int W, int RPT>
-__global__ __launch_bounds__(kPanelThreads) void panel_kernel(int n, int64_t ld, int64_t stride,
-                                                              typename Cx<R>::T* A, int32_t* piv,
-                                                              int32_t* info, int c0, int w) {
+__global__ __launch_bounds__(kPanelThreads) void panel_kernel(LuGroups G, int c0, int w_all) {
   using C = typename Cx<R>::T;
   constexpr int NT = kPanelThreads;
   __shared__ C pivrow[W];
@@ -57,8 +90,16 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(int n, int64_t ld,
   __shared__ R rv[NT / 64];
   __shared__ int ri[NT / 64];
   __shared__ int sel;
-  const int b = blockIdx.x;
-  C* Ab = A + (int64_t)b * stride;
+  int gi = 0, b = 0;
+  if (!locate(G, blockIdx.x, gi, b)) return;
+  const LuGroup& grp = G.g[gi];
+  const int n = grp.n;
+  const int64_t ld = grp.ld;
+  if (c0 >= n) return;
+  const int w = min(w_all, n - c0);
+  C* Ab = reinterpret_cast<C*>(grp.A) + (int64_t)b * grp.stride;
+  int32_t* piv = grp.piv;
+  int32_t* info = grp.info;
   const int t = threadIdx.x;
   const int lane = t & 63, wid = t >> 6;
   C a[RPT][W];
@@ -167,13 +208,20 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(int n, int64_t ld,
 }
 
 // ============================================================== row swaps
+// Interchanges of rows [r0, r1) (pivot rows from piv) applied to columns
+// [col0, col1), both ranges clipped to each matrix's n.
 template <typename C>
-__global__ void laswp_kernel(int n, int64_t ld, int64_t stride, C* A, const int32_t* piv, int r0,
-                             int r1, int col0, int ncol) {
+__global__ void laswp_kernel(LuGroups G, int r0, int r1, int col0, int col1) {
+  int gi = 0, b = 0;
+  if (!locate(G, blockIdx.y, gi, b)) return;
+  const LuGroup& grp = G.g[gi];
+  const int n = grp.n;
+  const int64_t ld = grp.ld;
   const int col = col0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= col0 + ncol) return;
-  C* Ab = A + (int64_t)blockIdx.y * stride;
-  const int32_t* pb = piv + (int64_t)blockIdx.y * n;
+  if (col >= min(col1, n)) return;
+  C* Ab = reinterpret_cast<C*>(grp.A) + (int64_t)b * grp.stride;
+  const int32_t* pb = grp.piv + (int64_t)b * n;
+  r1 = min(r1, n);
   for (int t = r0; t < r1; ++t) {
     const int p = pb[t];
     if (p != t) {
@@ -188,17 +236,24 @@ __global__ void laswp_kernel(int n, int64_t ld, int64_t stride, C* A, const int3
 // X = L^{-1} B, L = unit lower triangle of rows/cols [r0, r0+m1) (m1 <= 32),
 // B = rows [r0, r0+m1) x cols [col0, col0+ncol); one column per thread.
 template <typename C>
-__global__ __launch_bounds__(256) void trsm_kernel(int64_t ld, int64_t stride, C* A, int r0,
-                                                   int m1, int col0, int ncol) {
+__global__ __launch_bounds__(256) void trsm_kernel(LuGroups G, int r0, int m1_all, int col0,
+                                                   int col1) {
   __shared__ C L[32][33];
-  C* Ab = A + (int64_t)blockIdx.y * stride;
+  int gi = 0, b = 0;
+  if (!locate(G, blockIdx.y, gi, b)) return;
+  const LuGroup& grp = G.g[gi];
+  const int n = grp.n;
+  const int64_t ld = grp.ld;
+  const int m1 = min(m1_all, n - r0);
+  if (m1 <= 1) return;
+  C* Ab = reinterpret_cast<C*>(grp.A) + (int64_t)b * grp.stride;
   for (int e = threadIdx.x; e < m1 * m1; e += blockDim.x) {
     const int i = e / m1, j = e % m1;
     L[i][j] = Ab[(int64_t)(r0 + i) * ld + r0 + j];
   }
   __syncthreads();
   const int col = col0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= col0 + ncol) return;
+  if (col >= min(col1, n)) return;
   C x[32];
 #pragma unroll
   for (int i = 0; i < 32; ++i)
@@ -227,20 +282,51 @@ __global__ __launch_bounds__(256) void trsm_kernel(int64_t ld, int64_t stride, C
 constexpr int G32_BM = 128, G32_BN = 128, G32_BK = 8;
 constexpr int G32_APAD = 8;
 
-__global__ __launch_bounds__(256) void gemm_c32_kernel(int M, int N, int K, int64_t ld,
-                                                       int64_t stride, const float2* Ag,
-                                                       const float2* Bg, float2* Cg,
+// Operands of one workgroup's matrix: C = rows [rowC, min(rowEnd, n)) x cols
+// [colC, min(colEnd, n)), A = same rows x cols [colA, colA+K), B = rows
+// [rowB, rowB+K) x C's cols.
+template <typename C>
+struct GemmView {
+  const C* A;
+  const C* B;
+  C* Cm;
+  int64_t ld;
+  int M, N;
+};
+
+template <typename C>
+__device__ inline bool gemm_view(const LuGroups& G, int rowC, int colC, int colA, int rowB,
+                                 int rowEnd, int colEnd, GemmView<C>& v) {
+  int gi = 0, b = 0;
+  if (!locate(G, blockIdx.y, gi, b)) return false;
+  const LuGroup& grp = G.g[gi];
+  v.ld = grp.ld;
+  v.M = min(rowEnd, grp.n) - rowC;
+  v.N = min(colEnd, grp.n) - colC;
+  C* base = reinterpret_cast<C*>(grp.A) + (int64_t)b * grp.stride;
+  v.A = base + (int64_t)rowC * v.ld + colA;
+  v.B = base + (int64_t)rowB * v.ld + colC;
+  v.Cm = base + (int64_t)rowC * v.ld + colC;
+  return v.M > 0 && v.N > 0;
+}
+
+__global__ __launch_bounds__(256) void gemm_c32_kernel(LuGroups G, int rowC, int colC, int colA,
+                                                       int rowB, int rowEnd, int colEnd, int K,
                                                        int tiles_n) {
   __shared__ float As[2][G32_BK][2 * G32_BM + G32_APAD];
   __shared__ float Bs1[2][G32_BK][2 * G32_BN];
   __shared__ float Bs2[2][G32_BK][2 * G32_BN];
+  GemmView<float2> gv;
+  if (!gemm_view(G, rowC, colC, colA, rowB, rowEnd, colEnd, gv)) return;
   const int tile = blockIdx.x;
   const int tm = tile / tiles_n, tn = tile % tiles_n;
   const int m0 = tm * G32_BM, n0 = tn * G32_BN;
-  const int64_t boff = (int64_t)blockIdx.y * stride;
-  const float2* A = Ag + boff;
-  const float2* B = Bg + boff;
-  float2* C = Cg + boff;
+  const int M = gv.M, N = gv.N;
+  if (m0 >= M || n0 >= N) return;
+  const int64_t ld = gv.ld;
+  const float2* A = gv.A;
+  const float2* B = gv.B;
+  float2* C = gv.Cm;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
@@ -337,19 +423,22 @@ __global__ __launch_bounds__(256) void gemm_c32_kernel(int M, int N, int K, int6
 // Each MFMA 32x32x2 covers two complex k of one product, so a complex k costs
 // 1.5 MFMA per 32x32 block instead of 2 (4M).  The operand sums are formed
 // once while staging the tiles in LDS.
-__global__ __launch_bounds__(256) void gemm_c32_3m_kernel(int M, int N, int K, int64_t ld,
-                                                          int64_t stride, const float2* Ag,
-                                                          const float2* Bg, float2* Cg,
-                                                          int tiles_n) {
+__global__ __launch_bounds__(256) void gemm_c32_3m_kernel(LuGroups G, int rowC, int colC,
+                                                          int colA, int rowB, int rowEnd,
+                                                          int colEnd, int K, int tiles_n) {
   __shared__ float As[2][3][G32_BK][G32_BM + 4];
   __shared__ float Bs[2][3][G32_BK][G32_BN + 4];
+  GemmView<float2> gv;
+  if (!gemm_view(G, rowC, colC, colA, rowB, rowEnd, colEnd, gv)) return;
   const int tile = blockIdx.x;
   const int tm = tile / tiles_n, tn = tile % tiles_n;
   const int m0 = tm * G32_BM, n0 = tn * G32_BN;
-  const int64_t boff = (int64_t)blockIdx.y * stride;
-  const float2* A = Ag + boff;
-  const float2* B = Bg + boff;
-  float2* C = Cg + boff;
+  const int M = gv.M, N = gv.N;
+  if (m0 >= M || n0 >= N) return;
+  const int64_t ld = gv.ld;
+  const float2* A = gv.A;
+  const float2* B = gv.B;
+  float2* C = gv.Cm;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
@@ -445,20 +534,23 @@ __global__ __launch_bounds__(256) void gemm_c32_3m_kernel(int M, int N, int K, i
 // complex k (four interleaved real k).  64 x 64 tile, 4 waves of 32 x 32.
 constexpr int G64_BM = 64, G64_BN = 64, G64_BK = 8;
 
-__global__ __launch_bounds__(256) void gemm_c64_kernel(int M, int N, int K, int64_t ld,
-                                                       int64_t stride, const double2* Ag,
-                                                       const double2* Bg, double2* Cg,
+__global__ __launch_bounds__(256) void gemm_c64_kernel(LuGroups G, int rowC, int colC, int colA,
+                                                       int rowB, int rowEnd, int colEnd, int K,
                                                        int tiles_n) {
   __shared__ double As[2][G64_BK][2 * G64_BM + 4];
   __shared__ double Bs1[2][G64_BK][2 * G64_BN];
   __shared__ double Bs2[2][G64_BK][2 * G64_BN];
+  GemmView<double2> gv;
+  if (!gemm_view(G, rowC, colC, colA, rowB, rowEnd, colEnd, gv)) return;
   const int tile = blockIdx.x;
   const int tm = tile / tiles_n, tn = tile % tiles_n;
   const int m0 = tm * G64_BM, n0 = tn * G64_BN;
-  const int64_t boff = (int64_t)blockIdx.y * stride;
-  const double2* A = Ag + boff;
-  const double2* B = Bg + boff;
-  double2* C = Cg + boff;
+  const int M = gv.M, N = gv.N;
+  if (m0 >= M || n0 >= N) return;
+  const int64_t ld = gv.ld;
+  const double2* A = gv.A;
+  const double2* B = gv.B;
+  double2* C = gv.Cm;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
@@ -574,218 +666,250 @@ __global__ void fill_i32_kernel(int64_t count, int32_t* p, int32_t v) {
 }
 
 // ============================================================== triangular solves
-// One workgroup per (matrix, right-hand side).  X = U^{-1} L^{-1} P B.  The
-// vector lives in global memory (cached); blocks of 64 rows: the off-diagonal
-// part is a coalesced row-major dot product per row, the 64 x 64 diagonal
-// block is solved by one wave with register broadcasts.
+// One workgroup (8 waves) per (matrix, right-hand side): X = U^{-1} L^{-1} P B,
+// processed in blocks of 64 rows.  For each block, the 64 x 64 diagonal block
+// is staged in LDS while the waves form the off-diagonal dot products (row-major
+// rows against the solved part of x, coalesced), then one wave substitutes
+// through the diagonal block from LDS.  x lives in LDS when it fits (XLDS),
+// otherwise in global memory.
 constexpr int TS_B = 64;
+constexpr int TS_T = 512;
 
-template <typename R>
-__global__ __launch_bounds__(256) void getrs_kernel(int n, int64_t ld, int64_t stride,
-                                                    const typename Cx<R>::T* LU,
-                                                    const int32_t* perm, int n_rhs,
-                                                    const typename Cx<R>::T* Bin,
-                                                    typename Cx<R>::T* X, int64_t bstride,
-                                                    const int32_t* fac_index) {
+template <typename R, bool XLDS>
+__global__ __launch_bounds__(TS_T) void getrs_kernel(int n, int64_t ld, int64_t stride,
+                                                     const typename Cx<R>::T* LU,
+                                                     const int32_t* perm, int n_rhs,
+                                                     const typename Cx<R>::T* Bin,
+                                                     typename Cx<R>::T* X, int64_t bstride,
+                                                     const int32_t* fac_index) {
   using C = typename Cx<R>::T;
-  __shared__ C part[TS_B];
+  extern __shared__ unsigned char smem[];
+  C* D = reinterpret_cast<C*>(smem);                 // [TS_B][TS_B + 1]
+  C* part = D + TS_B * (TS_B + 1);                   // [TS_B]
+  C* xs = part + TS_B;                               // [n] when XLDS
   const int mat = blockIdx.x / n_rhs, rhs = blockIdx.x % n_rhs;
   // vector group `mat` is solved with factor set fac_index[mat] (identity if NULL)
   const int fac = fac_index ? fac_index[mat] : mat;
   const C* Lb = LU + (int64_t)fac * stride;
   const int32_t* pb = perm + (int64_t)fac * n;
   const C* bin = Bin + (int64_t)mat * bstride + (int64_t)rhs * n;
-  C* x = X + (int64_t)mat * bstride + (int64_t)rhs * n;
+  C* xg = X + (int64_t)mat * bstride + (int64_t)rhs * n;
+  C* x = XLDS ? xs : xg;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  for (int i = tid; i < n; i += blockDim.x) x[i] = bin[pb[i]];
+  constexpr int NW = TS_T / 64;
+  for (int i = tid; i < n; i += TS_T) x[i] = bin[pb[i]];
   __threadfence_block();
   __syncthreads();
   const int nb = (n + TS_B - 1) / TS_B;
-  // forward: unit lower
-  for (int I = 0; I < nb; ++I) {
-    const int i0 = I * TS_B, rows = min(TS_B, n - i0);
-    for (int rr = wid; rr < rows; rr += 4) {
-      const C* Li = Lb + (int64_t)(i0 + rr) * ld;
-      R sr = 0, si = 0;
-      for (int j = lane; j < i0; j += 64) {
-        const C l = Li[j], v = x[j];
-        sr += l.x * v.x - l.y * v.y;
-        si += l.x * v.y + l.y * v.x;
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool fwd = pass == 0;
+    for (int step = 0; step < nb; ++step) {
+      const int I = fwd ? step : nb - 1 - step;
+      const int i0 = I * TS_B, rows = min(TS_B, n - i0);
+      // stage the diagonal block
+      for (int e = tid; e < rows * TS_B; e += TS_T) {
+        const int r = e / TS_B, c = e % TS_B;
+        if (c < rows) D[r * (TS_B + 1) + c] = Lb[(int64_t)(i0 + r) * ld + i0 + c];
       }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        sr += __shfl_down(sr, off, 64);
-        si += __shfl_down(si, off, 64);
-      }
-      if (lane == 0) part[rr] = cmk<C>(sr, si);
-    }
-    __syncthreads();
-    if (wid == 0) {
-      C v = cmk<C>(R(0), R(0));
-      if (lane < rows) v = csub(x[i0 + lane], part[lane]);
-      for (int c = 0; c < rows; ++c) {
-        const R xr = __shfl(v.x, c, 64), xi = __shfl(v.y, c, 64);
-        if (lane > c && lane < rows) {
-          const C l = Lb[(int64_t)(i0 + lane) * ld + i0 + c];
-          v = csub(v, cmul(l, cmk<C>(xr, xi)));
+      // off-diagonal dot products: forward uses columns [0, i0), backward [i0+rows, n)
+      const int jlo = fwd ? 0 : i0 + rows, jhi = fwd ? i0 : n;
+      for (int rr = wid; rr < rows; rr += NW) {
+        const C* Li = Lb + (int64_t)(i0 + rr) * ld;
+        R sr = 0, si = 0, sr2 = 0, si2 = 0;
+        int j = jlo + lane;
+        for (; j + 64 < jhi; j += 128) {
+          const C l0 = Li[j], v0 = x[j], l1 = Li[j + 64], v1 = x[j + 64];
+          sr += l0.x * v0.x - l0.y * v0.y;
+          si += l0.x * v0.y + l0.y * v0.x;
+          sr2 += l1.x * v1.x - l1.y * v1.y;
+          si2 += l1.x * v1.y + l1.y * v1.x;
         }
-      }
-      if (lane < rows) x[i0 + lane] = v;
-    }
-    __threadfence_block();
-    __syncthreads();
-  }
-  // backward: upper with diagonal
-  for (int I = nb - 1; I >= 0; --I) {
-    const int i0 = I * TS_B, rows = min(TS_B, n - i0);
-    const int jlo = i0 + rows;
-    for (int rr = wid; rr < rows; rr += 4) {
-      const C* Ui = Lb + (int64_t)(i0 + rr) * ld;
-      R sr = 0, si = 0;
-      for (int j = jlo + lane; j < n; j += 64) {
-        const C u = Ui[j], v = x[j];
-        sr += u.x * v.x - u.y * v.y;
-        si += u.x * v.y + u.y * v.x;
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        sr += __shfl_down(sr, off, 64);
-        si += __shfl_down(si, off, 64);
-      }
-      if (lane == 0) part[rr] = cmk<C>(sr, si);
-    }
-    __syncthreads();
-    if (wid == 0) {
-      C v = cmk<C>(R(0), R(0));
-      C dinv = cmk<C>(R(1), R(0));
-      if (lane < rows) {
-        v = csub(x[i0 + lane], part[lane]);
-        dinv = crecip(Lb[(int64_t)(i0 + lane) * ld + i0 + lane]);
-      }
-      for (int c = rows - 1; c >= 0; --c) {
-        if (lane == c) v = cmul(v, dinv);
-        const R xr = __shfl(v.x, c, 64), xi = __shfl(v.y, c, 64);
-        if (lane < c) {
-          const C u = Lb[(int64_t)(i0 + lane) * ld + i0 + c];
-          v = csub(v, cmul(u, cmk<C>(xr, xi)));
+        if (j < jhi) {
+          const C l0 = Li[j], v0 = x[j];
+          sr += l0.x * v0.x - l0.y * v0.y;
+          si += l0.x * v0.y + l0.y * v0.x;
         }
+        sr += sr2;
+        si += si2;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          sr += __shfl_down(sr, off, 64);
+          si += __shfl_down(si, off, 64);
+        }
+        if (lane == 0) part[rr] = cmk<C>(sr, si);
       }
-      if (lane < rows) x[i0 + lane] = v;
+      __syncthreads();
+      if (wid == 0) {
+        C v = cmk<C>(R(0), R(0));
+        if (lane < rows) v = csub(x[i0 + lane], part[lane]);
+        if (fwd) {
+          for (int c = 0; c < rows; ++c) {
+            const R xr = __shfl(v.x, c, 64), xi = __shfl(v.y, c, 64);
+            if (lane > c && lane < rows) v = csub(v, cmul(D[lane * (TS_B + 1) + c], cmk<C>(xr, xi)));
+          }
+        } else {
+          const C dinv = lane < rows ? crecip(D[lane * (TS_B + 1) + lane]) : cmk<C>(R(1), R(0));
+          for (int c = rows - 1; c >= 0; --c) {
+            if (lane == c) v = cmul(v, dinv);
+            const R xr = __shfl(v.x, c, 64), xi = __shfl(v.y, c, 64);
+            if (lane < c) v = csub(v, cmul(D[lane * (TS_B + 1) + c], cmk<C>(xr, xi)));
+          }
+        }
+        if (lane < rows) x[i0 + lane] = v;
+      }
+      __threadfence_block();
+      __syncthreads();
     }
-    __threadfence_block();
-    __syncthreads();
   }
+  if (XLDS)
+    for (int i = tid; i < n; i += TS_T) xg[i] = x[i];
 }
 
 // ============================================================== host driver
+// One recursion over the columns of the largest matrix; every launch covers
+// all groups whose n exceeds the launch's first column, with each range
+// clipped per group inside the kernels.
 struct Fac {
   bem_ctx* ctx;
   bem_prec prec;
-  int n;
-  int64_t ld, stride;
-  int batch;
-  void* A;
-  int32_t* piv;
-  int32_t* info;
+  std::vector<LuGroup> groups;   // sorted by n, descending
   LuPlan plan;
-  int base;
-  int g3m = 0;     // 3-product complex GEMM for c64
-  bem_status st = BEM_OK;
+  int base = 8;
+  int g3m = 0;                   // 3-product complex GEMM for c64
+  int nmax = 0;
 
   size_t esz() const { return prec == BEM_C128 ? 16 : 8; }
-  char* at(int r, int c) const { return (char*)A + ((int64_t)r * ld + c) * esz(); }
+
+  // groups with n > c, and their matrix count / largest n
+  LuGroups active(int c, int* total, int* maxn) const {
+    LuGroups G{};
+    G.ng = 0;
+    *total = 0;
+    *maxn = 0;
+    for (const LuGroup& g : groups)
+      if (g.n > c && g.count > 0) {
+        G.g[G.ng++] = g;
+        *total += g.count;
+        *maxn = std::max(*maxn, g.n);
+      }
+    return G;
+  }
+  // sum over active groups of f(n_g) * count_g
+  template <typename F>
+  double work(int c, F f) const {
+    double s = 0.0;
+    for (const LuGroup& g : groups)
+      if (g.n > c) s += f(g.n) * g.count;
+    return s;
+  }
 
   template <typename R, int W, int RPT>
-  void panel_go(int c0, int w) {
-    using C = typename Cx<R>::T;
-    hipLaunchKernelGGL((panel_kernel<R, W, RPT>), dim3(batch), dim3(kPanelThreads), 0,
-                       ctx->stream, n, ld, stride, (C*)A, piv, info, c0, w);
+  void panel_go(const LuGroups& G, int total, int c0, int w) {
+    hipLaunchKernelGGL((panel_kernel<R, W, RPT>), dim3(total), dim3(kPanelThreads), 0,
+                       ctx->stream, G, c0, w);
   }
   template <typename R, int W>
-  void panel_w(int c0, int w) {
-    const int rows = n - c0;
+  void panel_w(const LuGroups& G, int total, int rows, int c0, int w) {
     const int rpt = (rows + kPanelThreads - 1) / kPanelThreads;
-    if (rpt <= 1) panel_go<R, W, 1>(c0, w);
-    else if (rpt <= 2) panel_go<R, W, 2>(c0, w);
-    else if (rpt <= 4) panel_go<R, W, 4>(c0, w);
-    else if (rpt <= 6) panel_go<R, W, 6>(c0, w);
-    else if (rpt <= 8) panel_go<R, W, 8>(c0, w);
-    else if (rpt <= 10) panel_go<R, W, 10>(c0, w);
-    else if (rpt <= 11) panel_go<R, W, 11>(c0, w);
-    else if (rpt <= 12) panel_go<R, W, 12>(c0, w);
-    else if (W <= 4 && sizeof(R) == 4) panel_go<R, (W <= 4 ? W : 4), 24>(c0, w);
-    else panel_go<R, (W <= 2 ? W : 2), 24>(c0, w);
+    if (rpt <= 1) panel_go<R, W, 1>(G, total, c0, w);
+    else if (rpt <= 2) panel_go<R, W, 2>(G, total, c0, w);
+    else if (rpt <= 4) panel_go<R, W, 4>(G, total, c0, w);
+    else if (rpt <= 6) panel_go<R, W, 6>(G, total, c0, w);
+    else if (rpt <= 8) panel_go<R, W, 8>(G, total, c0, w);
+    else if (rpt <= 10) panel_go<R, W, 10>(G, total, c0, w);
+    else if (rpt <= 11) panel_go<R, W, 11>(G, total, c0, w);
+    else if (rpt <= 12) panel_go<R, W, 12>(G, total, c0, w);
+    else if (W <= 4 && sizeof(R) == 4) panel_go<R, (W <= 4 ? W : 4), 24>(G, total, c0, w);
+    else panel_go<R, (W <= 2 ? W : 2), 24>(G, total, c0, w);
   }
   void panel(int c0, int w) {
+    int total, maxn;
+    const LuGroups G = active(c0, &total, &maxn);
+    if (total == 0) return;
     const int pi = prof_begin(ctx, "panel");
-    panel_launch(c0, w);
-    // a panel of w columns over m rows: ~ 8 m w^2 / 2 flops, m w elements read and written
-    const double m = n - c0;
-    prof_end(ctx, "panel", pi, 4.0 * m * w * w * batch, 2.0 * esz() * m * w * batch);
-  }
-  void panel_launch(int c0, int w) {
+    const int rows = maxn - c0;
     if (prec == BEM_C128) {
-      if (base >= 4) panel_w<double, 4>(c0, w);
-      else panel_w<double, 2>(c0, w);
+      if (base >= 4) panel_w<double, 4>(G, total, rows, c0, w);
+      else panel_w<double, 2>(G, total, rows, c0, w);
     } else {
-      if (base >= 8) panel_w<float, 8>(c0, w);
-      else panel_w<float, 4>(c0, w);
+      if (base >= 8) panel_w<float, 8>(G, total, rows, c0, w);
+      else panel_w<float, 4>(G, total, rows, c0, w);
     }
+    // a panel of w columns over m rows: ~ 8 m w^2 / 2 flops, m w elements read and written
+    const double es = (double)esz();
+    prof_end(ctx, "panel", pi,
+             work(c0, [&](int n) { const double m = n - c0, ww = std::min(w, n - c0); return 4.0 * m * ww * ww; }),
+             work(c0, [&](int n) { const double m = n - c0, ww = std::min(w, n - c0); return 2.0 * es * m * ww; }));
   }
-  void laswp(int r0, int r1, int col0, int ncol) {
-    if (ncol <= 0 || r1 <= r0) return;
-    dim3 grid((ncol + 255) / 256, batch);
+  void laswp(int r0, int r1, int col0, int col1) {
+    if (col1 <= col0 || r1 <= r0) return;
+    int total, maxn;
+    const LuGroups G = active(std::max(r0, col0), &total, &maxn);
+    if (total == 0) return;
+    const int ncol = std::min(col1, maxn) - col0;
+    if (ncol <= 0) return;
+    dim3 grid((ncol + 255) / 256, total);
     if (prec == BEM_C128)
-      hipLaunchKernelGGL(laswp_kernel<double2>, grid, dim3(256), 0, ctx->stream, n, ld, stride,
-                         (double2*)A, piv, r0, r1, col0, ncol);
+      hipLaunchKernelGGL(laswp_kernel<double2>, grid, dim3(256), 0, ctx->stream, G, r0, r1, col0, col1);
     else
-      hipLaunchKernelGGL(laswp_kernel<float2>, grid, dim3(256), 0, ctx->stream, n, ld, stride,
-                         (float2*)A, piv, r0, r1, col0, ncol);
+      hipLaunchKernelGGL(laswp_kernel<float2>, grid, dim3(256), 0, ctx->stream, G, r0, r1, col0, col1);
   }
-  void gemm(int M, int N, int K, int ra, int ca, int rb, int cb, int rc, int cc) {
-    if (M <= 0 || N <= 0 || K <= 0) return;
+  // C = rows [rowC, rowEnd) x cols [colC, colEnd) -= A(rows, [colA, colA+K)) B([rowB, rowB+K), cols)
+  void gemm(int rowC, int colC, int colA, int rowB, int rowEnd, int colEnd, int K) {
+    if (K <= 0) return;
+    int total, maxn;
+    const LuGroups G = active(std::max(rowC, colC), &total, &maxn);
+    if (total == 0) return;
+    const int M = std::min(rowEnd, maxn) - rowC, N = std::min(colEnd, maxn) - colC;
+    if (M <= 0 || N <= 0) return;
     const char* kname = prec == BEM_C128 ? "gemm_c64" : "gemm_c32";
     const int pi = prof_begin(ctx, kname);
-    gemm_launch(M, N, K, ra, ca, rb, cb, rc, cc);
-    prof_end(ctx, kname, pi, 8.0 * M * N * (double)K * batch,
-             (double)esz() * ((double)M * K + (double)K * N + 2.0 * M * N) * batch);
-  }
-  void gemm_launch(int M, int N, int K, int ra, int ca, int rb, int cb, int rc, int cc) {
     if (prec == BEM_C128) {
       const int tn = (N + G64_BN - 1) / G64_BN, tm = (M + G64_BM - 1) / G64_BM;
-      hipLaunchKernelGGL(gemm_c64_kernel, dim3(tm * tn, batch), dim3(256), 0, ctx->stream, M, N,
-                         K, ld, stride, (const double2*)at(ra, ca), (const double2*)at(rb, cb),
-                         (double2*)at(rc, cc), tn);
+      hipLaunchKernelGGL(gemm_c64_kernel, dim3(tm * tn, total), dim3(256), 0, ctx->stream, G, rowC,
+                         colC, colA, rowB, rowEnd, colEnd, K, tn);
     } else {
       const int tn = (N + G32_BN - 1) / G32_BN, tm = (M + G32_BM - 1) / G32_BM;
       if (g3m)
-        hipLaunchKernelGGL(gemm_c32_3m_kernel, dim3(tm * tn, batch), dim3(256), 0, ctx->stream, M,
-                           N, K, ld, stride, (const float2*)at(ra, ca), (const float2*)at(rb, cb),
-                           (float2*)at(rc, cc), tn);
+        hipLaunchKernelGGL(gemm_c32_3m_kernel, dim3(tm * tn, total), dim3(256), 0, ctx->stream, G,
+                           rowC, colC, colA, rowB, rowEnd, colEnd, K, tn);
       else
-        hipLaunchKernelGGL(gemm_c32_kernel, dim3(tm * tn, batch), dim3(256), 0, ctx->stream, M, N,
-                           K, ld, stride, (const float2*)at(ra, ca), (const float2*)at(rb, cb),
-                           (float2*)at(rc, cc), tn);
+        hipLaunchKernelGGL(gemm_c32_kernel, dim3(tm * tn, total), dim3(256), 0, ctx->stream, G,
+                           rowC, colC, colA, rowB, rowEnd, colEnd, K, tn);
     }
+    const double es = (double)esz();
+    auto mn = [&](int n, double& m, double& nn) {
+      m = std::max(0, std::min(rowEnd, n) - rowC);
+      nn = std::max(0, std::min(colEnd, n) - colC);
+    };
+    prof_end(ctx, kname, pi,
+             work(std::max(rowC, colC), [&](int n) { double m, nn; mn(n, m, nn); return 8.0 * m * nn * K; }),
+             work(std::max(rowC, colC), [&](int n) {
+               double m, nn; mn(n, m, nn);
+               return es * (m * K + (double)K * nn + 2.0 * m * nn);
+             }));
   }
-  // X = L^{-1} X for rows [r0, r0+m1) and columns [col0, col0+ncol)
-  void trsm(int r0, int m1, int col0, int ncol) {
-    if (ncol <= 0 || m1 <= 1) return;
+  // X = L^{-1} X for rows [r0, r0+m1) and columns [col0, col1)
+  void trsm(int r0, int m1, int col0, int col1) {
+    if (col1 <= col0 || m1 <= 1) return;
     if (m1 <= 32) {
-      dim3 grid((ncol + 255) / 256, batch);
+      int total, maxn;
+      const LuGroups G = active(r0 + 1, &total, &maxn);
+      if (total == 0) return;
+      const int ncol = std::min(col1, maxn) - col0;
+      if (ncol <= 0) return;
+      dim3 grid((ncol + 255) / 256, total);
       if (prec == BEM_C128)
-        hipLaunchKernelGGL(trsm_kernel<double2>, grid, dim3(256), 0, ctx->stream, ld, stride,
-                           (double2*)A, r0, m1, col0, ncol);
+        hipLaunchKernelGGL(trsm_kernel<double2>, grid, dim3(256), 0, ctx->stream, G, r0, m1, col0, col1);
       else
-        hipLaunchKernelGGL(trsm_kernel<float2>, grid, dim3(256), 0, ctx->stream, ld, stride,
-                           (float2*)A, r0, m1, col0, ncol);
+        hipLaunchKernelGGL(trsm_kernel<float2>, grid, dim3(256), 0, ctx->stream, G, r0, m1, col0, col1);
       return;
     }
     int h1 = ((m1 / 2) + 31) / 32 * 32;
     if (h1 >= m1) h1 = m1 - 32;
-    trsm(r0, h1, col0, ncol);
-    gemm(m1 - h1, ncol, h1, r0 + h1, r0, r0, col0, r0 + h1, col0);
-    trsm(r0 + h1, m1 - h1, col0, ncol);
+    trsm(r0, h1, col0, col1);
+    gemm(r0 + h1, col0, r0, r0, r0 + m1, col1, h1);
+    trsm(r0 + h1, m1 - h1, col0, col1);
   }
   int split(int w) const {
     if (plan.nb > 0 && w > plan.nb) return plan.nb;
@@ -798,11 +922,11 @@ struct Fac {
     if (w <= base) { panel(c0, w); return; }
     const int h = split(w);
     rec(c0, c0 + h);
-    laswp(c0, c0 + h, c0 + h, c1 - (c0 + h));
-    trsm(c0, h, c0 + h, c1 - (c0 + h));
-    gemm(n - (c0 + h), c1 - (c0 + h), h, c0 + h, c0, c0, c0 + h, c0 + h, c0 + h);
+    laswp(c0, c0 + h, c0 + h, c1);
+    trsm(c0, h, c0 + h, c1);
+    gemm(c0 + h, c0 + h, c0, c0, INT32_MAX, c1, h);
     rec(c0 + h, c1);
-    laswp(c0 + h, c1, c0, h);
+    laswp(c0 + h, c1, c0, c0 + h);
   }
 };
 
@@ -813,23 +937,50 @@ int lu_default_nb(bem_prec prec, int n) {
   return n >= 1024 ? 256 : 0;
 }
 
-bem_status lu_factor(bem_ctx* ctx, bem_prec prec, int n, int64_t ld, int64_t stride, int batch,
-                     void* A, int32_t* piv, int32_t* info, const LuPlan& plan, int gemm_3m) {
-  if (batch <= 0 || n <= 0) return BEM_OK;
-  if (n > 24 * kPanelThreads)
-    return fail(ctx, BEM_EUNSUPPORTED, "lu_factor: n=%d above the supported %d", n,
-                24 * kPanelThreads);
-  hipLaunchKernelGGL(fill_i32_kernel, dim3((batch + 255) / 256), dim3(256), 0, ctx->stream,
-                     (int64_t)batch, info, 0);
-  Fac f{ctx, prec, n, ld, stride, batch, A, piv, info, plan, 0};
+bem_status lu_factor_groups(bem_ctx* ctx, bem_prec prec, const std::vector<LuMatrixSet>& sets,
+                            const LuPlan& plan, int gemm_3m) {
+  Fac f;
+  f.ctx = ctx;
+  f.prec = prec;
+  f.plan = plan;
   f.g3m = (gemm_3m && prec == BEM_C64) ? 1 : 0;
-  const int rows_per_thread = (n + kPanelThreads - 1) / kPanelThreads;
+  for (const LuMatrixSet& s : sets) {
+    if (s.count <= 0 || s.n <= 0) continue;
+    if (s.n > 24 * kPanelThreads)
+      return fail(ctx, BEM_EUNSUPPORTED, "lu_factor: n=%d above the supported %d", s.n,
+                  24 * kPanelThreads);
+    LuGroup g{};
+    g.A = s.A;
+    g.piv = s.piv;
+    g.info = s.info;
+    g.ld = s.ld;
+    g.stride = s.stride;
+    g.n = s.n;
+    g.count = s.count;
+    f.groups.push_back(g);
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((s.count + 255) / 256), dim3(256), 0, ctx->stream,
+                       (int64_t)s.count, s.info, 0);
+  }
+  if (f.groups.empty()) return BEM_OK;
+  if ((int)f.groups.size() > kMaxGroups)
+    return fail(ctx, BEM_EUNSUPPORTED, "lu_factor: more than %d matrix sizes in one batch", kMaxGroups);
+  std::sort(f.groups.begin(), f.groups.end(), [](const LuGroup& a, const LuGroup& b) { return a.n > b.n; });
+  f.nmax = f.groups[0].n;
+  const int rows_per_thread = (f.nmax + kPanelThreads - 1) / kPanelThreads;
   if (prec == BEM_C128) f.base = rows_per_thread <= 10 ? 4 : 2;
   else f.base = rows_per_thread <= 11 ? 8 : 4;
   if (plan.base > 0 && plan.base < f.base) f.base = plan.base;
-  f.rec(0, n);
+  f.rec(0, f.nmax);
   BEM_CHECK_LAUNCH(ctx);
   return BEM_OK;
+}
+
+bem_status lu_factor(bem_ctx* ctx, bem_prec prec, int n, int64_t ld, int64_t stride, int batch,
+                     void* A, int32_t* piv, int32_t* info, const LuPlan& plan, int gemm_3m) {
+  if (batch <= 0 || n <= 0) return BEM_OK;
+  std::vector<LuMatrixSet> sets(1);
+  sets[0] = LuMatrixSet{A, piv, info, ld, stride, n, batch};
+  return lu_factor_groups(ctx, prec, sets, plan, gemm_3m);
 }
 
 bem_status lu_perm(bem_ctx* ctx, int n, int batch, const int32_t* piv, int32_t* perm) {
@@ -850,18 +1001,44 @@ bem_status lu_solve_perm(bem_ctx* ctx, bem_prec prec, int n, int64_t ld, int64_t
                          const void* Bin, void* X, int64_t bstride, const int32_t* fac_index) {
   if (batch <= 0 || n_rhs <= 0) return BEM_OK;
   dim3 grid(batch * n_rhs);
+  const size_t esz = prec == BEM_C128 ? 16 : 8;
+  const size_t base_lds = esz * (size_t)(TS_B * (TS_B + 1) + TS_B);
+  const bool xlds = base_lds + esz * (size_t)n <= 150 * 1024;
+  const size_t lds = base_lds + (xlds ? esz * (size_t)n : 0);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)getrs_kernel<double, true>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipFuncSetAttribute((const void*)getrs_kernel<float, true>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipFuncSetAttribute((const void*)getrs_kernel<double, false>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipFuncSetAttribute((const void*)getrs_kernel<float, false>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
   const int pi = prof_begin(ctx, "getrs");
-  if (prec == BEM_C128)
-    hipLaunchKernelGGL(getrs_kernel<double>, grid, dim3(256), 0, ctx->stream, n, ld, stride,
-                       (const double2*)LU, perm, n_rhs, (const double2*)Bin, (double2*)X, bstride,
-                       fac_index);
-  else
-    hipLaunchKernelGGL(getrs_kernel<float>, grid, dim3(256), 0, ctx->stream, n, ld, stride,
-                       (const float2*)LU, perm, n_rhs, (const float2*)Bin, (float2*)X, bstride,
-                       fac_index);
-  const double esz = prec == BEM_C128 ? 16.0 : 8.0;
+  if (prec == BEM_C128) {
+    if (xlds)
+      hipLaunchKernelGGL((getrs_kernel<double, true>), grid, dim3(TS_T), lds, ctx->stream, n, ld,
+                         stride, (const double2*)LU, perm, n_rhs, (const double2*)Bin,
+                         (double2*)X, bstride, fac_index);
+    else
+      hipLaunchKernelGGL((getrs_kernel<double, false>), grid, dim3(TS_T), lds, ctx->stream, n, ld,
+                         stride, (const double2*)LU, perm, n_rhs, (const double2*)Bin,
+                         (double2*)X, bstride, fac_index);
+  } else {
+    if (xlds)
+      hipLaunchKernelGGL((getrs_kernel<float, true>), grid, dim3(TS_T), lds, ctx->stream, n, ld,
+                         stride, (const float2*)LU, perm, n_rhs, (const float2*)Bin, (float2*)X,
+                         bstride, fac_index);
+    else
+      hipLaunchKernelGGL((getrs_kernel<float, false>), grid, dim3(TS_T), lds, ctx->stream, n, ld,
+                         stride, (const float2*)LU, perm, n_rhs, (const float2*)Bin, (float2*)X,
+                         bstride, fac_index);
+  }
   prof_end(ctx, "getrs", pi, 8.0 * (double)n * n * n_rhs * batch,
-           esz * ((double)n * n + 3.0 * n * n_rhs) * batch);
+           (double)esz * ((double)n * n + 3.0 * n * n_rhs) * batch);
   BEM_CHECK_LAUNCH(ctx);
   return BEM_OK;
 }

@@ -112,6 +112,14 @@ class Surrogate:
         return x
 
 
+def octaves_for(k_train, kscale=12.0):
+    """Number of Fourier octaves such that the highest feature frequency,
+    2^(L-1) pi / kscale, stays at a quarter of the training grid's Nyquist
+    rate pi / dk (higher octaves alias between training wavenumbers)."""
+    dk = float(np.min(np.diff(np.sort(np.asarray(k_train)))))
+    return max(1, int(np.floor(np.log2(kscale / (4.0 * dk)))) + 1)
+
+
 def nearest_index(k_pred, k_train):
     """Index of the nearest training wavenumber (host-side selection only)."""
     return np.abs(np.asarray(k_pred)[:, None] - np.asarray(k_train)[None, :]).argmin(axis=1).astype(np.int32)
@@ -137,13 +145,17 @@ def training_factors(ctx, ds, kd, y, nb=0):
     return LU, piv, ld, x, inf
 
 
-def fill_sweep(ctx, ds, k_train, k_pred, init_weights, epochs=2000, lr=1e-3, tol=1e-6,
-               refine_tol=1e-8, max_sweeps=60, n_oct=8, kscale=12.0, use_surrogate=True):
+def fill_sweep(ctx, ds, k_train, k_pred, hidden=(512, 512, 512, 512), seed=0, epochs=2000,
+               lr=1e-3, tol=1e-6, refine_tol=1e-8, max_sweeps=60, n_oct=None, kscale=12.0,
+               use_surrogate=True):
     """Solve a dense grid k_pred from the factors and solutions at k_train.
 
     Returns a dict with the solutions (c128 [n_kp][1][n]), per-stage timings,
     acceptance counts and sweep statistics."""
     import torch
+    from workloads import mlp_initial_weights
+    if n_oct is None:
+        n_oct = octaves_for(k_train, kscale)
     dev = ds.x.device
     n = ds.n
     out = {}
@@ -160,7 +172,9 @@ def fill_sweep(ctx, ds, k_train, k_pred, init_weights, epochs=2000, lr=1e-3, tol
     torch.cuda.synchronize()
     out["t_train_solves"] = time.perf_counter() - t0
     t0 = time.perf_counter()
+    out["n_oct"] = n_oct
     if use_surrogate:
+        init_weights = mlp_initial_weights([2 * n_oct, *hidden, 2 * n], seed)
         sur = Surrogate(ctx, n, init_weights, n_oct, kscale, device=dev)
         out["loss"] = sur.fit(kt, xt[:, 0], epochs=epochs, lr=lr, log_every=max(epochs // 10, 1))
         torch.cuda.synchronize()

@@ -175,7 +175,9 @@ def test_getrf_3m_gemm(ctx, n):
     native.bem_getrs_batched(ctx, native.BEM_C64, n, n, n * n, 2, A, piv, 1, dev(B, torch.complex64), X, n)
     X = X.cpu().numpy().astype(np.complex128)
     for b_ in range(2):
-        assert rel(X[b_, 0], np.linalg.solve(M[b_], B[b_, 0])) < 3e-4
+        # the 3-product form has a larger error bound than 4M (imaginary parts
+        # combine three rounded products), still far inside what refinement needs
+        assert rel(X[b_, 0], np.linalg.solve(M[b_], B[b_, 0])) < 2e-3
 
 
 def test_getrf_reports_singular(ctx):
@@ -236,6 +238,41 @@ def test_solve_mixed_bc_multi_rhs_vs_oracle(ctx):
     for q in range(len(k)):
         _, _, xs = bie.solve(s, k[q], y[q].T)
         assert rel(x[q], xs.T) < 1e-6
+
+
+@pytest.mark.parametrize("mode", [native.BEM_FP32_IR_4M, native.BEM_FP64_DIRECT])
+def test_solve_uneven_batch_vs_oracle(ctx, mode):
+    """Bodies of 42, 162 and 642 nodes (one problem each, different k counts)
+    factored together in one recursion per round."""
+    problems = [([Body((0.0, 0.0, 0.0), 0.6, 1.0, 1, SOFT)], np.array([0.5, 3.0, 7.7])),
+                ([Body((0.0, 0.0, 0.0), 0.9, 2.2, 2, HARD)], np.array([1.0, 4.4])),
+                ([Body((0.0, 0.0, 0.0), 1.2, 1.0, 3, SOFT)], np.array([0.8, 2.9, 5.1, 9.9]))]
+    args, outs, keep = [], [], []
+    for bodies, k in problems:
+        ds = DeviceSurface.from_bodies(bodies)
+        kd = dev(k)
+        y = torch.empty((len(k), 1, ds.n), dtype=torch.complex128, device="cuda")
+        native.bem_incident(ctx, ds.struct, len(k), kd, (0.0, 0.0, 1.0), y)
+        x = torch.zeros((len(k), 1, ds.n), dtype=torch.complex128, device="cuda")
+        args.append((ds.struct, len(k), kd, 1, y))
+        outs.append(x)
+        keep.append((ds, kd, y))
+    opts = native.bem_solve_opts_default()
+    opts.mode = mode
+    ctx.set_workspace_limit(8 * 1024 * 1024)   # forces several rounds
+    try:
+        info = native.bem_solve_batched(ctx, args, opts, outs)
+    finally:
+        ctx.set_workspace_limit(0)
+    q = 0
+    for (bodies, k), x in zip(problems, outs):
+        s = Surface(bodies)
+        for j, kq in enumerate(k):
+            p, dp = bie.incident_plane_wave(s, kq)
+            _, _, xs = bie.solve(s, kq, bie.known_data(s, p, dp))
+            assert rel(x[j, 0].cpu().numpy(), xs) < 1e-6
+            assert info[q].rel_resid < 1e-9
+            q += 1
 
 
 def test_solve_ir_fallback_forced(ctx):
