@@ -100,7 +100,8 @@ def main():
     t1 = time.perf_counter()
     elapsed = t1 - t0
     stats = {kname: ctx.kernel_stats(kname) for kname in
-             ("gemm_c32", "panel", "assemble", "residual", "getrs", "field", "synth")}
+             ("gemm_c32", "panel", "laswp", "trsm", "assemble", "residual", "getrs", "field",
+              "synth")}
     ctx.set_profiling(False)
     solves_per_s = n_k * args.steps / elapsed
     info = infos[-1]

@@ -21,6 +21,17 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
+// Pointers into the matrices are qualified with the global address space so
+// that loads and stores compile to global (not flat) memory instructions: flat
+// accesses also count against the LDS wait counter and would make every LDS
+// wait in the GEMM loop wait for the global prefetch as well.  (The qualifier
+// only exists in the device pass; the host pass sees plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GLOBAL __attribute__((address_space(1)))
+#else
+#define GLOBAL
+#endif
+
 template <typename R> struct Cx;
 template <> struct Cx<float> { using T = float2; };
 template <> struct Cx<double> { using T = double2; };
@@ -65,15 +76,37 @@ struct LuGroups {
   int ng;
 };
 
-// q: flattened matrix index -> group gi and index li inside it.
-__device__ inline bool locate(const LuGroups& G, int q, int& gi, int& li) {
+// q: flattened matrix index -> its group (copied out) and index li inside it.
+// Both loops run over constant indices and copy field by field, so the table
+// is read with uniform loads from the kernel arguments (a dynamic index or a
+// whole-struct copy would place the table in scratch memory).
+__device__ inline bool locate(const LuGroups& G, int q, LuGroup& out, int& li) {
+  int sel = -1;
 #pragma unroll
   for (int i = 0; i < kMaxGroups; ++i) {
-    if (i >= G.ng) break;
-    if (q < G.g[i].count) { gi = i; li = q; return true; }
-    q -= G.g[i].count;
+    if (sel < 0 && i < G.ng) {
+      if (q < G.g[i].count) { sel = i; li = q; }
+      else q -= G.g[i].count;
+    }
   }
-  return false;
+  if (sel < 0) return false;
+#pragma unroll
+  for (int i = 0; i < kMaxGroups; ++i)
+    if (i == sel) {
+      out.A = G.g[i].A;
+      out.piv = G.g[i].piv;
+      out.info = G.g[i].info;
+      out.ld = G.g[i].ld;
+      out.stride = G.g[i].stride;
+      out.n = G.g[i].n;
+      out.count = G.g[i].count;
+    }
+  return true;
+}
+
+// matrix b of a group, as a global pointer
+template <typename C> __device__ inline GLOBAL C* gmat(const LuGroup& g, int b) {
+  return (GLOBAL C*)g.A + (int64_t)b * g.stride;
 }
 
 // ============================================================== base panel
@@ -90,16 +123,16 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(LuGroups G, int c0
   __shared__ R rv[NT / 64];
   __shared__ int ri[NT / 64];
   __shared__ int sel;
-  int gi = 0, b = 0;
-  if (!locate(G, blockIdx.x, gi, b)) return;
-  const LuGroup& grp = G.g[gi];
+  LuGroup grp;
+  int b = 0;
+  if (!locate(G, blockIdx.x, grp, b)) return;
   const int n = grp.n;
   const int64_t ld = grp.ld;
   if (c0 >= n) return;
   const int w = min(w_all, n - c0);
-  C* Ab = reinterpret_cast<C*>(grp.A) + (int64_t)b * grp.stride;
-  int32_t* piv = grp.piv;
-  int32_t* info = grp.info;
+  GLOBAL C* Ab = gmat<C>(grp, b);
+  GLOBAL int32_t* piv = (GLOBAL int32_t*)grp.piv;
+  GLOBAL int32_t* info = (GLOBAL int32_t*)grp.info;
   const int t = threadIdx.x;
   const int lane = t & 63, wid = t >> 6;
   C a[RPT][W];
@@ -208,26 +241,106 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(LuGroups G, int c0
 }
 
 // ============================================================== row swaps
-// Interchanges of rows [r0, r1) (pivot rows from piv) applied to columns
-// [col0, col1), both ranges clipped to each matrix's n.
-template <typename C>
-__global__ void laswp_kernel(LuGroups G, int r0, int r1, int col0, int col1) {
-  int gi = 0, b = 0;
-  if (!locate(G, blockIdx.y, gi, b)) return;
-  const LuGroup& grp = G.g[gi];
+// Interchanges t <-> piv[t] for t in [r0, r1) (r1 - r0 <= kSwapRows), applied
+// in order to the columns [ca0, ca1) and [cb0, cb1), all clipped to each
+// matrix's n.  One workgroup per (matrix, strip of LW columns).
+//
+// The composition is formed on row indices in parallel.  Since piv[t] >= t,
+// position t is final after step t, and its content just before step t is
+// c(t) = c(u) for the last earlier step u with piv[u] = t, else row t itself;
+// c follows by pointer jumping over those parent links.  The final content of
+// position t is then c(t) if piv[t] = t, else the content of piv[t] before
+// step t: c(q) for the last earlier step q with the same target, else row
+// piv[t].  A row below r1 ends holding c(u) of the last step u that targets
+// it.  The touched rows are then gathered into LDS and scattered back.
+constexpr int kSwapRows = 256;
+
+template <typename C, int LW>
+__global__ __launch_bounds__(256) void laswp_kernel(LuGroups G, int r0, int r1_all, int ca0,
+                                                    int ca1_all, int cb0, int cb1_all) {
+  __shared__ int P[kSwapRows];
+  __shared__ int root[kSwapRows];
+  __shared__ int dst[2 * kSwapRows], src[2 * kSwapRows];
+  __shared__ int npair, any;
+  __shared__ C buf[2 * kSwapRows][LW];
+  LuGroup grp;
+  int b = 0;
+  if (!locate(G, blockIdx.y, grp, b)) return;
   const int n = grp.n;
   const int64_t ld = grp.ld;
-  const int col = col0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= min(col1, n)) return;
-  C* Ab = reinterpret_cast<C*>(grp.A) + (int64_t)b * grp.stride;
-  const int32_t* pb = grp.piv + (int64_t)b * n;
-  r1 = min(r1, n);
-  for (int t = r0; t < r1; ++t) {
-    const int p = pb[t];
-    if (p != t) {
-      C u = Ab[(int64_t)t * ld + col], v = Ab[(int64_t)p * ld + col];
-      Ab[(int64_t)t * ld + col] = v;
-      Ab[(int64_t)p * ld + col] = u;
+  const int r1 = min(r1_all, n);
+  if (r1 <= r0) return;
+  const int ca1 = min(ca1_all, n), cb1 = min(cb1_all, n);
+  const int na = max(0, ca1 - ca0), nbc = max(0, cb1 - cb0);
+  const int s0 = blockIdx.x * LW;
+  if (s0 >= na + nbc) return;
+  const int L = r1 - r0;
+  const int tid = threadIdx.x;
+  GLOBAL C* Ab = gmat<C>(grp, b);
+  const GLOBAL int32_t* pb = (const GLOBAL int32_t*)grp.piv + (int64_t)b * n;
+  if (tid == 0) { npair = 0; any = 0; }
+  __syncthreads();
+  int p = 0;
+  if (tid < L) {
+    p = pb[r0 + tid];
+    P[tid] = p;
+    root[tid] = -1;
+    if (p != r0 + tid) any = 1;
+  }
+  __syncthreads();
+  if (!any) return;
+  // parent links: the last earlier step whose target is this position
+  if (tid < L && p != r0 + tid && p < r1) atomicMax(&root[p - r0], tid);
+  __syncthreads();
+  if (tid < L && root[tid] < 0) root[tid] = tid;
+  __syncthreads();
+  // pointer jumping to the chain roots (root[i] == i marks a root)
+  for (int it = 0; it < 9; ++it) {
+    int rr = 0;
+    if (tid < L) rr = root[root[tid]];
+    __syncthreads();
+    if (tid < L) root[tid] = rr;
+    __syncthreads();
+  }
+  if (tid < L) {
+    const int i = tid;
+    int q = -1;
+    bool last = true;
+    for (int u = 0; u < L; ++u) {
+      const int pu = P[u];
+      if (pu == p && u != i) {
+        if (u < i) q = u;
+        else last = false;
+      }
+    }
+    const int s = p == r0 + i ? r0 + root[i] : (q >= 0 ? r0 + root[q] : p);
+    if (s != r0 + i) {
+      const int k = atomicAdd(&npair, 1);
+      dst[k] = r0 + i;
+      src[k] = s;
+    }
+    if (p >= r1 && last) {
+      const int k = atomicAdd(&npair, 1);
+      dst[k] = p;
+      src[k] = r0 + root[i];
+    }
+  }
+  __syncthreads();
+  const int m = npair;
+  // gather the source rows of this strip, then scatter them to their destinations
+  for (int e = tid; e < m * LW; e += 256) {
+    const int k = e / LW, j = e % LW, v = s0 + j;
+    if (v < na + nbc) {
+      const int col = v < na ? ca0 + v : cb0 + (v - na);
+      buf[k][j] = Ab[(int64_t)src[k] * ld + col];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < m * LW; e += 256) {
+    const int k = e / LW, j = e % LW, v = s0 + j;
+    if (v < na + nbc) {
+      const int col = v < na ? ca0 + v : cb0 + (v - na);
+      Ab[(int64_t)dst[k] * ld + col] = buf[k][j];
     }
   }
 }
@@ -239,14 +352,14 @@ template <typename C>
 __global__ __launch_bounds__(256) void trsm_kernel(LuGroups G, int r0, int m1_all, int col0,
                                                    int col1) {
   __shared__ C L[32][33];
-  int gi = 0, b = 0;
-  if (!locate(G, blockIdx.y, gi, b)) return;
-  const LuGroup& grp = G.g[gi];
+  LuGroup grp;
+  int b = 0;
+  if (!locate(G, blockIdx.y, grp, b)) return;
   const int n = grp.n;
   const int64_t ld = grp.ld;
   const int m1 = min(m1_all, n - r0);
   if (m1 <= 1) return;
-  C* Ab = reinterpret_cast<C*>(grp.A) + (int64_t)b * grp.stride;
+  GLOBAL C* Ab = gmat<C>(grp, b);
   for (int e = threadIdx.x; e < m1 * m1; e += blockDim.x) {
     const int i = e / m1, j = e % m1;
     L[i][j] = Ab[(int64_t)(r0 + i) * ld + r0 + j];
@@ -287,9 +400,9 @@ constexpr int G32_APAD = 8;
 // [rowB, rowB+K) x C's cols.
 template <typename C>
 struct GemmView {
-  const C* A;
-  const C* B;
-  C* Cm;
+  const GLOBAL C* A;
+  const GLOBAL C* B;
+  GLOBAL C* Cm;
   int64_t ld;
   int M, N;
 };
@@ -297,20 +410,20 @@ struct GemmView {
 template <typename C>
 __device__ inline bool gemm_view(const LuGroups& G, int rowC, int colC, int colA, int rowB,
                                  int rowEnd, int colEnd, GemmView<C>& v) {
-  int gi = 0, b = 0;
-  if (!locate(G, blockIdx.y, gi, b)) return false;
-  const LuGroup& grp = G.g[gi];
+  LuGroup grp;
+  int b = 0;
+  if (!locate(G, blockIdx.y, grp, b)) return false;
   v.ld = grp.ld;
   v.M = min(rowEnd, grp.n) - rowC;
   v.N = min(colEnd, grp.n) - colC;
-  C* base = reinterpret_cast<C*>(grp.A) + (int64_t)b * grp.stride;
+  GLOBAL C* base = gmat<C>(grp, b);
   v.A = base + (int64_t)rowC * v.ld + colA;
   v.B = base + (int64_t)rowB * v.ld + colC;
   v.Cm = base + (int64_t)rowC * v.ld + colC;
   return v.M > 0 && v.N > 0;
 }
 
-__global__ __launch_bounds__(256) void gemm_c32_kernel(LuGroups G, int rowC, int colC, int colA,
+__global__ __launch_bounds__(256, 2) void gemm_c32_kernel(LuGroups G, int rowC, int colC, int colA,
                                                        int rowB, int rowEnd, int colEnd, int K,
                                                        int tiles_n) {
   __shared__ float As[2][G32_BK][2 * G32_BM + G32_APAD];
@@ -324,9 +437,9 @@ __global__ __launch_bounds__(256) void gemm_c32_kernel(LuGroups G, int rowC, int
   const int M = gv.M, N = gv.N;
   if (m0 >= M || n0 >= N) return;
   const int64_t ld = gv.ld;
-  const float2* A = gv.A;
-  const float2* B = gv.B;
-  float2* C = gv.Cm;
+  const GLOBAL float2* A = gv.A;
+  const GLOBAL float2* B = gv.B;
+  GLOBAL float2* C = gv.Cm;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
@@ -347,10 +460,14 @@ __global__ __launch_bounds__(256) void gemm_c32_kernel(LuGroups G, int rowC, int
       const int e = tid + 256 * q;
       const int row = e >> 3, kk = e & 7;
       const int gr = m0 + row, gk = k0 + kk;
-      ra[q] = (gr < M && gk < K) ? A[(int64_t)gr * ld + gk] : make_float2(0.f, 0.f);
+      const bool oka = gr < M && gk < K;
+      const float2 va = A[oka ? (int64_t)gr * ld + gk : 0];
+      ra[q] = oka ? va : make_float2(0.f, 0.f);
       const int brow = e >> 7, bcol = e & 127;
       const int gbk = k0 + brow, gbc = n0 + bcol;
-      rb[q] = (gbk < K && gbc < N) ? B[(int64_t)gbk * ld + gbc] : make_float2(0.f, 0.f);
+      const bool okb = gbk < K && gbc < N;
+      const float2 vb = B[okb ? (int64_t)gbk * ld + gbc : 0];
+      rb[q] = okb ? vb : make_float2(0.f, 0.f);
     }
   };
   auto sstore = [&](int buf) {
@@ -402,16 +519,18 @@ __global__ __launch_bounds__(256) void gemm_c32_kernel(LuGroups G, int rowC, int
     for (int j = 0; j < 2; ++j) {
       const int col = n0 + wn * 64 + j * 32 + l32;
       if (col >= N) continue;
+      // all loads of the block first (one wait), then the stores
+      float2 c[16];
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-        if (row < M) {
-          float2* p = C + (int64_t)row * ld + col;
-          float2 c = *p;
-          c.x -= acc_re[i][j][v];
-          c.y -= acc_im[i][j][v];
-          *p = c;
-        }
+        c[v] = C[(int64_t)min(row, M - 1) * ld + col];
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        if (row < M)
+          C[(int64_t)row * ld + col] = make_float2(c[v].x - acc_re[i][j][v], c[v].y - acc_im[i][j][v]);
       }
     }
 }
@@ -436,9 +555,9 @@ __global__ __launch_bounds__(256) void gemm_c32_3m_kernel(LuGroups G, int rowC, 
   const int M = gv.M, N = gv.N;
   if (m0 >= M || n0 >= N) return;
   const int64_t ld = gv.ld;
-  const float2* A = gv.A;
-  const float2* B = gv.B;
-  float2* C = gv.Cm;
+  const GLOBAL float2* A = gv.A;
+  const GLOBAL float2* B = gv.B;
+  GLOBAL float2* C = gv.Cm;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
@@ -461,10 +580,14 @@ __global__ __launch_bounds__(256) void gemm_c32_3m_kernel(LuGroups G, int rowC, 
       const int e = tid + 256 * q;
       const int row = e >> 3, kk = e & 7;
       const int gr = m0 + row, gk = k0 + kk;
-      ra[q] = (gr < M && gk < K) ? A[(int64_t)gr * ld + gk] : make_float2(0.f, 0.f);
+      const bool oka = gr < M && gk < K;
+      const float2 va = A[oka ? (int64_t)gr * ld + gk : 0];
+      ra[q] = oka ? va : make_float2(0.f, 0.f);
       const int brow = e >> 7, bcol = e & 127;
       const int gbk = k0 + brow, gbc = n0 + bcol;
-      rb[q] = (gbk < K && gbc < N) ? B[(int64_t)gbk * ld + gbc] : make_float2(0.f, 0.f);
+      const bool okb = gbk < K && gbc < N;
+      const float2 vb = B[okb ? (int64_t)gbk * ld + gbc : 0];
+      rb[q] = okb ? vb : make_float2(0.f, 0.f);
     }
   };
   auto sstore = [&](int buf) {
@@ -514,17 +637,18 @@ __global__ __launch_bounds__(256) void gemm_c32_3m_kernel(LuGroups G, int rowC, 
     for (int j = 0; j < 2; ++j) {
       const int col = n0 + wn * 64 + j * 32 + l32;
       if (col >= N) continue;
+      float2 c[16];
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-        if (row < M) {
-          float2* p = C + (int64_t)row * ld + col;
-          float2 c = *p;
-          const float t1 = acc[0][i][j][v], t2 = acc[1][i][j][v], t3 = acc[2][i][j][v];
-          c.x -= t1 - t2;
-          c.y -= t3 - t1 - t2;
-          *p = c;
-        }
+        c[v] = C[(int64_t)min(row, M - 1) * ld + col];
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        const float t1 = acc[0][i][j][v], t2 = acc[1][i][j][v], t3 = acc[2][i][j][v];
+        if (row < M)
+          C[(int64_t)row * ld + col] = make_float2(c[v].x - (t1 - t2), c[v].y - (t3 - t1 - t2));
       }
     }
 }
@@ -548,9 +672,9 @@ __global__ __launch_bounds__(256) void gemm_c64_kernel(LuGroups G, int rowC, int
   const int M = gv.M, N = gv.N;
   if (m0 >= M || n0 >= N) return;
   const int64_t ld = gv.ld;
-  const double2* A = gv.A;
-  const double2* B = gv.B;
-  double2* C = gv.Cm;
+  const GLOBAL double2* A = gv.A;
+  const GLOBAL double2* B = gv.B;
+  GLOBAL double2* C = gv.Cm;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
@@ -572,10 +696,14 @@ __global__ __launch_bounds__(256) void gemm_c64_kernel(LuGroups G, int rowC, int
       const int e = tid + 256 * q;
       const int row = e >> 3, kk = e & 7;
       const int gr = m0 + row, gk = k0 + kk;
-      ra[q] = (gr < M && gk < K) ? A[(int64_t)gr * ld + gk] : make_double2(0.0, 0.0);
+      const bool oka = gr < M && gk < K;
+      const double2 va = A[oka ? (int64_t)gr * ld + gk : 0];
+      ra[q] = oka ? va : make_double2(0.0, 0.0);
       const int brow = e >> 6, bcol = e & 63;
       const int gbk = k0 + brow, gbc = n0 + bcol;
-      rb[q] = (gbk < K && gbc < N) ? B[(int64_t)gbk * ld + gbc] : make_double2(0.0, 0.0);
+      const bool okb = gbk < K && gbc < N;
+      const double2 vb = B[okb ? (int64_t)gbk * ld + gbc : 0];
+      rb[q] = okb ? vb : make_double2(0.0, 0.0);
     }
   };
   auto sstore = [&](int buf) {
@@ -626,17 +754,18 @@ __global__ __launch_bounds__(256) void gemm_c64_kernel(LuGroups G, int rowC, int
     for (int j = 0; j < 2; ++j) {
       const int col = n0 + wn * 32 + j * 16 + l16;
       if (col >= N) continue;
+      // f64 16x16x4 result layout: lane l, item v holds row l/16 + 4v, column l%16
+      double2 c[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        // f64 16x16x4 result layout: lane l, item v holds row l/16 + 4v, column l%16
         const int row = m0 + wm * 32 + i * 16 + kq + 4 * v;
-        if (row < M) {
-          double2* p = C + (int64_t)row * ld + col;
-          double2 c = *p;
-          c.x -= acc_re[i][j][v];
-          c.y -= acc_im[i][j][v];
-          *p = c;
-        }
+        c[v] = C[(int64_t)min(row, M - 1) * ld + col];
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm * 32 + i * 16 + kq + 4 * v;
+        if (row < M)
+          C[(int64_t)row * ld + col] = make_double2(c[v].x - acc_re[i][j][v], c[v].y - acc_im[i][j][v]);
       }
     }
 }
@@ -841,18 +970,29 @@ struct Fac {
              work(c0, [&](int n) { const double m = n - c0, ww = std::min(w, n - c0); return 4.0 * m * ww * ww; }),
              work(c0, [&](int n) { const double m = n - c0, ww = std::min(w, n - c0); return 2.0 * es * m * ww; }));
   }
-  void laswp(int r0, int r1, int col0, int col1) {
-    if (col1 <= col0 || r1 <= r0) return;
-    int total, maxn;
-    const LuGroups G = active(std::max(r0, col0), &total, &maxn);
-    if (total == 0) return;
-    const int ncol = std::min(col1, maxn) - col0;
-    if (ncol <= 0) return;
-    dim3 grid((ncol + 255) / 256, total);
-    if (prec == BEM_C128)
-      hipLaunchKernelGGL(laswp_kernel<double2>, grid, dim3(256), 0, ctx->stream, G, r0, r1, col0, col1);
-    else
-      hipLaunchKernelGGL(laswp_kernel<float2>, grid, dim3(256), 0, ctx->stream, G, r0, r1, col0, col1);
+  // interchanges of rows [r0, r1) applied to columns [ca0, ca1) and [cb0, cb1)
+  void laswp(int r0, int r1, int ca0, int ca1, int cb0 = 0, int cb1 = 0) {
+    for (int q0 = r0; q0 < r1; q0 += kSwapRows) {
+      const int q1 = std::min(r1, q0 + kSwapRows);
+      int total, maxn;
+      const LuGroups G = active(q0, &total, &maxn);
+      if (total == 0) return;
+      const int na = std::max(0, std::min(ca1, maxn) - ca0);
+      const int nbc = std::max(0, std::min(cb1, maxn) - cb0);
+      if (na + nbc == 0) return;
+      const int pi = prof_begin(ctx, "laswp");
+      if (prec == BEM_C128) {
+        constexpr int LW = 8;
+        hipLaunchKernelGGL((laswp_kernel<double2, LW>), dim3((na + nbc + LW - 1) / LW, total),
+                           dim3(256), 0, ctx->stream, G, q0, q1, ca0, ca1, cb0, cb1);
+      } else {
+        constexpr int LW = 16;
+        hipLaunchKernelGGL((laswp_kernel<float2, LW>), dim3((na + nbc + LW - 1) / LW, total),
+                           dim3(256), 0, ctx->stream, G, q0, q1, ca0, ca1, cb0, cb1);
+      }
+      // at most every row of the range moves once (read and write)
+      prof_end(ctx, "laswp", pi, 0.0, 2.0 * esz() * (double)(q1 - q0) * (na + nbc) * total);
+    }
   }
   // C = rows [rowC, rowEnd) x cols [colC, colEnd) -= A(rows, [colA, colA+K)) B([rowB, rowB+K), cols)
   void gemm(int rowC, int colC, int colA, int rowB, int rowEnd, int colEnd, int K) {
@@ -899,10 +1039,13 @@ struct Fac {
       const int ncol = std::min(col1, maxn) - col0;
       if (ncol <= 0) return;
       dim3 grid((ncol + 255) / 256, total);
+      const int pi = prof_begin(ctx, "trsm");
       if (prec == BEM_C128)
         hipLaunchKernelGGL(trsm_kernel<double2>, grid, dim3(256), 0, ctx->stream, G, r0, m1, col0, col1);
       else
         hipLaunchKernelGGL(trsm_kernel<float2>, grid, dim3(256), 0, ctx->stream, G, r0, m1, col0, col1);
+      prof_end(ctx, "trsm", pi, 4.0 * m1 * m1 * (double)ncol * total,
+               2.0 * esz() * m1 * (double)ncol * total);
       return;
     }
     int h1 = ((m1 / 2) + 31) / 32 * 32;
@@ -912,7 +1055,6 @@ struct Fac {
     trsm(r0 + h1, m1 - h1, col0, col1);
   }
   int split(int w) const {
-    if (plan.nb > 0 && w > plan.nb) return plan.nb;
     int h = (w / 2 + base - 1) / base * base;
     if (h >= w) h = w - base;
     return h;
@@ -928,13 +1070,26 @@ struct Fac {
     rec(c0 + h, c1);
     laswp(c0 + h, c1, c0, c0 + h);
   }
+  // Right-looking blocked top level: factor a block of nb columns (recursively),
+  // apply its interchanges to every column left and right of it in one pass,
+  // then the block row of U and the trailing update.
+  void blocked(int nb) {
+    for (int c = 0; c < nmax; c += nb) {
+      const int e = std::min(c + nb, nmax);
+      rec(c, e);
+      laswp(c, e, 0, c, e, nmax);
+      trsm(c, e - c, e, nmax);
+      gemm(e, e, c, c, INT32_MAX, nmax, e - c);
+    }
+  }
 };
 
 }  // namespace
 
 int lu_default_nb(bem_prec prec, int n) {
   (void)prec;
-  return n >= 1024 ? 256 : 0;
+  (void)n;
+  return kSwapRows;
 }
 
 bem_status lu_factor_groups(bem_ctx* ctx, bem_prec prec, const std::vector<LuMatrixSet>& sets,
@@ -970,7 +1125,9 @@ bem_status lu_factor_groups(bem_ctx* ctx, bem_prec prec, const std::vector<LuMat
   if (prec == BEM_C128) f.base = rows_per_thread <= 10 ? 4 : 2;
   else f.base = rows_per_thread <= 11 ? 8 : 4;
   if (plan.base > 0 && plan.base < f.base) f.base = plan.base;
-  f.rec(0, f.nmax);
+  // interchange ranges stay within kSwapRows rows: blocks of at most that width
+  const int nb = plan.nb > 0 ? std::min(plan.nb, kSwapRows) : kSwapRows;
+  f.blocked(nb);
   BEM_CHECK_LAUNCH(ctx);
   return BEM_OK;
 }
