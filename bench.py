@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_F32_MFMA = 157.3e12
+PEAK_BF16_MFMA = 2500.0e12
 PEAK_F64_MFMA = 78.6e12
 PEAK_HBM = 8.0e12
 
@@ -41,6 +42,8 @@ def main():
     ap.add_argument("--fp64-k", type=int, default=64, help="wavenumbers for the FP64 direct path")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-k", type=int, default=1)
+    ap.add_argument("--mode", choices=["b3", "4m", "3m"], default="b3",
+                    help="complex GEMM form of the float32 factorisation")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -76,7 +79,9 @@ def main():
     ins = torch.zeros(m, dtype=torch.uint8, device=dev)
     p = torch.zeros((1, m, T), dtype=torch.float32, device=dev)
     opts = native.bem_solve_opts_default()
-    opts.mode = native.BEM_FP32_IR_4M
+    mode = {"b3": native.BEM_FP32_IR_B3, "4m": native.BEM_FP32_IR_4M, "3m": native.BEM_FP32_IR_3M}[args.mode]
+    gname = {"b3": "gemm_b3", "4m": "gemm_c32", "3m": "gemm_3m"}[args.mode]
+    opts.mode = mode
     infos = []
 
     def step():
@@ -100,7 +105,7 @@ def main():
     t1 = time.perf_counter()
     elapsed = t1 - t0
     stats = {kname: ctx.kernel_stats(kname) for kname in
-             ("gemm_c32", "panel", "laswp", "trsm", "assemble", "residual", "getrs", "field",
+             (gname, "panel", "laswp", "trsm", "assemble", "residual", "getrs", "field",
               "synth")}
     ctx.set_profiling(False)
     solves_per_s = n_k * args.steps / elapsed
@@ -109,8 +114,13 @@ def main():
     fallbacks = sum(info[q].used_fp64 for q in range(n_k))
     max_resid = max(info[q].rel_resid for q in range(n_k))
 
-    gf, gb, gms, gl = stats["gemm_c32"]
-    achieved = gf / (gms * 1e-3) if gms > 0 else 0.0
+    gf, gb, gms, gl = stats[gname]
+    # stats count complex 4M flops (8 per complex multiply-add); the split form
+    # issues three bf16 MFMA products for each real product
+    mfma_flops = 3.0 * gf if args.mode == "b3" else (0.75 * gf if args.mode == "3m" else gf)
+    peak = PEAK_BF16_MFMA if args.mode == "b3" else PEAK_F32_MFMA
+    achieved = mfma_flops / (gms * 1e-3) if gms > 0 else 0.0
+    alg_4m = gf / (gms * 1e-3) if gms > 0 else 0.0
     ff, fb, fms, fl = stats["field"]
     field_rate = (m * n_k * args.steps) / (fms * 1e-3) if fms > 0 else 0.0
     sf, sb, sms, sl = stats["synth"]
@@ -147,20 +157,26 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 LU (f32 MFMA) + f64 residual refinement",
+        "dtype": {"b3": "c64 LU (bf16x3 split products on bf16 MFMA, f32 accumulate)",
+                  "4m": "c64 LU (f32 MFMA)", "3m": "c64 LU (3M on f32 MFMA)"}[args.mode]
+                 + " + f64 residual refinement",
         "data": "synthetic",
         "config": {"workload": w.name, "n": n, "n_k": n_k, "field_points": m, "T": T,
-                   "mode": "FP32_IR_4M", "nb": opts.nb},
+                   "mode": {"b3": "FP32_IR_B3", "4m": "FP32_IR_4M", "3m": "FP32_IR_3M"}[args.mode],
+                   "nb": opts.nb},
         "field_pt_freq_per_s": field_rate,
         "fp64_direct_solves_per_s": fp64_rate,
         "fp32ir_vs_fp64_direct_rel_err": rel64,
         "ir_iters_max": max(iters),
         "ir_fallbacks": fallbacks,
         "max_rel_resid": max_resid,
-        "roofline": {"kernel": "gemm_c32 (LU trailing update, complex 4M on MFMA f32)",
-                     "bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_F32_MFMA / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_F32_MFMA, "traffic": None,
+        "roofline": {"kernel": {"b3": "gemm_c32_b3_kernel (LU updates, bf16x3 split on MFMA bf16)",
+                                "4m": "gemm_c32_kernel (LU updates, complex 4M on MFMA f32)",
+                                "3m": "gemm_c32_3m_kernel (LU updates, complex 3M on MFMA f32)"}[args.mode],
+                     "bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
                      "launches": gl, "avg_launch_ms": gms / max(gl, 1),
+                     "complex_4m_equivalent_tflops": alg_4m / 1e12,
                      "share_of_step": gms * 1e-3 / elapsed},
         "kernels_ms_per_step": {kname: v[2] / args.steps for kname, v in stats.items()},
         "synth_hbm_frac": (sb / (sms * 1e-3)) / PEAK_HBM if sms > 0 else None,

@@ -148,9 +148,22 @@ bem_status bem_residual_check(bem_ctx* ctx, const bem_surface* s, int32_t n_k, c
  *                     float32 accumulation) + iterative refinement with the
  *                     float64 matrix-free residual, until ||dx||/||x|| <= tol_step
  *   BEM_FP32_IR_3M  : as 4M with the 3-product complex GEMM
+ *   BEM_FP32_IR_B3  : as 4M with every real product of the GEMM taken as three
+ *                     bfloat16 MFMA products of the split operands
+ *                     (x = hi + lo; hi hi + hi lo + lo hi, float32 accumulation)
+ * The refinement makes all three float32 modes reach the same float64-residual
+ * accuracy; they differ in speed and in the number of sweeps.
  * Items that do not converge within max_iter are re-solved with the FP64
  * direct path when fallback != 0 (flagged in info), else BEM_ENOCONV. */
-typedef enum { BEM_FP64_DIRECT = 0, BEM_FP32_IR_4M = 1, BEM_FP32_IR_3M = 2 } bem_mode;
+typedef enum {
+  BEM_FP64_DIRECT = 0,
+  BEM_FP32_IR_4M = 1,
+  BEM_FP32_IR_3M = 2,
+  BEM_FP32_IR_B3 = 3
+} bem_mode;
+
+/* complex GEMM form of a c64 factorisation (last argument of bem_getrf_batched) */
+typedef enum { BEM_GEMM_4M = 0, BEM_GEMM_3M = 1, BEM_GEMM_BF16X3 = 2 } bem_gemm_kind;
 
 typedef struct {
   const bem_surface* s;   /* [host] struct holding [dev] arrays */
@@ -196,14 +209,15 @@ bem_status bem_solve_batched(bem_ctx* ctx, const bem_problem* probs, int32_t n_p
  *   dimension ld >= n, stride >= n*ld elements) [dev].  piv[batch][n] [dev]
  *   int32: row i was interchanged with row piv[i] (absolute, 0-based).
  *   info[batch] [dev] int32: 0, or 1 + index of the first exactly-zero pivot.
- *   nb = top-level panel width (0 = tuned), 3M selects the 3-product complex
- *   GEMM for c64.
+ *   nb = top-level panel width (0 = tuned; at most 256 is used), gemm_kind
+ *   (bem_gemm_kind) the complex GEMM form of the trailing updates for c64
+ *   (ignored for c128).  n * ld must stay below 2^31.
  * bem_getrs_batched: X = A^{-1} B for n_rhs vectors per matrix:
  *   B, X [dev] [batch][n_rhs][n] (vector stride n, matrix stride bstride
  *   elements), same precision as the factors; B and X must not overlap. */
 bem_status bem_getrf_batched(bem_ctx* ctx, bem_prec prec, int32_t n, int32_t ld, int64_t stride,
                              int32_t batch, void* A, int32_t* piv, int32_t* info, int32_t nb,
-                             int32_t use_3m);
+                             int32_t gemm_kind);
 bem_status bem_getrs_batched(bem_ctx* ctx, bem_prec prec, int32_t n, int32_t ld, int64_t stride,
                              int32_t batch, const void* LU, const int32_t* piv, int32_t n_rhs,
                              const void* B, void* X, int64_t bstride);

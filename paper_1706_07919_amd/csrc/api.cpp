@@ -385,15 +385,16 @@ extern "C" bem_status bem_split_unknowns(bem_ctx* ctx, const bem_surface* s, int
 // ============================================================ LU building blocks
 extern "C" bem_status bem_getrf_batched(bem_ctx* ctx, bem_prec prec, int32_t n, int32_t ld,
                                         int64_t stride, int32_t batch, void* A, int32_t* piv,
-                                        int32_t* info, int32_t nb, int32_t use_3m) {
+                                        int32_t* info, int32_t nb, int32_t gemm_kind) {
   if (!ctx) return BEM_EINVAL;
   if (n <= 0 || ld < n || stride < (int64_t)n * ld || batch <= 0 || !A || !piv || !info ||
-      (prec != BEM_C64 && prec != BEM_C128) || nb < 0)
+      (prec != BEM_C64 && prec != BEM_C128) || nb < 0 || gemm_kind < BEM_GEMM_4M ||
+      gemm_kind > BEM_GEMM_BF16X3)
     return fail(ctx, BEM_EINVAL, "bem_getrf_batched: bad argument");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
   LuPlan plan;
   plan.nb = nb > 0 ? nb : lu_default_nb(prec, n);
-  return lu_factor(ctx, prec, n, ld, stride, batch, A, piv, info, plan, use_3m);
+  return lu_factor(ctx, prec, n, ld, stride, batch, A, piv, info, plan, gemm_kind);
 }
 
 extern "C" bem_status bem_getrs_batched(bem_ctx* ctx, bem_prec prec, int32_t n, int32_t ld,
@@ -578,7 +579,7 @@ extern "C" bem_status bem_solve_batched(bem_ctx* ctx, const bem_problem* probs, 
   bem_solve_opts o;
   bem_solve_opts_default(&o);
   if (opts) o = *opts;
-  if (o.mode < 0 || o.mode > 2 || o.max_iter < 0 || !(o.tol_step >= 0.0) || o.nb < 0)
+  if (o.mode < BEM_FP64_DIRECT || o.mode > BEM_FP32_IR_B3 || o.max_iter < 0 || !(o.tol_step >= 0.0) || o.nb < 0)
     return fail(ctx, BEM_EINVAL, "bem_solve_batched: bad options");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
   bem_status st;
@@ -643,7 +644,9 @@ extern "C" bem_status bem_solve_batched(bem_ctx* ctx, const bem_problem* probs, 
       std::vector<LuMatrixSet> sets;
       for (size_t q = s0; q < std::min(slices.size(), s0 + 8); ++q)
         sets.push_back(chunk_set(runs[slices[q].p], slices[q].c, slices[q].kc, ld[slices[q].p]));
-      if ((st = lu_factor_groups(ctx, prec, sets, plan, o.mode == BEM_FP32_IR_3M)) != BEM_OK) return st;
+      const int gk = o.mode == BEM_FP32_IR_3M ? BEM_GEMM_3M
+                     : o.mode == BEM_FP32_IR_B3 ? BEM_GEMM_BF16X3 : BEM_GEMM_4M;
+      if ((st = lu_factor_groups(ctx, prec, sets, plan, gk)) != BEM_OK) return st;
     }
     std::vector<std::vector<int>> bad(slices.size());
     for (size_t q = 0; q < slices.size(); ++q) {

@@ -78,12 +78,16 @@ bem_status launch_split(bem_ctx*, const bem_surface*, int n_k, int n_rhs, const 
 // Batched LU with partial pivoting of row-major matrices A_b = A + b*stride
 // (n x n, leading dimension ld).  piv_b = piv + b*n (absolute row indices).
 // info_b = info + b: 0, or 1 + first zero pivot column.
+// complex GEMM forms of the c64 factorisation (the last argument of
+// bem_getrf_batched)
+enum { kGemm4M = 0, kGemm3M = 1, kGemmBf16x3 = 2 };
+
 struct LuPlan {
   int nb = 0;          // top-level panel width (0 = recursive halving)
   int base = 8;        // width of the register-held base panel
 };
 bem_status lu_factor(bem_ctx*, bem_prec, int n, int64_t ld, int64_t stride, int batch, void* A,
-                     int32_t* piv, int32_t* info, const LuPlan& plan, int gemm_3m);
+                     int32_t* piv, int32_t* info, const LuPlan& plan, int gemm_kind);
 // Uneven batches: up to 8 sets of equal-size matrices factored together, one
 // launch per recursion step covering every set that still has columns left.
 struct LuMatrixSet {
@@ -94,7 +98,7 @@ struct LuMatrixSet {
   int n, count;
 };
 bem_status lu_factor_groups(bem_ctx*, bem_prec, const std::vector<LuMatrixSet>& sets,
-                            const LuPlan& plan, int gemm_3m);
+                            const LuPlan& plan, int gemm_kind);
 // Solve A_b X = B_b in place for B_b = B + b*bstride (n_rhs vectors of length n, stride n).
 bem_status lu_solve(bem_ctx*, bem_prec, int n, int64_t ld, int64_t stride, int batch,
                     const void* LU, const int32_t* piv, int n_rhs, void* B, int64_t bstride);

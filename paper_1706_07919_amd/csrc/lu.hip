@@ -653,6 +653,161 @@ __global__ __launch_bounds__(256) void gemm_c32_3m_kernel(LuGroups G, int rowC, 
     }
 }
 
+// ============================================================== GEMM f32 via bf16 split
+// The same 4M update with every real product taken as three bfloat16 MFMA
+// products: each float32 operand x is split into hi = bf16(x) and
+// lo = bf16(x - hi), and x y ~ hi_x hi_y + hi_x lo_y + lo_x hi_y (the dropped
+// lo_x lo_y and the rounding of lo leave about 16 significant bits per
+// product), accumulated in float32 by MFMA 32x32x16 bf16.  The split is done
+// while staging the tiles in LDS.  128 x 128 tile per workgroup of 4 waves,
+// each 64 x 64 as 2 x 2 MFMA blocks; 8 complex k per LDS stage (two k groups
+// of 8 interleaved real k).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+union Pack8 {
+  uint4 u;
+  bf16x8 v;
+  __bf16 e[8];
+};
+
+__device__ inline void split8(const float* x, uint4& hi, uint4& lo) {
+  Pack8 h, l;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 bh = (__bf16)x[e];
+    h.e[e] = bh;
+    l.e[e] = (__bf16)(x[e] - (float)bh);
+  }
+  hi = h.u;
+  lo = l.u;
+}
+
+constexpr int GB_BM = 128, GB_BN = 128, GB_KB = 8;
+
+__global__ __launch_bounds__(256, 2) void gemm_c32_b3_kernel(LuGroups G, int rowC, int colC,
+                                                             int colA, int rowB, int rowEnd,
+                                                             int colEnd, int K, int tiles_n) {
+  // LDS stage: A hi/lo [k group][row], B hi/lo of the real-part pattern
+  // (Re B, -Im B) and of the imaginary-part pattern (Im B, Re B) [k group][col]
+  __shared__ uint4 Ah[2][2][GB_BM], Al[2][2][GB_BM];
+  __shared__ uint4 Brh[2][2][GB_BN], Brl[2][2][GB_BN], Bih[2][2][GB_BN], Bil[2][2][GB_BN];
+  GemmView<float2> gv;
+  if (!gemm_view(G, rowC, colC, colA, rowB, rowEnd, colEnd, gv)) return;
+  const int tile = blockIdx.x;
+  const int tm = tile / tiles_n, tn = tile % tiles_n;
+  const int m0 = tm * GB_BM, n0 = tn * GB_BN;
+  const int M = gv.M, N = gv.N;
+  if (m0 >= M || n0 >= N) return;
+  const int ld = (int)gv.ld;   // n * ld < 2^31 is checked on the host
+  const GLOBAL float2* A = gv.A;
+  const GLOBAL float2* B = gv.B;
+  GLOBAL float2* C = gv.Cm;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  const int h = lane >> 5, l32 = lane & 31;
+  floatx16 acc_re[2][2], acc_im[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) { acc_re[i][j][v] = 0.f; acc_im[i][j][v] = 0.f; }
+
+  // staging: thread -> A (row ar, k group akg) and B (col bc, k group bkg), 4 complex each
+  const int ar = tid >> 1, akg = tid & 1, bc = tid & 127, bkg = tid >> 7;
+  const bool arow_ok = m0 + ar < M, bcol_ok = n0 + bc < N;
+  const GLOBAL float2* Ap = A + min(m0 + ar, M - 1) * ld;
+  const GLOBAL float2* Bp = B + min(n0 + bc, N - 1);
+  float2 ra[4], rb[4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int gk = k0 + 4 * akg + q;
+      const float2 va = Ap[min(gk, K - 1)];
+      ra[q] = (arow_ok && gk < K) ? va : make_float2(0.f, 0.f);
+      const int gbk = k0 + 4 * bkg + q;
+      const float2 vb = Bp[min(gbk, K - 1) * ld];
+      rb[q] = (bcol_ok && gbk < K) ? vb : make_float2(0.f, 0.f);
+    }
+  };
+  auto sstore = [&](int buf) {
+    float xa[8], xr[8], xi[8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      xa[2 * q] = ra[q].x;
+      xa[2 * q + 1] = ra[q].y;
+      xr[2 * q] = rb[q].x;
+      xr[2 * q + 1] = -rb[q].y;
+      xi[2 * q] = rb[q].y;
+      xi[2 * q + 1] = rb[q].x;
+    }
+    uint4 hi, lo;
+    split8(xa, hi, lo);
+    Ah[buf][akg][ar] = hi;
+    Al[buf][akg][ar] = lo;
+    split8(xr, hi, lo);
+    Brh[buf][bkg][bc] = hi;
+    Brl[buf][bkg][bc] = lo;
+    split8(xi, hi, lo);
+    Bih[buf][bkg][bc] = hi;
+    Bil[buf][bkg][bc] = lo;
+  };
+
+  const int nk = (K + GB_KB - 1) / GB_KB;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * GB_KB);
+    // lanes 0-31 take k group 0, lanes 32-63 k group 1 (8 real k each)
+    Pack8 ah[2], al[2], brh[2], brl[2], bih[2], bil[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      ah[i].u = Ah[cur][h][wm * 64 + i * 32 + l32];
+      al[i].u = Al[cur][h][wm * 64 + i * 32 + l32];
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      brh[j].u = Brh[cur][h][wn * 64 + j * 32 + l32];
+      brl[j].u = Brl[cur][h][wn * 64 + j * 32 + l32];
+      bih[j].u = Bih[cur][h][wn * 64 + j * 32 + l32];
+      bil[j].u = Bil[cur][h][wn * 64 + j * 32 + l32];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        acc_re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i].v, brh[j].v, acc_re[i][j], 0, 0, 0);
+        acc_re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i].v, brl[j].v, acc_re[i][j], 0, 0, 0);
+        acc_re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i].v, brh[j].v, acc_re[i][j], 0, 0, 0);
+        acc_im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i].v, bih[j].v, acc_im[i][j], 0, 0, 0);
+        acc_im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i].v, bil[j].v, acc_im[i][j], 0, 0, 0);
+        acc_im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i].v, bih[j].v, acc_im[i][j], 0, 0, 0);
+      }
+    if (kt + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn * 64 + j * 32 + l32;
+      if (col >= N) continue;
+      float2 c[16];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        c[v] = C[min(row, M - 1) * ld + col];
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        if (row < M) C[row * ld + col] = make_float2(c[v].x - acc_re[i][j][v], c[v].y - acc_im[i][j][v]);
+      }
+    }
+}
+
 // ============================================================== GEMM f64
 // Same contraction in float64 on MFMA 16x16x4 f64: one MFMA covers two
 // complex k (four interleaved real k).  64 x 64 tile, 4 waves of 32 x 32.
@@ -904,7 +1059,7 @@ struct Fac {
   std::vector<LuGroup> groups;   // sorted by n, descending
   LuPlan plan;
   int base = 8;
-  int g3m = 0;                   // 3-product complex GEMM for c64
+  int gkind = kGemm4M;           // complex GEMM form for c64 (bem_gemm_kind)
   int nmax = 0;
 
   size_t esz() const { return prec == BEM_C128 ? 16 : 8; }
@@ -1002,7 +1157,9 @@ struct Fac {
     if (total == 0) return;
     const int M = std::min(rowEnd, maxn) - rowC, N = std::min(colEnd, maxn) - colC;
     if (M <= 0 || N <= 0) return;
-    const char* kname = prec == BEM_C128 ? "gemm_c64" : "gemm_c32";
+    const char* kname = prec == BEM_C128 ? "gemm_c64"
+                        : gkind == kGemmBf16x3 ? "gemm_b3"
+                        : gkind == kGemm3M ? "gemm_3m" : "gemm_c32";
     const int pi = prof_begin(ctx, kname);
     if (prec == BEM_C128) {
       const int tn = (N + G64_BN - 1) / G64_BN, tm = (M + G64_BM - 1) / G64_BM;
@@ -1010,7 +1167,10 @@ struct Fac {
                          colC, colA, rowB, rowEnd, colEnd, K, tn);
     } else {
       const int tn = (N + G32_BN - 1) / G32_BN, tm = (M + G32_BM - 1) / G32_BM;
-      if (g3m)
+      if (gkind == kGemmBf16x3)
+        hipLaunchKernelGGL(gemm_c32_b3_kernel, dim3(tm * tn, total), dim3(256), 0, ctx->stream, G,
+                           rowC, colC, colA, rowB, rowEnd, colEnd, K, tn);
+      else if (gkind == kGemm3M)
         hipLaunchKernelGGL(gemm_c32_3m_kernel, dim3(tm * tn, total), dim3(256), 0, ctx->stream, G,
                            rowC, colC, colA, rowB, rowEnd, colEnd, K, tn);
       else
@@ -1093,17 +1253,20 @@ int lu_default_nb(bem_prec prec, int n) {
 }
 
 bem_status lu_factor_groups(bem_ctx* ctx, bem_prec prec, const std::vector<LuMatrixSet>& sets,
-                            const LuPlan& plan, int gemm_3m) {
+                            const LuPlan& plan, int gemm_kind) {
   Fac f;
   f.ctx = ctx;
   f.prec = prec;
   f.plan = plan;
-  f.g3m = (gemm_3m && prec == BEM_C64) ? 1 : 0;
+  f.gkind = prec == BEM_C64 ? gemm_kind : kGemm4M;
   for (const LuMatrixSet& s : sets) {
     if (s.count <= 0 || s.n <= 0) continue;
     if (s.n > 24 * kPanelThreads)
       return fail(ctx, BEM_EUNSUPPORTED, "lu_factor: n=%d above the supported %d", s.n,
                   24 * kPanelThreads);
+    if ((int64_t)s.n * s.ld >= ((int64_t)1 << 31))
+      return fail(ctx, BEM_EUNSUPPORTED, "lu_factor: n*ld = %lld must stay below 2^31",
+                  (long long)s.n * s.ld);
     LuGroup g{};
     g.A = s.A;
     g.piv = s.piv;
@@ -1133,11 +1296,11 @@ bem_status lu_factor_groups(bem_ctx* ctx, bem_prec prec, const std::vector<LuMat
 }
 
 bem_status lu_factor(bem_ctx* ctx, bem_prec prec, int n, int64_t ld, int64_t stride, int batch,
-                     void* A, int32_t* piv, int32_t* info, const LuPlan& plan, int gemm_3m) {
+                     void* A, int32_t* piv, int32_t* info, const LuPlan& plan, int gemm_kind) {
   if (batch <= 0 || n <= 0) return BEM_OK;
   std::vector<LuMatrixSet> sets(1);
   sets[0] = LuMatrixSet{A, piv, info, ld, stride, n, batch};
-  return lu_factor_groups(ctx, prec, sets, plan, gemm_3m);
+  return lu_factor_groups(ctx, prec, sets, plan, gemm_kind);
 }
 
 bem_status lu_perm(bem_ctx* ctx, int n, int batch, const int32_t* piv, int32_t* perm) {

@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(HERE, "libbem.so")
 BEM_OK, BEM_EINVAL, BEM_ENOMEM, BEM_EHIP, BEM_ESINGULAR, BEM_ENOCONV, BEM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 BEM_C64, BEM_C128 = 0, 1
 BEM_BC_HARD, BEM_BC_SOFT = 0, 1
-BEM_FP64_DIRECT, BEM_FP32_IR_4M, BEM_FP32_IR_3M = 0, 1, 2
+BEM_FP64_DIRECT, BEM_FP32_IR_4M, BEM_FP32_IR_3M, BEM_FP32_IR_B3 = 0, 1, 2, 3
+BEM_GEMM_4M, BEM_GEMM_3M, BEM_GEMM_BF16X3 = 0, 1, 2
 PULSE_KINDS = {"paper": 0, "gauss": 1, "ricker": 2, "nwave": 3, "chirp": 4, "gsine": 5, "gaussk": 6}
 
 EXPORTED = [
@@ -238,9 +239,9 @@ def bem_solve_batched(ctx, problems, opts, x_out, want_info=True):
     return info
 
 
-def bem_getrf_batched(ctx, prec, n, ld, stride, batch, A, piv, info, nb=0, use_3m=0):
+def bem_getrf_batched(ctx, prec, n, ld, stride, batch, A, piv, info, nb=0, gemm_kind=0):
     _check(load().bem_getrf_batched(ctx.handle, prec, n, ld, stride, batch, _ptr(A), _ptr(piv),
-                                    _ptr(info), nb, use_3m), ctx)
+                                    _ptr(info), nb, gemm_kind), ctx)
 
 
 def bem_getrs_batched(ctx, prec, n, ld, stride, batch, LU, piv, n_rhs, B, X, bstride):
