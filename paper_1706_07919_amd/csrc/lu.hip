@@ -657,43 +657,73 @@ __global__ __launch_bounds__(256) void gemm_c32_3m_kernel(LuGroups G, int rowC, 
 // The same 4M update with every real product taken as three bfloat16 MFMA
 // products: each float32 operand x is split into hi = bf16(x) and
 // lo = bf16(x - hi), and x y ~ hi_x hi_y + hi_x lo_y + lo_x hi_y (the dropped
-// lo_x lo_y and the rounding of lo leave about 16 significant bits per
-// product), accumulated in float32 by MFMA 32x32x16 bf16.  The split is done
-// while staging the tiles in LDS.  128 x 128 tile per workgroup of 4 waves,
-// each 64 x 64 as 2 x 2 MFMA blocks; 8 complex k per LDS stage (two k groups
-// of 8 interleaved real k).
+// lo_x lo_y and the rounding of lo leave about 17 significant bits per
+// operand), accumulated in float32 by MFMA 32x32x16 bf16.
+//
+// 128 x 128 tile per workgroup of 4 waves, each 64 x 64 as 2 x 2 MFMA blocks;
+// 16 complex k per LDS stage (four k groups of 8 interleaved real k), double
+// buffered.  The split is done while staging: A as hi/lo of (Re A, Im A)
+// pairs, B as hi/lo of the real-part pattern (Re B, -Im B); the
+// imaginary-part pattern (Im B, Re B) is derived from it in registers (swap
+// the halves of each 32-bit pair, flip one sign bit).  Bounds are applied as
+// masks at staging time, so the global loads of the next stage stay in flight
+// across the MFMA loop.
+//
+// Tile order: the grid is padded to a multiple of 8 so that workgroup x runs
+// on XCD x % 8; each XCD takes a contiguous range of tiles walked in groups of
+// GB_GM tile rows, so the workgroups resident on one XCD share A and B panels
+// in that XCD's L2.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
 union Pack8 {
   uint4 u;
   bf16x8 v;
-  __bf16 e[8];
 };
 
 __device__ inline void split8(const float* x, uint4& hi, uint4& lo) {
-  Pack8 h, l;
+  unsigned hw[4], lw[4];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const __bf16 bh = (__bf16)x[e];
-    h.e[e] = bh;
-    l.e[e] = (__bf16)(x[e] - (float)bh);
+  for (int p = 0; p < 4; ++p) {
+    const f2v v = {x[2 * p], x[2 * p + 1]};
+    const unsigned hu = __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf2v));
+    const f2v r = {x[2 * p] - __uint_as_float(hu << 16), x[2 * p + 1] - __uint_as_float(hu & 0xffff0000u)};
+    hw[p] = hu;
+    lw[p] = __builtin_bit_cast(unsigned, __builtin_convertvector(r, bf2v));
   }
-  hi = h.u;
-  lo = l.u;
+  hi = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+  lo = make_uint4(lw[0], lw[1], lw[2], lw[3]);
 }
 
-constexpr int GB_BM = 128, GB_BN = 128, GB_KB = 8;
+// (a, b) pairs of the real-part pattern -> (-b, a) of the imaginary-part pattern
+__device__ inline uint4 re_to_im(uint4 r) {
+  uint4 o;
+  o.x = ((r.x >> 16) | (r.x << 16)) ^ 0x8000u;
+  o.y = ((r.y >> 16) | (r.y << 16)) ^ 0x8000u;
+  o.z = ((r.z >> 16) | (r.z << 16)) ^ 0x8000u;
+  o.w = ((r.w >> 16) | (r.w << 16)) ^ 0x8000u;
+  return o;
+}
+
+constexpr int GB_BM = 128, GB_BN = 128, GB_KB = 16, GB_KG = GB_KB / 4, GB_GM = 8;
 
 __global__ __launch_bounds__(256, 2) void gemm_c32_b3_kernel(LuGroups G, int rowC, int colC,
                                                              int colA, int rowB, int rowEnd,
-                                                             int colEnd, int K, int tiles_n) {
-  // LDS stage: A hi/lo [k group][row], B hi/lo of the real-part pattern
-  // (Re B, -Im B) and of the imaginary-part pattern (Im B, Re B) [k group][col]
-  __shared__ uint4 Ah[2][2][GB_BM], Al[2][2][GB_BM];
-  __shared__ uint4 Brh[2][2][GB_BN], Brl[2][2][GB_BN], Bih[2][2][GB_BN], Bil[2][2][GB_BN];
+                                                             int colEnd, int K, int tiles_m,
+                                                             int tiles_n) {
+  __shared__ uint4 Ah[2][GB_KG][GB_BM], Al[2][GB_KG][GB_BM];
+  __shared__ uint4 Brh[2][GB_KG][GB_BN], Brl[2][GB_KG][GB_BN];
+  // XCD-aware grouped tile order (launch-level tile counts; tiles outside a
+  // smaller matrix exit below)
+  const int per = gridDim.x / 8;
+  const int t = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (t >= tiles_m * tiles_n) return;
+  const int grp = t / (GB_GM * tiles_n), first = grp * GB_GM;
+  const int gsz = min(tiles_m - first, GB_GM);
+  const int tm = first + (t % (GB_GM * tiles_n)) % gsz;
+  const int tn = (t % (GB_GM * tiles_n)) / gsz;
   GemmView<float2> gv;
   if (!gemm_view(G, rowC, colC, colA, rowB, rowEnd, colEnd, gv)) return;
-  const int tile = blockIdx.x;
-  const int tm = tile / tiles_n, tn = tile % tiles_n;
   const int m0 = tm * GB_BM, n0 = tn * GB_BN;
   const int M = gv.M, N = gv.N;
   if (m0 >= M || n0 >= N) return;
@@ -713,79 +743,88 @@ __global__ __launch_bounds__(256, 2) void gemm_c32_b3_kernel(LuGroups G, int row
 #pragma unroll
       for (int v = 0; v < 16; ++v) { acc_re[i][j][v] = 0.f; acc_im[i][j][v] = 0.f; }
 
-  // staging: thread -> A (row ar, k group akg) and B (col bc, k group bkg), 4 complex each
-  const int ar = tid >> 1, akg = tid & 1, bc = tid & 127, bkg = tid >> 7;
-  const bool arow_ok = m0 + ar < M, bcol_ok = n0 + bc < N;
-  const GLOBAL float2* Ap = A + min(m0 + ar, M - 1) * ld;
-  const GLOBAL float2* Bp = B + min(n0 + bc, N - 1);
-  float2 ra[4], rb[4];
+  // staging: chunk e = tid + 256 c; A chunk = (row e / 4, k group e % 4),
+  // B chunk = (col e % 128, k group e / 128); 4 complex each
+  constexpr int NC = GB_BM * GB_KG / 256;
+  float2 ra[NC][4], rb[NC][4];
   auto gload = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int gk = k0 + 4 * akg + q;
-      const float2 va = Ap[min(gk, K - 1)];
-      ra[q] = (arow_ok && gk < K) ? va : make_float2(0.f, 0.f);
-      const int gbk = k0 + 4 * bkg + q;
-      const float2 vb = Bp[min(gbk, K - 1) * ld];
-      rb[q] = (bcol_ok && gbk < K) ? vb : make_float2(0.f, 0.f);
+    for (int c = 0; c < NC; ++c) {
+      const int e = tid + 256 * c;
+      const int row = e / GB_KG, akg = e % GB_KG;
+      const GLOBAL float2* Ap = A + min(m0 + row, M - 1) * ld;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) ra[c][q] = Ap[min(k0 + 4 * akg + q, K - 1)];
+      const int col = e % GB_BN, bkg = e / GB_BN;
+      const GLOBAL float2* Bp = B + min(n0 + col, N - 1);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) rb[c][q] = Bp[min(k0 + 4 * bkg + q, K - 1) * ld];
     }
   };
-  auto sstore = [&](int buf) {
-    float xa[8], xr[8], xi[8];
+  auto sstore = [&](int buf, int k0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      xa[2 * q] = ra[q].x;
-      xa[2 * q + 1] = ra[q].y;
-      xr[2 * q] = rb[q].x;
-      xr[2 * q + 1] = -rb[q].y;
-      xi[2 * q] = rb[q].y;
-      xi[2 * q + 1] = rb[q].x;
+    for (int c = 0; c < NC; ++c) {
+      const int e = tid + 256 * c;
+      const int row = e / GB_KG, akg = e % GB_KG;
+      const int col = e % GB_BN, bkg = e / GB_BN;
+      const bool rok = m0 + row < M, cok = n0 + col < N;
+      float xa[8], xr[8];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const unsigned ma = (rok && k0 + 4 * akg + q < K) ? 0xffffffffu : 0u;
+        xa[2 * q] = __uint_as_float(__float_as_uint(ra[c][q].x) & ma);
+        xa[2 * q + 1] = __uint_as_float(__float_as_uint(ra[c][q].y) & ma);
+        const unsigned mb = (cok && k0 + 4 * bkg + q < K) ? 0xffffffffu : 0u;
+        xr[2 * q] = __uint_as_float(__float_as_uint(rb[c][q].x) & mb);
+        xr[2 * q + 1] = __uint_as_float(__float_as_uint(-rb[c][q].y) & mb);
+      }
+      uint4 hi, lo;
+      split8(xa, hi, lo);
+      Ah[buf][akg][row] = hi;
+      Al[buf][akg][row] = lo;
+      split8(xr, hi, lo);
+      Brh[buf][bkg][col] = hi;
+      Brl[buf][bkg][col] = lo;
     }
-    uint4 hi, lo;
-    split8(xa, hi, lo);
-    Ah[buf][akg][ar] = hi;
-    Al[buf][akg][ar] = lo;
-    split8(xr, hi, lo);
-    Brh[buf][bkg][bc] = hi;
-    Brl[buf][bkg][bc] = lo;
-    split8(xi, hi, lo);
-    Bih[buf][bkg][bc] = hi;
-    Bil[buf][bkg][bc] = lo;
   };
 
   const int nk = (K + GB_KB - 1) / GB_KB;
   gload(0);
-  sstore(0);
+  sstore(0, 0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < nk) gload((kt + 1) * GB_KB);
-    // lanes 0-31 take k group 0, lanes 32-63 k group 1 (8 real k each)
-    Pack8 ah[2], al[2], brh[2], brl[2], bih[2], bil[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      ah[i].u = Ah[cur][h][wm * 64 + i * 32 + l32];
-      al[i].u = Al[cur][h][wm * 64 + i * 32 + l32];
-    }
+    for (int s2 = 0; s2 < GB_KG / 2; ++s2) {
+      // lanes 0-31 take k group 2 s2, lanes 32-63 k group 2 s2 + 1
+      const int g = 2 * s2 + h;
+      Pack8 ah[2], al[2], brh[2], brl[2], bih[2], bil[2];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      brh[j].u = Brh[cur][h][wn * 64 + j * 32 + l32];
-      brl[j].u = Brl[cur][h][wn * 64 + j * 32 + l32];
-      bih[j].u = Bih[cur][h][wn * 64 + j * 32 + l32];
-      bil[j].u = Bil[cur][h][wn * 64 + j * 32 + l32];
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 2; ++i) {
+        ah[i].u = Ah[cur][g][wm * 64 + i * 32 + l32];
+        al[i].u = Al[cur][g][wm * 64 + i * 32 + l32];
+      }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        acc_re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i].v, brh[j].v, acc_re[i][j], 0, 0, 0);
-        acc_re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i].v, brl[j].v, acc_re[i][j], 0, 0, 0);
-        acc_re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i].v, brh[j].v, acc_re[i][j], 0, 0, 0);
-        acc_im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i].v, bih[j].v, acc_im[i][j], 0, 0, 0);
-        acc_im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i].v, bil[j].v, acc_im[i][j], 0, 0, 0);
-        acc_im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i].v, bih[j].v, acc_im[i][j], 0, 0, 0);
+        brh[j].u = Brh[cur][g][wn * 64 + j * 32 + l32];
+        brl[j].u = Brl[cur][g][wn * 64 + j * 32 + l32];
+        bih[j].u = re_to_im(brh[j].u);
+        bil[j].u = re_to_im(brl[j].u);
       }
-    if (kt + 1 < nk) sstore(cur ^ 1);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i].v, brh[j].v, acc_re[i][j], 0, 0, 0);
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i].v, brl[j].v, acc_re[i][j], 0, 0, 0);
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i].v, brh[j].v, acc_re[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i].v, bih[j].v, acc_im[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i].v, bil[j].v, acc_im[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i].v, bih[j].v, acc_im[i][j], 0, 0, 0);
+        }
+    }
+    if (kt + 1 < nk) sstore(cur ^ 1, (kt + 1) * GB_KB);
     __syncthreads();
   }
 #pragma unroll
@@ -1167,9 +1206,12 @@ struct Fac {
                          colC, colA, rowB, rowEnd, colEnd, K, tn);
     } else {
       const int tn = (N + G32_BN - 1) / G32_BN, tm = (M + G32_BM - 1) / G32_BM;
-      if (gkind == kGemmBf16x3)
-        hipLaunchKernelGGL(gemm_c32_b3_kernel, dim3(tm * tn, total), dim3(256), 0, ctx->stream, G,
-                           rowC, colC, colA, rowB, rowEnd, colEnd, K, tn);
+      if (gkind == kGemmBf16x3) {
+        const int tmb = (M + GB_BM - 1) / GB_BM, tnb = (N + GB_BN - 1) / GB_BN;
+        const int gx = (tmb * tnb + 7) / 8 * 8;
+        hipLaunchKernelGGL(gemm_c32_b3_kernel, dim3(gx, total), dim3(256), 0, ctx->stream, G,
+                           rowC, colC, colA, rowB, rowEnd, colEnd, K, tmb, tnb);
+      }
       else if (gkind == kGemm3M)
         hipLaunchKernelGGL(gemm_c32_3m_kernel, dim3(tm * tn, total), dim3(256), 0, ctx->stream, G,
                            rowC, colC, colA, rowB, rowEnd, colEnd, K, tn);
