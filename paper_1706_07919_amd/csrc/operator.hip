@@ -6,15 +6,15 @@
 //   g = cos s, f = sin(s)/k, g' = -k sin(s) (n_i.n_j), f' = cos(s) (n_i.n_j)
 //   (M_phi)_ij = -w_j H,  (M_psi)_ij = w_j G,
 //   (M_phi)_ii = 4 pi - sum_j w_j (g' G - g H),  (M_psi)_ii = -sum_j w_j (f' G - f H).
-// One workgroup owns one (wavenumber, row) pair and sweeps j with coalesced
-// loads of the node arrays and coalesced stores of the row-major matrix row.
+// One workgroup owns one row and a chunk of wavenumbers and sweeps j with
+// coalesced loads of the node arrays and coalesced stores of the row-major
+// matrix rows.
 #include "common.h"
 
 namespace bem {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kRhsChunk = 4;
 constexpr double kFourPi = 12.566370614359172953850573533118;
 
 __device__ inline double2 cmul(double2 a, double2 b) {
@@ -27,179 +27,249 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// Block-wide sum of `cnt` doubles held per thread; result valid in thread 0.
-template <int CNT>
-__device__ inline void block_sum(double (&v)[CNT]) {
-  __shared__ double red[kThreads / 64][CNT];
+// Block-wide sum of a [R][C] array held per thread; result valid in thread 0.
+template <int R, int C>
+__device__ inline void block_sum_2d(double (&v)[R][C]) {
+  __shared__ double red[kThreads / 64][R][C];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-  for (int c = 0; c < CNT; ++c) v[c] = wave_sum(v[c]);
+  for (int a = 0; a < R; ++a)
+#pragma unroll
+    for (int c = 0; c < C; ++c) v[a][c] = wave_sum(v[a][c]);
   if (lane == 0)
 #pragma unroll
-    for (int c = 0; c < CNT; ++c) red[wid][c] = v[c];
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+      for (int c = 0; c < C; ++c) red[wid][a][c] = v[a][c];
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int c = 0; c < CNT; ++c) {
-      double s = 0.0;
-      for (int q = 0; q < kThreads / 64; ++q) s += red[q][c];
-      v[c] = s;
-    }
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        double t = 0.0;
+        for (int q = 0; q < kThreads / 64; ++q) t += red[q][a][c];
+        v[a][c] = t;
+      }
   }
 }
 
-struct PairGH {
-  double2 G, H;
+// ---------------------------------------------------------------- wavenumber chunks
+// A workgroup owns one row i and a chunk of consecutive
+// wavenumbers.  The pair geometry (d, r, 1/r, d.n_j, n_i.d, n_i.n_j) is formed
+// once per pair and shared by the chunk.  When the chunk's wavenumbers are
+// evenly spaced (k_q = k_0 + q dk to a few ulp, the uniform grids of the
+// frequency sweep), the phases are advanced by multiplication:
+// e^{i k_q r} = e^{i k_0 r} (e^{i dk r})^q, and likewise e^{i k_q n_i.d}, so a
+// chunk costs two sincos per pair and phase instead of one per wavenumber; otherwise each
+// wavenumber takes its own sincos.  The recurrence adds about one rounding
+// per step (relative error below 1e-15 over a chunk).
+constexpr int kKcResidual = 8;   // wavenumbers per workgroup, residual
+constexpr int kKcAssemble = 4;   // wavenumbers per workgroup, assembly (more accumulators)
+
+template <int KC>
+struct KChunk {
+  double k[KC];
+  double dk;
+  int kc;
+  bool uniform;
 };
 
-// G, H of the pair (i -> j) and the in-plane quantities used by f, g.
-__device__ inline PairGH pair_gh(double k, double dx, double dy, double dz, double njx,
-                                 double njy, double njz, double& r) {
-  const double r2 = dx * dx + dy * dy + dz * dz;
-  r = sqrt(r2);
-  const double rinv = 1.0 / r;
-  double sn, cs;
-  sincos(k * r, &sn, &cs);
-  PairGH o;
-  o.G = make_double2(cs * rinv, sn * rinv);
-  const double q = (dx * njx + dy * njy + dz * njz) * (rinv * rinv * rinv);
-  const double kr = k * r;
-  // E (ikr - 1) q
-  o.H = make_double2(q * (-cs - kr * sn), q * (kr * cs - sn));
-  return o;
+template <int KC>
+__device__ inline KChunk<KC> load_chunk(const double* __restrict__ kv, int nk) {
+  KChunk<KC> c;
+  const int q0 = blockIdx.y * KC;
+  c.kc = min(KC, nk - q0);
+#pragma unroll
+  for (int q = 0; q < KC; ++q) c.k[q] = q < c.kc ? kv[q0 + q] : 0.0;
+  c.uniform = c.kc > 1;
+  c.dk = c.kc > 1 ? (c.k[c.kc - 1] - c.k[0]) / (c.kc - 1) : 0.0;
+#pragma unroll
+  for (int q = 1; q < KC; ++q)
+    if (q < c.kc && !(fabs(c.k[q] - (c.k[0] + q * c.dk)) <= 4e-16 * fabs(c.k[q]))) c.uniform = false;
+  return c;
 }
 
+// Phase e^{i k_q t} stepped along the chunk: start() gives q = 0, next(q)
+// advances to wavenumber q (by the recurrence, or a fresh sincos).
+struct Phase {
+  double2 e, d;
+  template <int KC>
+  __device__ inline void start(const KChunk<KC>& c, double t) {
+    double s, co;
+    sincos(c.k[0] * t, &s, &co);
+    e = make_double2(co, s);
+    if (c.uniform) {
+      sincos(c.dk * t, &s, &co);
+      d = make_double2(co, s);
+    }
+  }
+  template <int KC>
+  __device__ inline void next(const KChunk<KC>& c, int q, double t) {
+    if (c.uniform) {
+      e = make_double2(e.x * d.x - e.y * d.y, e.x * d.y + e.y * d.x);
+    } else {
+      double s, co;
+      sincos(c.k[q] * t, &s, &co);
+      e = make_double2(co, s);
+    }
+  }
+};
+
+// Assembly for one row and a chunk of wavenumbers, one right-hand side
+// (column rhs of y).  WRITE_A: write the matrix row and the diagonal
+// (first pass); later passes only form b for further right-hand sides.
 template <bool OUT128, bool WRITE_A>
-__global__ __launch_bounds__(kThreads) void assemble_kernel(
+__global__ __launch_bounds__(kThreads) void assemble_kc_kernel(
     int n, const double* __restrict__ x, const double* __restrict__ nrm,
     const double* __restrict__ w, const uint8_t* __restrict__ bc, const double* __restrict__ kv,
-    int n_rhs, int rhs0, const double2* __restrict__ y, void* __restrict__ A, int64_t ld,
+    int nk, int n_rhs, int rhs, const double2* __restrict__ y, void* __restrict__ A, int64_t ld,
     int64_t a_stride, double2* __restrict__ b, double2* __restrict__ diag64) {
   const int i = blockIdx.x;
-  const int kq = blockIdx.y;
-  const double k = kv[kq];
+  const KChunk<kKcAssemble> kc = load_chunk<kKcAssemble>(kv, nk);
+  const int q0 = blockIdx.y * kKcAssemble;
   const double xi = x[3 * i], yi = x[3 * i + 1], zi = x[3 * i + 2];
   const double nix = nrm[3 * i], niy = nrm[3 * i + 1], niz = nrm[3 * i + 2];
-  const int nr = min(kRhsChunk, n_rhs - rhs0);
-  const double2* yk = y + (int64_t)kq * n_rhs * n;
-
-  // acc: Dphi(re,im), Dpsi(re,im), then b partial sums (re,im) per rhs
-  double acc[4 + 2 * kRhsChunk];
+  // per wavenumber: Dphi (re, im), Dpsi (re, im), b (re, im)
+  double acc[kKcAssemble][6];
 #pragma unroll
-  for (int c = 0; c < 4 + 2 * kRhsChunk; ++c) acc[c] = 0.0;
-
-  float2* A32 = reinterpret_cast<float2*>(A) + (int64_t)kq * a_stride + (int64_t)i * ld;
-  double2* A64 = reinterpret_cast<double2*>(A) + (int64_t)kq * a_stride + (int64_t)i * ld;
-  const double kinv = 1.0 / k;
-
+  for (int q = 0; q < kKcAssemble; ++q)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[q][c] = 0.0;
   for (int j = threadIdx.x; j < n; j += kThreads) {
     if (j == i) continue;
     const double dx = x[3 * j] - xi, dy = x[3 * j + 1] - yi, dz = x[3 * j + 2] - zi;
     const double njx = nrm[3 * j], njy = nrm[3 * j + 1], njz = nrm[3 * j + 2];
-    double r;
-    const PairGH p = pair_gh(k, dx, dy, dz, njx, njy, njz, r);
-    double ss, cs;
-    sincos(k * (nix * dx + niy * dy + niz * dz), &ss, &cs);
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    const double rinv = 1.0 / r;
+    const double qn = (dx * njx + dy * njy + dz * njz) * (rinv * rinv * rinv);
+    const double s0 = nix * dx + niy * dy + niz * dz;
     const double nn = nix * njx + niy * njy + niz * njz;
-    const double g = cs, f = ss * kinv, gp = -k * ss * nn, fp = cs * nn;
     const double wj = w[j];
-    acc[0] += wj * (gp * p.G.x - g * p.H.x);
-    acc[1] += wj * (gp * p.G.y - g * p.H.y);
-    acc[2] += wj * (fp * p.G.x - f * p.H.x);
-    acc[3] += wj * (fp * p.G.y - f * p.H.y);
     const bool hard = bc[j] == BEM_BC_HARD;
-    const double2 mphi = make_double2(-wj * p.H.x, -wj * p.H.y);
-    const double2 mpsi = make_double2(wj * p.G.x, wj * p.G.y);
-    const double2 a = hard ? mphi : mpsi;
-    const double2 bb = hard ? mpsi : mphi;
-    if (WRITE_A && A) {
-      if (OUT128)
-        A64[j] = a;
-      else
-        A32[j] = make_float2((float)a.x, (float)a.y);
-    }
+    Phase E, F;
+    E.start(kc, r);
+    F.start(kc, s0);
 #pragma unroll
-    for (int q = 0; q < kRhsChunk; ++q) {
-      if (q < nr) {
-        const double2 yy = yk[(int64_t)(rhs0 + q) * n + j];
-        acc[4 + 2 * q] += bb.x * yy.x - bb.y * yy.y;
-        acc[5 + 2 * q] += bb.x * yy.y + bb.y * yy.x;
+    for (int q = 0; q < kKcAssemble; ++q) {
+      if (q < kc.kc) {
+        if (q > 0) {
+          E.next(kc, q, r);
+          F.next(kc, q, s0);
+        }
+        const double k = kc.k[q], kr = k * r;
+        const double2 G = make_double2(E.e.x * rinv, E.e.y * rinv);
+        // H = E (ikr - 1) (d.n_j) / r^3
+        const double2 H = make_double2(qn * (-E.e.x - kr * E.e.y), qn * (kr * E.e.x - E.e.y));
+        // g = cos(k s0), f = sin(k s0)/k, g' = -k sin(k s0) nn, f' = cos(k s0) nn
+        const double g = F.e.x, f = F.e.y / k, gp = -k * F.e.y * nn, fp = F.e.x * nn;
+        acc[q][0] += wj * (gp * G.x - g * H.x);
+        acc[q][1] += wj * (gp * G.y - g * H.y);
+        acc[q][2] += wj * (fp * G.x - f * H.x);
+        acc[q][3] += wj * (fp * G.y - f * H.y);
+        const double2 mphi = make_double2(-wj * H.x, -wj * H.y);
+        const double2 mpsi = make_double2(wj * G.x, wj * G.y);
+        const double2 a = hard ? mphi : mpsi;
+        const double2 bb = hard ? mpsi : mphi;
+        const int64_t kq = q0 + q;
+        if (WRITE_A && A) {
+          if (OUT128)
+            reinterpret_cast<double2*>(A)[kq * a_stride + (int64_t)i * ld + j] = a;
+          else
+            reinterpret_cast<float2*>(A)[kq * a_stride + (int64_t)i * ld + j] =
+                make_float2((float)a.x, (float)a.y);
+        }
+        const double2 yy = y[(kq * n_rhs + rhs) * n + j];
+        acc[q][4] += bb.x * yy.x - bb.y * yy.y;
+        acc[q][5] += bb.x * yy.y + bb.y * yy.x;
       }
     }
   }
-  block_sum(acc);
+  block_sum_2d(acc);
   if (threadIdx.x == 0) {
-    const double2 mphi = make_double2(kFourPi - acc[0], -acc[1]);
-    const double2 mpsi = make_double2(-acc[2], -acc[3]);
     const bool hard = bc[i] == BEM_BC_HARD;
-    const double2 a = hard ? mphi : mpsi;
-    const double2 bb = hard ? mpsi : mphi;
-    if (WRITE_A) {
-      if (A) {
-        if (OUT128)
-          A64[i] = a;
-        else
-          A32[i] = make_float2((float)a.x, (float)a.y);
+#pragma unroll
+    for (int q = 0; q < kKcAssemble; ++q) {
+      if (q >= kc.kc) break;
+      const int64_t kq = q0 + q;
+      const double2 mphi = make_double2(kFourPi - acc[q][0], -acc[q][1]);
+      const double2 mpsi = make_double2(-acc[q][2], -acc[q][3]);
+      const double2 a = hard ? mphi : mpsi;
+      const double2 bb = hard ? mpsi : mphi;
+      if (WRITE_A) {
+        if (A) {
+          if (OUT128)
+            reinterpret_cast<double2*>(A)[kq * a_stride + (int64_t)i * ld + i] = a;
+          else
+            reinterpret_cast<float2*>(A)[kq * a_stride + (int64_t)i * ld + i] =
+                make_float2((float)a.x, (float)a.y);
+        }
+        if (diag64) {
+          diag64[(kq * n + i) * 2] = mphi;
+          diag64[(kq * n + i) * 2 + 1] = mpsi;
+        }
       }
-      if (diag64) {
-        diag64[((int64_t)kq * n + i) * 2] = mphi;
-        diag64[((int64_t)kq * n + i) * 2 + 1] = mpsi;
-      }
-    }
-    for (int q = 0; q < nr; ++q) {
-      const double2 yy = yk[(int64_t)(rhs0 + q) * n + i];
+      const double2 yy = y[(kq * n_rhs + rhs) * n + i];
       const double2 t = cmul(bb, yy);
-      b[((int64_t)kq * n_rhs + rhs0 + q) * n + i] =
-          make_double2(-(acc[4 + 2 * q] + t.x), -(acc[5 + 2 * q] + t.y));
+      b[(kq * n_rhs + rhs) * n + i] = make_double2(-(acc[q][4] + t.x), -(acc[q][5] + t.y));
     }
   }
 }
 
-// r = -(M_phi phi + M_psi psi) with (phi, psi) from the unknowns x and data y.
-__global__ __launch_bounds__(kThreads) void residual_kernel(
+// r = -(M_phi phi + M_psi psi) for one row, a chunk of wavenumbers and one
+// right-hand side, with (phi, psi) from the unknowns xs and data y.
+__global__ __launch_bounds__(kThreads) void residual_kc_kernel(
     int n, const double* __restrict__ x, const double* __restrict__ nrm,
     const double* __restrict__ w, const uint8_t* __restrict__ bc, const double* __restrict__ kv,
-    int n_rhs, int rhs0, const double2* __restrict__ y, const double2* __restrict__ xs,
+    int nk, int n_rhs, int rhs, const double2* __restrict__ y, const double2* __restrict__ xs,
     const double2* __restrict__ diag64, double2* __restrict__ r_out) {
   const int i = blockIdx.x;
-  const int kq = blockIdx.y;
-  const double k = kv[kq];
+  const KChunk<kKcResidual> kc = load_chunk<kKcResidual>(kv, nk);
+  const int q0 = blockIdx.y * kKcResidual;
   const double xi = x[3 * i], yi = x[3 * i + 1], zi = x[3 * i + 2];
-  const int nr = min(kRhsChunk, n_rhs - rhs0);
-  const int64_t base = (int64_t)kq * n_rhs * n;
-  double acc[2 * kRhsChunk];
+  double acc[kKcResidual][2];
 #pragma unroll
-  for (int c = 0; c < 2 * kRhsChunk; ++c) acc[c] = 0.0;
+  for (int q = 0; q < kKcResidual; ++q) { acc[q][0] = 0.0; acc[q][1] = 0.0; }
   for (int j = threadIdx.x; j < n; j += kThreads) {
     if (j == i) continue;
     const double dx = x[3 * j] - xi, dy = x[3 * j + 1] - yi, dz = x[3 * j + 2] - zi;
-    double r;
-    const PairGH p = pair_gh(k, dx, dy, dz, nrm[3 * j], nrm[3 * j + 1], nrm[3 * j + 2], r);
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    const double rinv = 1.0 / r;
+    const double qn = (dx * nrm[3 * j] + dy * nrm[3 * j + 1] + dz * nrm[3 * j + 2]) * (rinv * rinv * rinv);
     const double wj = w[j];
     const bool hard = bc[j] == BEM_BC_HARD;
+    Phase E;
+    E.start(kc, r);
 #pragma unroll
-    for (int q = 0; q < kRhsChunk; ++q) {
-      if (q < nr) {
-        const int64_t o = base + (int64_t)(rhs0 + q) * n + j;
+    for (int q = 0; q < kKcResidual; ++q) {
+      if (q < kc.kc) {
+        if (q > 0) E.next(kc, q, r);
+        const double kr = kc.k[q] * r;
+        const double2 G = make_double2(E.e.x * rinv, E.e.y * rinv);
+        const double2 H = make_double2(qn * (-E.e.x - kr * E.e.y), qn * (kr * E.e.x - E.e.y));
+        const int64_t o = ((int64_t)(q0 + q) * n_rhs + rhs) * n + j;
         const double2 u = xs[o], v = y[o];
         const double2 phi = hard ? u : v, psi = hard ? v : u;
         // -w H phi + w G psi
-        acc[2 * q] += wj * ((p.G.x * psi.x - p.G.y * psi.y) - (p.H.x * phi.x - p.H.y * phi.y));
-        acc[2 * q + 1] += wj * ((p.G.x * psi.y + p.G.y * psi.x) - (p.H.x * phi.y + p.H.y * phi.x));
+        acc[q][0] += wj * ((G.x * psi.x - G.y * psi.y) - (H.x * phi.x - H.y * phi.y));
+        acc[q][1] += wj * ((G.x * psi.y + G.y * psi.x) - (H.x * phi.y + H.y * phi.x));
       }
     }
   }
-  block_sum(acc);
+  block_sum_2d(acc);
   if (threadIdx.x == 0) {
-    const double2 dphi = diag64[((int64_t)kq * n + i) * 2];
-    const double2 dpsi = diag64[((int64_t)kq * n + i) * 2 + 1];
     const bool hard = bc[i] == BEM_BC_HARD;
-    for (int q = 0; q < nr; ++q) {
-      const int64_t o = base + (int64_t)(rhs0 + q) * n + i;
+#pragma unroll
+    for (int q = 0; q < kKcResidual; ++q) {
+      if (q >= kc.kc) break;
+      const int64_t kq = q0 + q;
+      const double2 dphi = diag64[(kq * n + i) * 2];
+      const double2 dpsi = diag64[(kq * n + i) * 2 + 1];
+      const int64_t o = (kq * n_rhs + rhs) * n + i;
       const double2 u = xs[o], v = y[o];
       const double2 phi = hard ? u : v, psi = hard ? v : u;
       const double2 t1 = cmul(dphi, phi), t2 = cmul(dpsi, psi);
-      r_out[o] = make_double2(-(acc[2 * q] + t1.x + t2.x), -(acc[2 * q + 1] + t1.y + t2.y));
+      r_out[o] = make_double2(-(acc[q][0] + t1.x + t2.x), -(acc[q][1] + t1.y + t2.y));
     }
   }
 }
@@ -249,41 +319,41 @@ bem_status launch_incident(bem_ctx* ctx, const bem_surface* s, int n_k, const do
 bem_status launch_assemble(bem_ctx* ctx, const bem_surface* s, int n_k, const double* k,
                            int n_rhs, const void* y, bem_prec prec, void* A, int64_t ld,
                            int64_t a_stride, void* b, void* diag64) {
-  for (int k0 = 0; k0 < n_k; k0 += 65535) {
-    const int nk = std::min(65535, n_k - k0);
-    dim3 grid(s->n, nk);
-    for (int r0 = 0; r0 < std::max(n_rhs, 1); r0 += kRhsChunk) {
-      const bool first = r0 == 0;
+  const int kmax = 65535 * kKcAssemble;
+  for (int k0 = 0; k0 < n_k; k0 += kmax) {
+    const int nk = std::min(kmax, n_k - k0);
+    dim3 grid(s->n, (nk + kKcAssemble - 1) / kKcAssemble);
+    const double2* yk = reinterpret_cast<const double2*>(y) + (int64_t)k0 * n_rhs * s->n;
+    double2* bk = reinterpret_cast<double2*>(b) + (int64_t)k0 * n_rhs * s->n;
+    double2* dk = diag64 ? reinterpret_cast<double2*>(diag64) + (int64_t)k0 * s->n * 2 : nullptr;
+    const size_t esz = prec == BEM_C128 ? 16 : 8;
+    void* Ak = A ? reinterpret_cast<char*>(A) + (int64_t)k0 * a_stride * esz : nullptr;
+    for (int r = 0; r < std::max(n_rhs, 1); ++r) {
+      const bool first = r == 0;
       const int pi = prof_begin(ctx, "assemble");
-      const double2* yk = reinterpret_cast<const double2*>(y) + (int64_t)k0 * n_rhs * s->n;
-      double2* bk = reinterpret_cast<double2*>(b) + (int64_t)k0 * n_rhs * s->n;
-      double2* dk = diag64 ? reinterpret_cast<double2*>(diag64) + (int64_t)k0 * s->n * 2 : nullptr;
-      const size_t esz = prec == BEM_C128 ? 16 : 8;
-      void* Ak = A ? reinterpret_cast<char*>(A) + (int64_t)k0 * a_stride * esz : nullptr;
       if (prec == BEM_C128) {
         if (first)
-          hipLaunchKernelGGL((assemble_kernel<true, true>), grid, dim3(kThreads), 0, ctx->stream,
-                             s->n, s->x, s->nrm, s->w, s->bc, k + k0, n_rhs, r0, yk, Ak, ld,
+          hipLaunchKernelGGL((assemble_kc_kernel<true, true>), grid, dim3(kThreads), 0, ctx->stream,
+                             s->n, s->x, s->nrm, s->w, s->bc, k + k0, nk, n_rhs, r, yk, Ak, ld,
                              a_stride, bk, dk);
         else
-          hipLaunchKernelGGL((assemble_kernel<true, false>), grid, dim3(kThreads), 0, ctx->stream,
-                             s->n, s->x, s->nrm, s->w, s->bc, k + k0, n_rhs, r0, yk, Ak, ld,
-                             a_stride, bk, dk);
+          hipLaunchKernelGGL((assemble_kc_kernel<true, false>), grid, dim3(kThreads), 0,
+                             ctx->stream, s->n, s->x, s->nrm, s->w, s->bc, k + k0, nk, n_rhs, r,
+                             yk, Ak, ld, a_stride, bk, dk);
       } else {
         if (first)
-          hipLaunchKernelGGL((assemble_kernel<false, true>), grid, dim3(kThreads), 0, ctx->stream,
-                             s->n, s->x, s->nrm, s->w, s->bc, k + k0, n_rhs, r0, yk, Ak, ld,
-                             a_stride, bk, dk);
+          hipLaunchKernelGGL((assemble_kc_kernel<false, true>), grid, dim3(kThreads), 0,
+                             ctx->stream, s->n, s->x, s->nrm, s->w, s->bc, k + k0, nk, n_rhs, r,
+                             yk, Ak, ld, a_stride, bk, dk);
         else
-          hipLaunchKernelGGL((assemble_kernel<false, false>), grid, dim3(kThreads), 0,
-                             ctx->stream, s->n, s->x, s->nrm, s->w, s->bc, k + k0, n_rhs, r0, yk,
-                             Ak, ld, a_stride, bk, dk);
+          hipLaunchKernelGGL((assemble_kc_kernel<false, false>), grid, dim3(kThreads), 0,
+                             ctx->stream, s->n, s->x, s->nrm, s->w, s->bc, k + k0, nk, n_rhs, r,
+                             yk, Ak, ld, a_stride, bk, dk);
       }
       // node pairs evaluated; bytes: matrix written (first pass) + b written
       const double pairs = (double)s->n * s->n * nk;
       prof_end(ctx, "assemble", pi, pairs,
-               (first ? (double)(prec == BEM_C128 ? 16 : 8) * s->n * s->n * nk : 0.0) +
-                   16.0 * s->n * std::min(kRhsChunk, std::max(n_rhs - r0, 0)) * nk);
+               (first && A ? (double)esz * s->n * s->n * nk : 0.0) + 16.0 * s->n * nk);
       BEM_CHECK_LAUNCH(ctx);
     }
   }
@@ -292,20 +362,20 @@ bem_status launch_assemble(bem_ctx* ctx, const bem_surface* s, int n_k, const do
 
 bem_status launch_residual(bem_ctx* ctx, const bem_surface* s, int n_k, const double* k,
                            int n_rhs, const void* y, const void* x, const void* diag64, void* r) {
-  for (int k0 = 0; k0 < n_k; k0 += 65535) {
-    const int nk = std::min(65535, n_k - k0);
-    dim3 grid(s->n, nk);
+  const int kmax = 65535 * kKcResidual;
+  for (int k0 = 0; k0 < n_k; k0 += kmax) {
+    const int nk = std::min(kmax, n_k - k0);
+    dim3 grid(s->n, (nk + kKcResidual - 1) / kKcResidual);
     const int64_t off = (int64_t)k0 * n_rhs * s->n;
-    for (int r0 = 0; r0 < n_rhs; r0 += kRhsChunk) {
+    for (int rh = 0; rh < n_rhs; ++rh) {
       const int pi = prof_begin(ctx, "residual");
-      hipLaunchKernelGGL(residual_kernel, grid, dim3(kThreads), 0, ctx->stream, s->n, s->x,
-                         s->nrm, s->w, s->bc, k + k0, n_rhs, r0,
+      hipLaunchKernelGGL(residual_kc_kernel, grid, dim3(kThreads), 0, ctx->stream, s->n, s->x,
+                         s->nrm, s->w, s->bc, k + k0, nk, n_rhs, rh,
                          reinterpret_cast<const double2*>(y) + off,
                          reinterpret_cast<const double2*>(x) + off,
                          reinterpret_cast<const double2*>(diag64) + (int64_t)k0 * s->n * 2,
                          reinterpret_cast<double2*>(r) + off);
-      prof_end(ctx, "residual", pi, (double)s->n * s->n * nk,
-               48.0 * s->n * std::min(kRhsChunk, n_rhs - r0) * nk);
+      prof_end(ctx, "residual", pi, (double)s->n * s->n * nk, 48.0 * s->n * nk);
       BEM_CHECK_LAUNCH(ctx);
     }
   }

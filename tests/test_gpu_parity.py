@@ -56,25 +56,34 @@ def test_incident_known_data(ctx):
 
 
 # ------------------------------------------------------------------ S3/S4
+# wavenumber sets: scattered values (one sincos per wavenumber) and an evenly
+# spaced grid with a ragged last chunk whose tail breaks the spacing (phase
+# recurrence inside the uniform chunks, direct evaluation in the rest)
+K_SETS = {"scattered": np.array([0.7, 3.1, 9.4]),
+          "grid": np.concatenate([0.75 * np.arange(1, 10), [7.9, 11.3]])}
+
+
+@pytest.mark.parametrize("kset", ["scattered", "grid"])
 @pytest.mark.parametrize("level", [1, 2])
-def test_assemble_c128_entries_diag_rhs(ctx, level):
+def test_assemble_c128_entries_diag_rhs(ctx, level, kset):
     bodies = mixed_bodies(level)
     s = Surface(bodies)
     ds = DeviceSurface.from_bodies(bodies)
     n = s.n
-    k = np.array([0.7, 3.1, 9.4])
+    k = K_SETS[kset]
+    nk = len(k)
     rng = np.random.default_rng(0)
-    nr = 5   # more than one rhs chunk
-    y = seeded_complex(rng, (3, nr, n))
+    nr = 5 if kset == "scattered" else 2
+    y = seeded_complex(rng, (nk, nr, n))
     ld = n + 3
-    A = torch.zeros((3, n, ld), dtype=torch.complex128, device="cuda")
-    b = torch.zeros((3, nr, n), dtype=torch.complex128, device="cuda")
-    dg = torch.zeros((3, n, 2), dtype=torch.complex128, device="cuda")
-    native.bem_assemble(ctx, ds.struct, 3, dev(k), nr, dev(y), native.BEM_C128, A, ld, b, dg)
+    A = torch.zeros((nk, n, ld), dtype=torch.complex128, device="cuda")
+    b = torch.zeros((nk, nr, n), dtype=torch.complex128, device="cuda")
+    dg = torch.zeros((nk, n, 2), dtype=torch.complex128, device="cuda")
+    native.bem_assemble(ctx, ds.struct, nk, dev(k), nr, dev(y), native.BEM_C128, A, ld, b, dg)
     A = A.cpu().numpy()[:, :, :n]
     b = b.cpu().numpy()
     dg = dg.cpu().numpy()
-    for q in range(3):
+    for q in range(nk):
         Mphi, Mpsi = bie.operator_matrices(s, k[q])
         Aref, _ = bie.system(s, k[q], y[q, 0])
         scale = np.max(np.abs(Aref), axis=1, keepdims=True)
@@ -102,23 +111,25 @@ def test_assemble_c64_is_rounded_fp64(ctx):
     assert rel(b.cpu().numpy()[0, 0], bref) < 1e-12
 
 
-def test_residual_matrix_free(ctx):
+@pytest.mark.parametrize("kset", ["scattered", "grid"])
+def test_residual_matrix_free(ctx, kset):
     bodies = mixed_bodies(2)
     s = Surface(bodies)
     ds = DeviceSurface.from_bodies(bodies)
     n = s.n
-    k = np.array([1.9, 6.6])
+    k = K_SETS[kset]
+    nk = len(k)
     rng = np.random.default_rng(2)
-    y = seeded_complex(rng, (2, 2, n))
-    x = seeded_complex(rng, (2, 2, n))
-    A = torch.zeros((2, n, n), dtype=torch.complex128, device="cuda")
-    b = torch.zeros((2, 2, n), dtype=torch.complex128, device="cuda")
-    dg = torch.zeros((2, n, 2), dtype=torch.complex128, device="cuda")
-    r = torch.zeros((2, 2, n), dtype=torch.complex128, device="cuda")
-    native.bem_assemble(ctx, ds.struct, 2, dev(k), 2, dev(y), native.BEM_C128, A, n, b, dg)
-    native.bem_residual(ctx, ds.struct, 2, dev(k), 2, dev(y), dev(x), dg, r)
+    y = seeded_complex(rng, (nk, 2, n))
+    x = seeded_complex(rng, (nk, 2, n))
+    A = torch.zeros((nk, n, n), dtype=torch.complex128, device="cuda")
+    b = torch.zeros((nk, 2, n), dtype=torch.complex128, device="cuda")
+    dg = torch.zeros((nk, n, 2), dtype=torch.complex128, device="cuda")
+    r = torch.zeros((nk, 2, n), dtype=torch.complex128, device="cuda")
+    native.bem_assemble(ctx, ds.struct, nk, dev(k), 2, dev(y), native.BEM_C128, A, n, b, dg)
+    native.bem_residual(ctx, ds.struct, nk, dev(k), 2, dev(y), dev(x), dg, r)
     r = r.cpu().numpy()
-    for q in range(2):
+    for q in range(nk):
         for j in range(2):
             Aref, bref = bie.system(s, k[q], y[q, j])
             ref = bref - Aref @ x[q, j]
