@@ -44,6 +44,10 @@ def main():
     ap.add_argument("--cpu-k", type=int, default=1)
     ap.add_argument("--mode", choices=["b3", "4m", "3m"], default="b3",
                     help="complex GEMM form of the float32 factorisation")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="first run one plain elementwise copy of 256 MiB (reads 256 MiB, "
+                         "writes 256 MiB: the reference for the HBM byte counters of a "
+                         "profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -55,6 +59,13 @@ def main():
 
     from paper_1706_07919_amd import DeviceSurface, native
     from workloads import config2, plane_grid
+
+    if args.copy_calib:
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     w = config2(args.n_k)
     n_k = len(w.k)
@@ -174,7 +185,11 @@ def main():
                                 "4m": "gemm_c32_kernel (LU updates, complex 4M on MFMA f32)",
                                 "3m": "gemm_c32_3m_kernel (LU updates, complex 3M on MFMA f32)"}[args.mode],
                      "bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": measured_traffic("gemm_c32_b3") if args.mode == "b3" else None,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                     "scaled by a copy kernel)",
+                     "algorithmic_bytes_per_launch": gb / max(gl, 1),
                      "launches": gl, "avg_launch_ms": gms / max(gl, 1),
                      "complex_4m_equivalent_tflops": alg_4m / 1e12,
                      "share_of_step": gms * 1e-3 / elapsed},
@@ -183,6 +198,25 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when there is none or lu.hip changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_two_spheres_N5124_nk512.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            key, _, val = line.partition(":")
+            vals[key.strip()] = val.strip()
+    src = os.path.join(ROOT, "paper_1706_07919_amd", "csrc", "lu.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if vals.get("lu_hip_sha256") != sha or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(w, x_gpu, n_cpu_k):
