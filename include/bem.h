@@ -203,7 +203,8 @@ bem_status bem_solve_batched(bem_ctx* ctx, const bem_problem* probs, int32_t n_p
 
 /* Building blocks of the direct solve (Sec. IV A), exposed for testing and for
  * callers that keep the factors to re-use them for other right-hand sides
- * (Sec. V: "the solution matrix ... can be stored").
+ * (Sec. V notes that the factorised system of a frequency can be kept and
+ * re-used).
  * bem_getrf_batched: in-place LU with partial pivoting (P A = L U, unit L) of
  *   `batch` row-major n x n matrices A + b*stride (elements of `prec`, leading
  *   dimension ld >= n, stride >= n*ld elements) [dev].  piv[batch][n] [dev]

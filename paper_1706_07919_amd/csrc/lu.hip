@@ -1,6 +1,6 @@
 // Batched dense complex LU with partial pivoting and triangular solves for the
-// one-system-per-wavenumber direct solve of Sec. IV A ("a linear system ...
-// solved using a direct method").  Matrices are row-major (element (i,j) at
+// direct solve of the discrete system at each wavenumber (Sec. IV A).
+// Matrices are row-major (element (i,j) at
 // i*ld + j), so row interchanges touch contiguous memory.
 //
 // Factorisation = recursion over column ranges (left half, swaps, triangular
