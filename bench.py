@@ -200,10 +200,20 @@ def main():
     print(json.dumps(out))
 
 
+def kernel_source_sha256():
+    """Hash of the bf16x3 GEMM's source section of lu.hip (its block comment,
+    helpers and kernel, up to the next section)."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_1706_07919_amd", "csrc", "lu.hip")).read()
+    a = src.index("// ============================================================== GEMM f32 via bf16 split")
+    b = src.index("// ============================================================== GEMM f64")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when there is none or lu.hip changed since it was taken."""
-    import hashlib
+    summary, or None when there is none or the kernel's source changed since
+    the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_two_spheres_N5124_nk512.txt")
     if not os.path.exists(path):
         return None
@@ -212,9 +222,8 @@ def measured_traffic(kernel):
         if ":" in line:
             key, _, val = line.partition(":")
             vals[key.strip()] = val.strip()
-    src = os.path.join(ROOT, "paper_1706_07919_amd", "csrc", "lu.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if vals.get("lu_hip_sha256") != sha or "traffic_bytes_per_launch" not in vals:
+    if vals.get("kernel_source_sha256") != kernel_source_sha256() or \
+            "traffic_bytes_per_launch" not in vals:
         return None
     return float(vals["traffic_bytes_per_launch"])
 
