@@ -44,6 +44,11 @@ def main():
     ap.add_argument("--cpu-k", type=int, default=1)
     ap.add_argument("--mode", choices=["b3", "4m", "3m"], default="b3",
                     help="complex GEMM form of the float32 factorisation")
+    ap.add_argument("--workload", choices=["spheres", "surrogate"], default="spheres",
+                    help="spheres: the headline sweep; surrogate: the learned-fill gain "
+                         "test (256 training / 4096 predicted wavenumbers, N = 5124)")
+    ap.add_argument("--sur-epochs", type=int, default=300)
+    ap.add_argument("--sur-sweeps", type=int, default=20)
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run one plain elementwise copy of 256 MiB (reads 256 MiB, "
                          "writes 256 MiB: the reference for the HBM byte counters of a "
@@ -56,6 +61,10 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.workload == "surrogate":
+        run_surrogate(args)
+        return
 
     from paper_1706_07919_amd import DeviceSurface, native
     from workloads import config2, plane_grid
@@ -197,6 +206,72 @@ def main():
         "synth_hbm_frac": (sb / (sms * 1e-3)) / PEAK_HBM if sms > 0 else None,
         "cpu_baseline": cpu,
     }
+    print(json.dumps(out))
+
+
+def run_surrogate(args):
+    """Gain test of the learned fill (one JSON line): the 4096-wavenumber sweep
+    of the two-sphere workload solved (i) directly, (ii) from 256 direct
+    training solves + network prediction + FP64 residual check + refinement
+    with the nearest training factors + direct fallback, (iii) as (ii) without
+    the network (refinement from zero).  All three reach the same FP64-residual
+    tolerance; times are whole-path wall clock with inputs resident."""
+    import torch
+
+    from paper_1706_07919_amd import DeviceSurface, native
+    from paper_1706_07919_amd import surrogate as sg
+    from workloads import config4, config4_train_k
+
+    w = config4()
+    k_train = config4_train_k(256)
+    k_pred = w.k
+    ctx = native.Context(0)
+    ds = DeviceSurface.from_bodies(w.bodies)
+    n, nkp = ds.n, len(k_pred)
+    dev = torch.device("cuda:0")
+    kp = torch.as_tensor(k_pred).to(dev)
+    yp = torch.empty((nkp, 1, n), dtype=torch.complex128, device=dev)
+    native.bem_incident(ctx, ds.struct, nkp, kp, (0.0, 0.0, 1.0), yp)
+    opts = native.bem_solve_opts_default()
+    opts.mode = native.BEM_FP32_IR_B3
+    x_dir = torch.zeros((nkp, 1, n), dtype=torch.complex128, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    native.bem_solve_batched(ctx, [(ds.struct, nkp, kp, 1, yp)], opts, [x_dir])
+    torch.cuda.synchronize()
+    t_direct = time.perf_counter() - t0
+    print(f"direct solves of {nkp} wavenumbers: {t_direct:.2f} s", file=sys.stderr, flush=True)
+    out = {"metric": "surrogate fill of 4096 wavenumbers at N=5124: wall time vs direct",
+           "unit": "s", "higher_is_better": False, "data": "synthetic",
+           "config": {"workload": w.name, "n": n, "n_train": len(k_train), "n_pred": nkp,
+                      "hidden": [512] * 4, "acceptance_tol": 1e-6},
+           "direct_s": t_direct}
+    for name, use in (("surrogate", True), ("zero_start", False)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = sg.fill_sweep(ctx, ds, k_train, k_pred, hidden=(512, 512, 512, 512),
+                            epochs=args.sur_epochs, lr=1e-3, tol=1e-6, refine_tol=1e-8,
+                            max_sweeps=args.sur_sweeps, use_surrogate=use)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        print(f"{name}: {total:.2f} s", file=sys.stderr, flush=True)
+        err = (torch.linalg.vector_norm(res["x"] - x_dir, dim=(1, 2)) /
+               torch.linalg.vector_norm(x_dir, dim=(1, 2))).max().item()
+        rr = native.bem_residual_check(ctx, ds.struct, nkp, kp, 1, res["y"], res["x"])
+        out[name] = {"total_s": total, "train_solves_s": res["t_train_solves"],
+                     "fit_s": res["t_fit"], "fill_s": res["t_fill"],
+                     "accepted_as_predicted": res["accepted_as_predicted"],
+                     "refined": res["refined"], "fallback": res["fallback"],
+                     "sweeps_mean": res["sweeps_mean"], "sweeps_max": res["sweeps_max"],
+                     "median_prediction_residual": float(np.median(res["rel_resid_prediction"])),
+                     "max_rel_err_vs_direct": err, "max_rel_resid": float(rr.max()),
+                     "n_oct": res["n_oct"]}
+        if use:
+            out[name]["final_loss"] = res["loss"][-1][1] if res.get("loss") else None
+        del res
+    out["value"] = out["surrogate"]["total_s"]
+    out["gain_vs_direct"] = t_direct / out["surrogate"]["total_s"]
+    out["gain_vs_zero_start"] = out["zero_start"]["total_s"] / out["surrogate"]["total_s"]
     print(json.dumps(out))
 
 

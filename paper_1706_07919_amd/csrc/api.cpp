@@ -16,7 +16,8 @@ namespace bem {
 bem_status lu_perm(bem_ctx* ctx, int n, int batch, const int32_t* piv, int32_t* perm);
 bem_status lu_solve_perm(bem_ctx* ctx, bem_prec prec, int n, int64_t ld, int64_t stride,
                          int batch, const void* LU, const int32_t* perm, int n_rhs,
-                         const void* Bin, void* X, int64_t bstride, const int32_t* fac_index = nullptr);
+                         const void* Bin, void* X, int64_t bstride, const int32_t* fac_index = nullptr,
+                         const int32_t* vidx = nullptr, int n_sel = 0);
 
 bem_status fail(bem_ctx* ctx, bem_status st, const char* fmt, ...) {
   if (ctx) {
@@ -694,7 +695,7 @@ extern "C" bem_status bem_refine_batched(bem_ctx* ctx, const bem_surface* s, int
       if (fi[q] < 0 || fi[q] >= n_fac)
         return fail(ctx, BEM_EINVAL, "bem_refine_batched: fac_index[%d] = %d out of range", q, fi[q]);
   }
-  const int kc = std::min(n_k, 512);
+  const int kc = std::min(n_k, 4096);   // wavenumbers refined together (workspace ~0.4 MB per k at N = 5124)
   const size_t v = (size_t)kc * n_rhs * n;
   size_t need = 0;
   auto sz = [&](size_t b) { return (b + 255) / 256 * 256; };
@@ -714,15 +715,15 @@ extern "C" bem_status bem_refine_batched(bem_ctx* ctx, const bem_surface* s, int
   double* dn2 = (double*)take((size_t)kc * n_rhs * 8);
   double* xn2 = (double*)take((size_t)kc * n_rhs * 8);
   uint8_t* active = (uint8_t*)take((size_t)kc * n_rhs);
-  int32_t* fidx = (int32_t*)take((size_t)kc * 4);
-  (void)fidx;
+  int32_t* kidx = (int32_t*)take((size_t)kc * 4);   // wavenumbers still refining
   if ((st = lu_perm(ctx, n, n_fac, piv, perm)) != BEM_OK) return st;
   void* hp = nullptr;
   const int nvmax = kc * n_rhs;
-  if ((st = pinned(ctx, (size_t)nvmax * 17, &hp)) != BEM_OK) return st;
+  if ((st = pinned(ctx, (size_t)nvmax * 17 + (size_t)kc * 4 + 64, &hp)) != BEM_OK) return st;
   double* h_dn = (double*)hp;
   double* h_xn = h_dn + nvmax;
-  uint8_t* h_act = (uint8_t*)(h_xn + nvmax);
+  int32_t* h_kidx = (int32_t*)(h_xn + nvmax);
+  uint8_t* h_act = (uint8_t*)(h_kidx + kc);
   for (int k0 = 0; k0 < n_k; k0 += kc) {
     const int cur = std::min(kc, n_k - k0);
     const int nv = cur * n_rhs;
@@ -734,12 +735,26 @@ extern "C" bem_status bem_refine_batched(bem_ctx* ctx, const bem_surface* s, int
     std::vector<double> step(nv, 1.0);
     std::vector<int> iters(nv, 0);
     for (int it = 0; it < max_iter; ++it) {
-      if ((st = launch_residual(ctx, s, cur, k + k0, n_rhs, yk, xk, diag, r)) != BEM_OK) return st;
+      // once some wavenumbers have converged, the residual and the correction
+      // solve run over the list of those still refining
+      int nsel = 0;
+      for (int q = 0; q < cur; ++q) {
+        bool any = false;
+        for (int c = 0; c < n_rhs; ++c) any = any || act[(size_t)q * n_rhs + c];
+        if (any) h_kidx[nsel++] = q;
+      }
+      const int32_t* sel = nullptr;
+      if (nsel < cur) {
+        BEM_HIP_TRY(ctx, hipMemcpyAsync(kidx, h_kidx, 4 * (size_t)nsel, hipMemcpyHostToDevice, ctx->stream));
+        sel = kidx;
+      }
+      if ((st = launch_residual(ctx, s, cur, k + k0, n_rhs, yk, xk, diag, r, sel, nsel)) != BEM_OK)
+        return st;
       std::memcpy(h_act, act.data(), nv);
       BEM_HIP_TRY(ctx, hipMemcpyAsync(active, h_act, nv, hipMemcpyHostToDevice, ctx->stream));
       if ((st = launch_ir_scale(ctx, nv, n, r, r32, scale)) != BEM_OK) return st;
       if ((st = lu_solve_perm(ctx, BEM_C64, n, ld, stride, cur, LU, perm, n_rhs, r32, d32,
-                              (int64_t)n_rhs * n, fac_index + k0)) != BEM_OK)
+                              (int64_t)n_rhs * n, fac_index + k0, sel, nsel)) != BEM_OK)
         return st;
       if ((st = launch_ir_update(ctx, nv, n, d32, scale, active, xk, dn2, xn2)) != BEM_OK) return st;
       BEM_HIP_TRY(ctx, hipMemcpyAsync(h_dn, dn2, 8 * nv, hipMemcpyDeviceToHost, ctx->stream));

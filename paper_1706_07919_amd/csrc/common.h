@@ -69,8 +69,11 @@ bem_status launch_incident(bem_ctx*, const bem_surface*, int n_k, const double* 
 bem_status launch_assemble(bem_ctx*, const bem_surface*, int n_k, const double* k, int n_rhs,
                            const void* y, bem_prec prec, void* A, int64_t ld,
                            int64_t a_stride, void* b, void* diag64);
+// kidx (optional, device): evaluate only the n_sel wavenumbers listed (indices
+// into k, y, x, diag64, r), leaving the other rows of r untouched.
 bem_status launch_residual(bem_ctx*, const bem_surface*, int n_k, const double* k, int n_rhs,
-                           const void* y, const void* x, const void* diag64, void* r);
+                           const void* y, const void* x, const void* diag64, void* r,
+                           const int32_t* kidx = nullptr, int n_sel = 0);
 bem_status launch_split(bem_ctx*, const bem_surface*, int n_k, int n_rhs, const void* x,
                         const void* y, void* phi, void* psi);
 

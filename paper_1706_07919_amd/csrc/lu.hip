@@ -1004,13 +1004,16 @@ __global__ __launch_bounds__(TS_T) void getrs_kernel(int n, int64_t ld, int64_t 
                                                      const int32_t* perm, int n_rhs,
                                                      const typename Cx<R>::T* Bin,
                                                      typename Cx<R>::T* X, int64_t bstride,
-                                                     const int32_t* fac_index) {
+                                                     const int32_t* fac_index,
+                                                     const int32_t* vidx) {
   using C = typename Cx<R>::T;
   extern __shared__ unsigned char smem[];
   C* D = reinterpret_cast<C*>(smem);                 // [TS_B][TS_B + 1]
   C* part = D + TS_B * (TS_B + 1);                   // [TS_B]
   C* xs = part + TS_B;                               // [n] when XLDS
-  const int mat = blockIdx.x / n_rhs, rhs = blockIdx.x % n_rhs;
+  // vector group: blockIdx / n_rhs, or the vidx entry when a subset is solved
+  const int mat = vidx ? vidx[blockIdx.x / n_rhs] : blockIdx.x / n_rhs;
+  const int rhs = blockIdx.x % n_rhs;
   // vector group `mat` is solved with factor set fac_index[mat] (identity if NULL)
   const int fac = fac_index ? fac_index[mat] : mat;
   const C* Lb = LU + (int64_t)fac * stride;
@@ -1360,7 +1363,9 @@ bem_status lu_perm(bem_ctx* ctx, int n, int batch, const int32_t* piv, int32_t* 
 
 bem_status lu_solve_perm(bem_ctx* ctx, bem_prec prec, int n, int64_t ld, int64_t stride,
                          int batch, const void* LU, const int32_t* perm, int n_rhs,
-                         const void* Bin, void* X, int64_t bstride, const int32_t* fac_index) {
+                         const void* Bin, void* X, int64_t bstride, const int32_t* fac_index,
+                         const int32_t* vidx, int n_sel) {
+  if (vidx) batch = n_sel;
   if (batch <= 0 || n_rhs <= 0) return BEM_OK;
   dim3 grid(batch * n_rhs);
   const size_t esz = prec == BEM_C128 ? 16 : 8;
@@ -1384,20 +1389,20 @@ bem_status lu_solve_perm(bem_ctx* ctx, bem_prec prec, int n, int64_t ld, int64_t
     if (xlds)
       hipLaunchKernelGGL((getrs_kernel<double, true>), grid, dim3(TS_T), lds, ctx->stream, n, ld,
                          stride, (const double2*)LU, perm, n_rhs, (const double2*)Bin,
-                         (double2*)X, bstride, fac_index);
+                         (double2*)X, bstride, fac_index, vidx);
     else
       hipLaunchKernelGGL((getrs_kernel<double, false>), grid, dim3(TS_T), lds, ctx->stream, n, ld,
                          stride, (const double2*)LU, perm, n_rhs, (const double2*)Bin,
-                         (double2*)X, bstride, fac_index);
+                         (double2*)X, bstride, fac_index, vidx);
   } else {
     if (xlds)
       hipLaunchKernelGGL((getrs_kernel<float, true>), grid, dim3(TS_T), lds, ctx->stream, n, ld,
                          stride, (const float2*)LU, perm, n_rhs, (const float2*)Bin, (float2*)X,
-                         bstride, fac_index);
+                         bstride, fac_index, vidx);
     else
       hipLaunchKernelGGL((getrs_kernel<float, false>), grid, dim3(TS_T), lds, ctx->stream, n, ld,
                          stride, (const float2*)LU, perm, n_rhs, (const float2*)Bin, (float2*)X,
-                         bstride, fac_index);
+                         bstride, fac_index, vidx);
   }
   prof_end(ctx, "getrs", pi, 8.0 * (double)n * n * n_rhs * batch,
            (double)esz * ((double)n * n + 3.0 * n * n_rhs) * batch);

@@ -75,13 +75,17 @@ struct KChunk {
   bool uniform;
 };
 
+// kidx (optional): slot t of the launch -> wavenumber index kidx[t]; the
+// chunk is formed over slots, so a sparse list of wavenumbers is evaluated
+// with a sincos per wavenumber unless its values still form an even grid.
 template <int KC>
-__device__ inline KChunk<KC> load_chunk(const double* __restrict__ kv, int nk) {
+__device__ inline KChunk<KC> load_chunk(const double* __restrict__ kv, int nk,
+                                        const int32_t* __restrict__ kidx) {
   KChunk<KC> c;
   const int q0 = blockIdx.y * KC;
   c.kc = min(KC, nk - q0);
 #pragma unroll
-  for (int q = 0; q < KC; ++q) c.k[q] = q < c.kc ? kv[q0 + q] : 0.0;
+  for (int q = 0; q < KC; ++q) c.k[q] = q < c.kc ? kv[kidx ? kidx[q0 + q] : q0 + q] : 0.0;
   c.uniform = c.kc > 1;
   c.dk = c.kc > 1 ? (c.k[c.kc - 1] - c.k[0]) / (c.kc - 1) : 0.0;
 #pragma unroll
@@ -126,7 +130,7 @@ __global__ __launch_bounds__(kThreads) void assemble_kc_kernel(
     int nk, int n_rhs, int rhs, const double2* __restrict__ y, void* __restrict__ A, int64_t ld,
     int64_t a_stride, double2* __restrict__ b, double2* __restrict__ diag64) {
   const int i = blockIdx.x;
-  const KChunk<kKcAssemble> kc = load_chunk<kKcAssemble>(kv, nk);
+  const KChunk<kKcAssemble> kc = load_chunk<kKcAssemble>(kv, nk, nullptr);
   const int q0 = blockIdx.y * kKcAssemble;
   const double xi = x[3 * i], yi = x[3 * i + 1], zi = x[3 * i + 2];
   const double nix = nrm[3 * i], niy = nrm[3 * i + 1], niz = nrm[3 * i + 2];
@@ -222,10 +226,14 @@ __global__ __launch_bounds__(kThreads) void residual_kc_kernel(
     int n, const double* __restrict__ x, const double* __restrict__ nrm,
     const double* __restrict__ w, const uint8_t* __restrict__ bc, const double* __restrict__ kv,
     int nk, int n_rhs, int rhs, const double2* __restrict__ y, const double2* __restrict__ xs,
-    const double2* __restrict__ diag64, double2* __restrict__ r_out) {
+    const double2* __restrict__ diag64, double2* __restrict__ r_out,
+    const int32_t* __restrict__ kidx) {
   const int i = blockIdx.x;
-  const KChunk<kKcResidual> kc = load_chunk<kKcResidual>(kv, nk);
+  const KChunk<kKcResidual> kc = load_chunk<kKcResidual>(kv, nk, kidx);
   const int q0 = blockIdx.y * kKcResidual;
+  int64_t kq_of[kKcResidual];
+#pragma unroll
+  for (int q = 0; q < kKcResidual; ++q) kq_of[q] = q < kc.kc ? (kidx ? kidx[q0 + q] : q0 + q) : 0;
   const double xi = x[3 * i], yi = x[3 * i + 1], zi = x[3 * i + 2];
   double acc[kKcResidual][2];
 #pragma unroll
@@ -247,7 +255,7 @@ __global__ __launch_bounds__(kThreads) void residual_kc_kernel(
         const double kr = kc.k[q] * r;
         const double2 G = make_double2(E.e.x * rinv, E.e.y * rinv);
         const double2 H = make_double2(qn * (-E.e.x - kr * E.e.y), qn * (kr * E.e.x - E.e.y));
-        const int64_t o = ((int64_t)(q0 + q) * n_rhs + rhs) * n + j;
+        const int64_t o = (kq_of[q] * n_rhs + rhs) * n + j;
         const double2 u = xs[o], v = y[o];
         const double2 phi = hard ? u : v, psi = hard ? v : u;
         // -w H phi + w G psi
@@ -262,7 +270,7 @@ __global__ __launch_bounds__(kThreads) void residual_kc_kernel(
 #pragma unroll
     for (int q = 0; q < kKcResidual; ++q) {
       if (q >= kc.kc) break;
-      const int64_t kq = q0 + q;
+      const int64_t kq = kq_of[q];
       const double2 dphi = diag64[(kq * n + i) * 2];
       const double2 dpsi = diag64[(kq * n + i) * 2 + 1];
       const int64_t o = (kq * n_rhs + rhs) * n + i;
@@ -361,7 +369,26 @@ bem_status launch_assemble(bem_ctx* ctx, const bem_surface* s, int n_k, const do
 }
 
 bem_status launch_residual(bem_ctx* ctx, const bem_surface* s, int n_k, const double* k,
-                           int n_rhs, const void* y, const void* x, const void* diag64, void* r) {
+                           int n_rhs, const void* y, const void* x, const void* diag64, void* r,
+                           const int32_t* kidx, int n_sel) {
+  if (kidx) {
+    // a selected subset of the n_k wavenumbers, evaluated in place
+    if (n_sel <= 0) return BEM_OK;
+    if (n_sel > 65535 * kKcResidual)
+      return fail(ctx, BEM_EUNSUPPORTED, "residual: %d selected wavenumbers in one call", n_sel);
+    dim3 grid(s->n, (n_sel + kKcResidual - 1) / kKcResidual);
+    for (int rh = 0; rh < n_rhs; ++rh) {
+      const int pi = prof_begin(ctx, "residual");
+      hipLaunchKernelGGL(residual_kc_kernel, grid, dim3(kThreads), 0, ctx->stream, s->n, s->x,
+                         s->nrm, s->w, s->bc, k, n_sel, n_rhs, rh,
+                         reinterpret_cast<const double2*>(y), reinterpret_cast<const double2*>(x),
+                         reinterpret_cast<const double2*>(diag64), reinterpret_cast<double2*>(r),
+                         kidx);
+      prof_end(ctx, "residual", pi, (double)s->n * s->n * n_sel, 48.0 * s->n * n_sel);
+      BEM_CHECK_LAUNCH(ctx);
+    }
+    return BEM_OK;
+  }
   const int kmax = 65535 * kKcResidual;
   for (int k0 = 0; k0 < n_k; k0 += kmax) {
     const int nk = std::min(kmax, n_k - k0);
@@ -374,7 +401,7 @@ bem_status launch_residual(bem_ctx* ctx, const bem_surface* s, int n_k, const do
                          reinterpret_cast<const double2*>(y) + off,
                          reinterpret_cast<const double2*>(x) + off,
                          reinterpret_cast<const double2*>(diag64) + (int64_t)k0 * s->n * 2,
-                         reinterpret_cast<double2*>(r) + off);
+                         reinterpret_cast<double2*>(r) + off, nullptr);
       prof_end(ctx, "residual", pi, (double)s->n * s->n * nk, 48.0 * s->n * nk);
       BEM_CHECK_LAUNCH(ctx);
     }

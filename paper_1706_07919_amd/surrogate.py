@@ -125,9 +125,11 @@ def nearest_index(k_pred, k_train):
     return np.abs(np.asarray(k_pred)[:, None] - np.asarray(k_train)[None, :]).argmin(axis=1).astype(np.int32)
 
 
-def training_factors(ctx, ds, kd, y, nb=0):
+def training_factors(ctx, ds, kd, y, nb=0, gemm_kind=None):
     """Float32 factors of the training wavenumbers (kept for re-use) and the
     FP64-accurate training solutions obtained by refining with them."""
+    if gemm_kind is None:
+        gemm_kind = native.BEM_GEMM_BF16X3
     t = __import__("torch")
     n = ds.n
     nk = int(kd.shape[0])
@@ -137,7 +139,7 @@ def training_factors(ctx, ds, kd, y, nb=0):
     native.bem_assemble(ctx, ds.struct, nk, kd, 1, y, native.BEM_C64, LU, ld, b, None)
     piv = t.empty((nk, n), dtype=t.int32, device=y.device)
     info = t.empty(nk, dtype=t.int32, device=y.device)
-    native.bem_getrf_batched(ctx, native.BEM_C64, n, ld, n * ld, nk, LU, piv, info, nb, 0)
+    native.bem_getrf_batched(ctx, native.BEM_C64, n, ld, n * ld, nk, LU, piv, info, nb, gemm_kind)
     x = t.zeros((nk, 1, n), dtype=t.complex128, device=y.device)
     fidx = t.arange(nk, dtype=t.int32, device=y.device)
     inf = native.bem_refine_batched(ctx, ds.struct, nk, kd, 1, y, LU, ld, n * ld, piv, nk, fidx,
@@ -208,6 +210,7 @@ def fill_sweep(ctx, ds, k_train, k_pred, hidden=(512, 512, 512, 512), seed=0, ep
     if fallback.size:
         xf = torch.zeros((fallback.size, 1, n), dtype=torch.complex128, device=dev)
         opts = native.bem_solve_opts_default()
+        opts.mode = native.BEM_FP32_IR_B3
         native.bem_solve_batched(ctx, [(ds.struct, int(fallback.size), kp[fallback].contiguous(), 1,
                                         yp[fallback].contiguous())], opts, [xf])
         x[fallback] = xf
