@@ -178,7 +178,10 @@ typedef struct {
   double tol_step;        /* stop when ||dx||_2/||x||_2 <= tol_step (default 1e-8) */
   int32_t max_iter;       /* refinement sweeps (default 10) */
   int32_t fallback;       /* 1: re-solve non-converged items in FP64 */
-  int32_t use_graph;      /* 1: replay the factorisation as a captured hipGraph */
+  int32_t use_graph;      /* 1 (default): replay the factorisation as a hipGraph captured
+                             on first use of a given set of matrices and sizes (kept by
+                             the context, dropped when its workspace moves); ignored
+                             while profiling is on */
   int32_t nb;             /* panel width of the factorisation, 0 = tuned */
 } bem_solve_opts;
 

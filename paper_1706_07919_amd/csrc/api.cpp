@@ -90,6 +90,7 @@ bem_status workspace(bem_ctx* ctx, size_t bytes, void** out) {
   }
   if (ctx->ws) {
     BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    drop_graphs(ctx);   // captured factorisations point into the old workspace
     BEM_HIP_TRY(ctx, hipFree(ctx->ws));
     ctx->ws = nullptr;
     ctx->ws_size = 0;
@@ -243,6 +244,8 @@ extern "C" void bem_ctx_destroy(bem_ctx* ctx) {
   if (!ctx) return;
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   else (void)hipDeviceSynchronize();
+  drop_graphs(ctx);
+  if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   resolve_stats(ctx);
@@ -286,7 +289,7 @@ extern "C" void bem_solve_opts_default(bem_solve_opts* o) {
   o->tol_step = 1e-8;
   o->max_iter = 10;
   o->fallback = 1;
-  o->use_graph = 0;
+  o->use_graph = 1;
   o->nb = 0;
 }
 
@@ -647,7 +650,13 @@ extern "C" bem_status bem_solve_batched(bem_ctx* ctx, const bem_problem* probs, 
         sets.push_back(chunk_set(runs[slices[q].p], slices[q].c, slices[q].kc, ld[slices[q].p]));
       const int gk = o.mode == BEM_FP32_IR_3M ? BEM_GEMM_3M
                      : o.mode == BEM_FP32_IR_B3 ? BEM_GEMM_BF16X3 : BEM_GEMM_4M;
-      if ((st = lu_factor_groups(ctx, prec, sets, plan, gk)) != BEM_OK) return st;
+      // captured graphs replay the launch sequence; per-kernel profiling needs
+      // the individual launches
+      if (o.use_graph && !ctx->profiling)
+        st = lu_factor_groups_graph(ctx, prec, sets, plan, gk);
+      else
+        st = lu_factor_groups(ctx, prec, sets, plan, gk);
+      if (st != BEM_OK) return st;
     }
     std::vector<std::vector<int>> bad(slices.size());
     for (size_t q = 0; q < slices.size(); ++q) {

@@ -38,6 +38,14 @@ struct bem_ctx {
   bool profiling = false;
   std::map<std::string, KernelStat> stats;
   std::vector<hipEvent_t> event_pool;
+  // captured factorisations, keyed by every argument of the launch sequence
+  // (matrix pointers, sizes, plan, GEMM form); dropped when the workspace moves
+  struct LuGraph {
+    std::vector<int64_t> key;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<LuGraph> lu_graphs;
+  hipStream_t capture_stream = nullptr;
 };
 
 namespace bem {
@@ -102,6 +110,11 @@ struct LuMatrixSet {
 };
 bem_status lu_factor_groups(bem_ctx*, bem_prec, const std::vector<LuMatrixSet>& sets,
                             const LuPlan& plan, int gemm_kind);
+// The same factorisation replayed from a captured hipGraph (captured on first
+// use of a given argument set, launched on ctx->stream).
+bem_status lu_factor_groups_graph(bem_ctx*, bem_prec, const std::vector<LuMatrixSet>& sets,
+                                  const LuPlan& plan, int gemm_kind);
+void drop_graphs(bem_ctx* ctx);
 // Solve A_b X = B_b in place for B_b = B + b*bstride (n_rhs vectors of length n, stride n).
 bem_status lu_solve(bem_ctx*, bem_prec, int n, int64_t ld, int64_t stride, int batch,
                     const void* LU, const int32_t* piv, int n_rhs, void* B, int64_t bstride);

@@ -1340,6 +1340,63 @@ bem_status lu_factor_groups(bem_ctx* ctx, bem_prec prec, const std::vector<LuMat
   return BEM_OK;
 }
 
+void drop_graphs(bem_ctx* ctx) {
+  for (auto& g : ctx->lu_graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  ctx->lu_graphs.clear();
+}
+
+bem_status lu_factor_groups_graph(bem_ctx* ctx, bem_prec prec, const std::vector<LuMatrixSet>& sets,
+                                  const LuPlan& plan, int gemm_kind) {
+  std::vector<int64_t> key{(int64_t)prec, plan.nb, plan.base, gemm_kind, (int64_t)sets.size()};
+  for (const LuMatrixSet& m : sets) {
+    key.push_back((int64_t)(intptr_t)m.A);
+    key.push_back((int64_t)(intptr_t)m.piv);
+    key.push_back((int64_t)(intptr_t)m.info);
+    key.push_back(m.ld);
+    key.push_back(m.stride);
+    key.push_back(m.n);
+    key.push_back(m.count);
+  }
+  for (auto& g : ctx->lu_graphs)
+    if (g.key == key) {
+      BEM_HIP_TRY(ctx, hipGraphLaunch(g.exec, ctx->stream));
+      return BEM_OK;
+    }
+  if (!ctx->capture_stream)
+    BEM_HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+  // record the launch sequence on the side stream (nothing executes), then
+  // launch the instantiated graph on the context stream
+  hipStream_t saved = ctx->stream;
+  ctx->stream = ctx->capture_stream;
+  const bool prof = ctx->profiling;
+  ctx->profiling = false;
+  BEM_HIP_TRY(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+  const bem_status st = lu_factor_groups(ctx, prec, sets, plan, gemm_kind);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(ctx->capture_stream, &graph);
+  ctx->stream = saved;
+  ctx->profiling = prof;
+  if (st != BEM_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (ec != hipSuccess)
+    return fail(ctx, BEM_EHIP, "hipStreamEndCapture failed: %s", hipGetErrorString(ec));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess)
+    return fail(ctx, BEM_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
+  if (ctx->lu_graphs.size() >= 8) {
+    (void)hipGraphExecDestroy(ctx->lu_graphs.front().exec);
+    ctx->lu_graphs.erase(ctx->lu_graphs.begin());
+  }
+  ctx->lu_graphs.push_back(bem_ctx::LuGraph{key, exec});
+  BEM_HIP_TRY(ctx, hipGraphLaunch(exec, ctx->stream));
+  return BEM_OK;
+}
+
 bem_status lu_factor(bem_ctx* ctx, bem_prec prec, int n, int64_t ld, int64_t stride, int batch,
                      void* A, int32_t* piv, int32_t* info, const LuPlan& plan, int gemm_kind) {
   if (batch <= 0 || n <= 0) return BEM_OK;

@@ -302,6 +302,51 @@ def test_solve_uneven_batch_vs_oracle(ctx, mode):
             q += 1
 
 
+@pytest.mark.parametrize("mode", [native.BEM_FP32_IR_B3, native.BEM_FP64_DIRECT])
+def test_solve_graph_replays_match_eager(ctx, mode):
+    """The factorisation captured as a hipGraph and replayed: every replay,
+    with eager work of another problem in between, gives the eager result bit
+    for bit (same kernels on the same data); a different problem size makes a
+    second capture, and the first one keeps replaying correctly."""
+    import time
+    problems = [([Body((0.0, 0.0, 0.0), 0.9, 2.2, 2, HARD)], np.array([1.0, 4.4, 6.1])),
+                ([Body((0.0, 0.0, 0.0), 1.0, 1.0, 2, SOFT)], np.array([0.7, 2.5]))]
+    prepared = []
+    for bodies, k in problems:
+        ds = DeviceSurface.from_bodies(bodies)
+        kd = dev(k)
+        y = torch.empty((len(k), 1, ds.n), dtype=torch.complex128, device="cuda")
+        native.bem_incident(ctx, ds.struct, len(k), kd, (0.0, 0.0, 1.0), y)
+        prepared.append((ds, kd, y, len(k)))
+
+    def run(i, graph):
+        ds, kd, y, nk = prepared[i]
+        x = torch.zeros((nk, 1, ds.n), dtype=torch.complex128, device="cuda")
+        opts = native.bem_solve_opts_default()
+        opts.mode = mode
+        opts.use_graph = 1 if graph else 0
+        native.bem_solve_batched(ctx, [(ds.struct, nk, kd, 1, y)], opts, [x])
+        return x.cpu().numpy()
+
+    eager = [run(0, False), run(1, False)]
+    for rep in range(3):
+        t0 = time.perf_counter()
+        a = run(0, True)
+        t1 = time.perf_counter()
+        b = run(1, False)                      # eager work between replays
+        c = run(1, True)
+        assert np.array_equal(a, eager[0]), f"replay {rep}, problem 0"
+        assert np.array_equal(b, eager[1])
+        assert np.array_equal(c, eager[1]), f"replay {rep}, problem 1"
+    bodies, k = problems[0]
+    s = Surface(bodies)
+    for j, kq in enumerate(k):
+        p, dp = bie.incident_plane_wave(s, kq)
+        _, _, xs = bie.solve(s, kq, bie.known_data(s, p, dp))
+        assert rel(a[j, 0], xs) < 1e-6
+    print(f"\nlast graph replay solve: {1e3 * (t1 - t0):.2f} ms")
+
+
 def test_solve_ir_fallback_forced(ctx):
     # max_iter = 1 cannot reach the step tolerance: every item falls back to FP64
     w = config1()
