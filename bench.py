@@ -50,6 +50,9 @@ def main():
                          "uneven: eight bodies of 642 to 10242 nodes solved together")
     ap.add_argument("--uneven-k", type=int, default=64,
                     help="wavenumbers per body for --workload uneven")
+    ap.add_argument("--nb", type=int, default=0, help="LU block width (0 = library default)")
+    ap.add_argument("--autotune", type=int, default=0,
+                    help="measure the LU block width on this many matrices before the run")
     ap.add_argument("--sur-epochs", type=int, default=300)
     ap.add_argument("--sur-sweeps", type=int, default=20)
     ap.add_argument("--copy-calib", action="store_true",
@@ -108,6 +111,13 @@ def main():
     mode = {"b3": native.BEM_FP32_IR_B3, "4m": native.BEM_FP32_IR_4M, "3m": native.BEM_FP32_IR_3M}[args.mode]
     gname = {"b3": "gemm_b3", "4m": "gemm_c32", "3m": "gemm_3m"}[args.mode]
     opts.mode = mode
+    opts.nb = args.nb
+    tuned = None
+    if args.autotune > 0:
+        gk = {"b3": native.BEM_GEMM_BF16X3, "4m": native.BEM_GEMM_4M, "3m": native.BEM_GEMM_3M}[args.mode]
+        tuned = native.bem_autotune_lu(ctx, native.BEM_C64, n, args.autotune, gk)
+        print(f"autotuned block width {tuned[0]} ({tuned[1]:.1f} ms for {args.autotune} matrices)",
+              file=sys.stderr, flush=True)
     infos = []
 
     def step():
@@ -189,7 +199,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": n, "n_k": n_k, "field_points": m, "T": T,
                    "mode": {"b3": "FP32_IR_B3", "4m": "FP32_IR_4M", "3m": "FP32_IR_3M"}[args.mode],
-                   "nb": opts.nb},
+                   "nb": opts.nb, "autotuned_nb": tuned[0] if tuned else None},
         "field_pt_freq_per_s": field_rate,
         "fp64_direct_solves_per_s": fp64_rate,
         "fp32ir_vs_fp64_direct_rel_err": rel64,
@@ -201,7 +211,8 @@ def main():
                                 "3m": "gemm_c32_3m_kernel (LU updates, complex 3M on MFMA f32)"}[args.mode],
                      "bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": measured_traffic("gemm_c32_b3") if args.mode == "b3" else None,
+                     "traffic": (measured_traffic("gemm_c32_b3", args.nb or (tuned[0] if tuned else "default"))
+                                 if args.mode == "b3" else None),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                      "scaled by a copy kernel)",
                      "algorithmic_bytes_per_launch": gb / max(gl, 1),
@@ -343,10 +354,11 @@ def kernel_source_sha256():
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, block_width="default"):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when there is none or the kernel's source changed since
-    the counters were taken."""
+    summary, or None when there is none, the kernel's source changed since the
+    counters were taken, or the factorisation's block width differs (it sets
+    the launch sizes)."""
     path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_two_spheres_N5124_nk512.txt")
     if not os.path.exists(path):
         return None
@@ -356,7 +368,7 @@ def measured_traffic(kernel):
             key, _, val = line.partition(":")
             vals[key.strip()] = val.strip()
     if vals.get("kernel_source_sha256") != kernel_source_sha256() or \
-            "traffic_bytes_per_launch" not in vals:
+            vals.get("block_width") != str(block_width) or "traffic_bytes_per_launch" not in vals:
         return None
     return float(vals["traffic_bytes_per_launch"])
 

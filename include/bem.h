@@ -182,7 +182,8 @@ typedef struct {
                              on first use of a given set of matrices and sizes (kept by
                              the context, dropped when its workspace moves); ignored
                              while profiling is on */
-  int32_t nb;             /* panel width of the factorisation, 0 = tuned */
+  int32_t nb;             /* block width of the factorisation; 0 = the width measured by
+                             bem_autotune_lu for this size class, else the default */
 } bem_solve_opts;
 
 typedef struct {
@@ -213,7 +214,8 @@ bem_status bem_solve_batched(bem_ctx* ctx, const bem_problem* probs, int32_t n_p
  *   dimension ld >= n, stride >= n*ld elements) [dev].  piv[batch][n] [dev]
  *   int32: row i was interchanged with row piv[i] (absolute, 0-based).
  *   info[batch] [dev] int32: 0, or 1 + index of the first exactly-zero pivot.
- *   nb = top-level panel width (0 = tuned; at most 256 is used), gemm_kind
+ *   nb = block width (0 = the width measured by bem_autotune_lu for this size
+ *   class, else 512 for n >= 4096 and 256 below; at most 1024 is used), gemm_kind
  *   (bem_gemm_kind) the complex GEMM form of the trailing updates for c64
  *   (ignored for c128).  n * ld must stay below 2^31.
  * bem_getrs_batched: X = A^{-1} B for n_rhs vectors per matrix:
@@ -225,6 +227,19 @@ bem_status bem_getrf_batched(bem_ctx* ctx, bem_prec prec, int32_t n, int32_t ld,
 bem_status bem_getrs_batched(bem_ctx* ctx, bem_prec prec, int32_t n, int32_t ld, int64_t stride,
                              int32_t batch, const void* LU, const int32_t* piv, int32_t n_rhs,
                              const void* B, void* X, int64_t bstride);
+
+/* Block width of the factorisation measured on this device: factors `batch`
+ * pseudo-random n x n matrices (diagonally dominant, deterministic) of the
+ * given precision and GEMM form once per candidate width (a 0-terminated list
+ * [host], or NULL for 256, 384, 512, 768, 1024), best of two runs each, and
+ * keeps the fastest in the context for every later factorisation of that
+ * precision, GEMM form and size class (n rounded up to 512) whose caller
+ * passes nb = 0.  best_nb, best_ms [host] may be NULL.  Allocates
+ * batch * n * ld elements for the duration of the call (BEM_ENOMEM if they do
+ * not fit); synchronises the stream. */
+bem_status bem_autotune_lu(bem_ctx* ctx, bem_prec prec, int32_t n, int32_t batch,
+                           int32_t gemm_kind, const int32_t* candidates, int32_t* best_nb,
+                           double* best_ms);
 
 /* Iterative refinement of given unknowns with stored float32 factors of
  * other (nearby) wavenumbers: x <- x + LU_f^{-1} (b - A(k) x), residual in

@@ -397,8 +397,23 @@ extern "C" bem_status bem_getrf_batched(bem_ctx* ctx, bem_prec prec, int32_t n, 
     return fail(ctx, BEM_EINVAL, "bem_getrf_batched: bad argument");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
   LuPlan plan;
-  plan.nb = nb > 0 ? nb : lu_default_nb(prec, n);
+  plan.nb = nb > 0 ? nb : lu_plan_nb(ctx, prec, prec == BEM_C64 ? gemm_kind : 0, n);
   return lu_factor(ctx, prec, n, ld, stride, batch, A, piv, info, plan, gemm_kind);
+}
+
+extern "C" bem_status bem_autotune_lu(bem_ctx* ctx, bem_prec prec, int32_t n, int32_t batch,
+                                      int32_t gemm_kind, const int32_t* candidates,
+                                      int32_t* best_nb, double* best_ms) {
+  if (!ctx) return BEM_EINVAL;
+  if (n <= 0 || batch <= 0 || (prec != BEM_C64 && prec != BEM_C128) ||
+      gemm_kind < BEM_GEMM_4M || gemm_kind > BEM_GEMM_BF16X3)
+    return fail(ctx, BEM_EINVAL, "bem_autotune_lu: bad argument");
+  if (candidates)
+    for (int c = 0; candidates[c] != 0; ++c)
+      if (candidates[c] < 0) return fail(ctx, BEM_EINVAL, "bem_autotune_lu: negative block width");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
+  return lu_autotune(ctx, prec, n, batch, prec == BEM_C64 ? gemm_kind : 0, candidates, best_nb,
+                     best_ms);
 }
 
 extern "C" bem_status bem_getrs_batched(bem_ctx* ctx, bem_prec prec, int32_t n, int32_t ld,
@@ -483,7 +498,7 @@ bem_status solve_fp64_chunk(SolveRun& R, const Chunk& c, int k0, int kc, int64_t
   bem_status st;
   if ((st = chunk_assemble(R, c, k0, kc, ld, BEM_C128)) != BEM_OK) return st;
   LuPlan plan;
-  plan.nb = R.o->nb > 0 ? R.o->nb : lu_default_nb(BEM_C128, R.pr->s->n);
+  plan.nb = R.o->nb > 0 ? R.o->nb : lu_plan_nb(R.ctx, BEM_C128, 0, R.pr->s->n);
   std::vector<LuMatrixSet> sets(1, chunk_set(R, c, kc, ld));
   if ((st = lu_factor_groups(R.ctx, BEM_C128, sets, plan, 0)) != BEM_OK) return st;
   return chunk_finish_fp64(R, c, k0, kc, ld);
@@ -625,7 +640,11 @@ extern "C" bem_status bem_solve_batched(bem_ctx* ctx, const bem_problem* probs, 
   void* ws = nullptr;
   if ((st = workspace(ctx, std::max(round_bytes(rounds), fallback_bytes), &ws)) != BEM_OK) return st;
   LuPlan plan;
-  plan.nb = o.nb > 0 ? o.nb : lu_default_nb(prec, nmax);
+  {
+    const int gk0 = o.mode == BEM_FP32_IR_3M ? BEM_GEMM_3M
+                    : o.mode == BEM_FP32_IR_B3 ? BEM_GEMM_BF16X3 : BEM_GEMM_4M;
+    plan.nb = o.nb > 0 ? o.nb : lu_plan_nb(ctx, prec, fp64 ? 0 : gk0, nmax);
+  }
   std::vector<SolveRun> runs;
   for (int p = 0; p < n_probs; ++p)
     runs.push_back(SolveRun{ctx, &probs[p], &o, (double2*)x_out[p], info ? info + info_off[p] : nullptr});

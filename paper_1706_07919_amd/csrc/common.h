@@ -32,7 +32,8 @@ struct bem_ctx {
   // small pinned host staging buffer for norms / flags
   void* pinned = nullptr;
   size_t pinned_size = 0;
-  // autotuned panel widths keyed by (precision, n-bucket)
+  // measured block widths of the factorisation keyed by
+  // (precision * 16 + GEMM form, n rounded up to 512)
   std::map<std::pair<int, int>, int> tuned_nb;
   int num_cus = 256;
   bool profiling = false;
@@ -119,6 +120,11 @@ void drop_graphs(bem_ctx* ctx);
 bem_status lu_solve(bem_ctx*, bem_prec, int n, int64_t ld, int64_t stride, int batch,
                     const void* LU, const int32_t* piv, int n_rhs, void* B, int64_t bstride);
 int lu_default_nb(bem_prec prec, int n);
+// block width for a factorisation: the measured one of this context when
+// bem_autotune_lu has run for the size class, else the default
+int lu_plan_nb(bem_ctx* ctx, bem_prec prec, int gemm_kind, int n);
+bem_status lu_autotune(bem_ctx* ctx, bem_prec prec, int n, int batch, int gemm_kind,
+                       const int32_t* candidates, int32_t* best_nb, double* best_ms);
 
 // ------------------------------------------------------------------ iterative refinement
 bem_status launch_ir_scale(bem_ctx*, int nvec, int n, const void* r, void* r32, double* scale);

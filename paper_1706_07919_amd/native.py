@@ -27,6 +27,7 @@ EXPORTED = [
     "bem_ctx_set_profiling", "bem_ctx_kernel_stats",
     "bem_mesh_counts", "bem_mesh_icosphere", "bem_incident", "bem_assemble", "bem_residual",
     "bem_solve_opts_default", "bem_solve_batched", "bem_getrf_batched", "bem_getrs_batched",
+    "bem_autotune_lu",
     "bem_split_unknowns", "bem_field_eval", "pulse_synthesize", "bem_pulse_coeffs",
     "bem_residual_check", "bem_refine_batched", "bem_mlp_features", "bem_mlp_dense_fwd", "bem_mlp_dense_bwd",
     "bem_mlp_mse_grad", "bem_mlp_adam", "bem_mlp_pack", "bem_mlp_unpack",
@@ -90,6 +91,8 @@ def load(path: str = LIB_PATH):
                                C.POINTER(bem_solve_info)], C.c_int),
         "bem_getrf_batched": ([vp, C.c_int, i32, i32, i64, i32, vp, vp, vp, i32, i32], C.c_int),
         "bem_getrs_batched": ([vp, C.c_int, i32, i32, i64, i32, vp, vp, i32, vp, vp, i64], C.c_int),
+        "bem_autotune_lu": ([vp, C.c_int, i32, i32, i32, vp, C.POINTER(i32), C.POINTER(dbl)],
+                            C.c_int),
         "bem_split_unknowns": ([vp, C.POINTER(bem_surface), i32, i32, vp, vp, vp, vp], C.c_int),
         "bem_field_eval": ([vp, C.POINTER(bem_surface), i32, vp, i32, vp, vp, i32, vp, vp, i32, vp,
                             C.c_int, vp], C.c_int),
@@ -242,6 +245,19 @@ def bem_solve_batched(ctx, problems, opts, x_out, want_info=True):
 def bem_getrf_batched(ctx, prec, n, ld, stride, batch, A, piv, info, nb=0, gemm_kind=0):
     _check(load().bem_getrf_batched(ctx.handle, prec, n, ld, stride, batch, _ptr(A), _ptr(piv),
                                     _ptr(info), nb, gemm_kind), ctx)
+
+
+def bem_autotune_lu(ctx, prec, n, batch, gemm_kind=0, candidates=None):
+    """Measure the factorisation for each candidate block width; returns
+    (best_nb, best_ms) and keeps the choice in the context."""
+    cand = None
+    if candidates is not None:
+        cand = (C.c_int32 * (len(candidates) + 1))(*candidates, 0)
+    best = C.c_int32()
+    ms = C.c_double()
+    _check(load().bem_autotune_lu(ctx.handle, prec, n, batch, gemm_kind, cand, C.byref(best),
+                                  C.byref(ms)), ctx)
+    return best.value, ms.value
 
 
 def bem_getrs_batched(ctx, prec, n, ld, stride, batch, LU, piv, n_rhs, B, X, bstride):

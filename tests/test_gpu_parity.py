@@ -206,6 +206,33 @@ def test_getrf_3m_and_split_gemm(ctx, n, kind):
             assert bwd < 3e-5
 
 
+def test_autotune_block_width_then_factor(ctx):
+    """The tuner times each candidate width on pseudo-random matrices and keeps
+    the fastest for the size class; a later nb = 0 factorisation of that class
+    uses it and stays correct."""
+    n = 300
+    best, ms = native.bem_autotune_lu(ctx, native.BEM_C64, n, 4, native.BEM_GEMM_BF16X3, [64, 128])
+    assert best in (64, 128) and ms > 0
+    rng = np.random.default_rng(5)
+    M = seeded_complex(rng, (2, n, n)) + 0.5 * np.sqrt(n) * np.eye(n)[None]
+    A = dev(M, torch.complex64)
+    piv = torch.zeros((2, n), dtype=torch.int32, device="cuda")
+    info = torch.ones(2, dtype=torch.int32, device="cuda")
+    native.bem_getrf_batched(ctx, native.BEM_C64, n, n, n * n, 2, A, piv, info, 0,
+                             native.BEM_GEMM_BF16X3)
+    B = seeded_complex(rng, (2, 1, n))
+    X = torch.zeros((2, 1, n), dtype=torch.complex64, device="cuda")
+    native.bem_getrs_batched(ctx, native.BEM_C64, n, n, n * n, 2, A, piv, 1, dev(B, torch.complex64), X, n)
+    X = X.cpu().numpy().astype(np.complex128)
+    for b_ in range(2):
+        # backward error of the bf16-split factorisation (see the split-GEMM test)
+        x = X[b_, 0]
+        bwd = np.linalg.norm(M[b_] @ x - B[b_, 0]) / (np.linalg.norm(M[b_]) * np.linalg.norm(x))
+        assert bwd < 3e-5
+    with pytest.raises(native.BemError):
+        native.bem_autotune_lu(ctx, native.BEM_C64, n, 2, 7)
+
+
 def test_getrf_reports_singular(ctx):
     n = 40
     M = seeded_complex(np.random.default_rng(9), (1, n, n))
