@@ -141,8 +141,8 @@ def main():
     t1 = time.perf_counter()
     elapsed = t1 - t0
     stats = {kname: ctx.kernel_stats(kname) for kname in
-             (gname, "panel", "laswp", "trsm", "assemble", "residual", "getrs", "field",
-              "synth")}
+             (gname, "gemm_b3_narrow", "panel", "laswp", "trsm", "assemble", "residual",
+              "getrs", "field", "synth")}
     ctx.set_profiling(False)
     solves_per_s = n_k * args.steps / elapsed
     info = infos[-1]
@@ -346,11 +346,11 @@ def run_surrogate(args):
 
 def kernel_source_sha256():
     """Hash of the bf16x3 GEMM's source section of lu.hip (its block comment,
-    helpers and kernel, up to the next section)."""
+    helpers and kernel, up to the narrow variant's section)."""
     import hashlib
     src = open(os.path.join(ROOT, "paper_1706_07919_amd", "csrc", "lu.hip")).read()
     a = src.index("// ============================================================== GEMM f32 via bf16 split")
-    b = src.index("// ============================================================== GEMM f64")
+    b = src.index("// ============================================================== GEMM f32 via bf16 split, narrow")
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 

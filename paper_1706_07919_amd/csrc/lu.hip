@@ -847,6 +847,128 @@ __global__ __launch_bounds__(256, 2) void gemm_c32_b3_kernel(LuGroups G, int row
     }
 }
 
+// ============================================================== GEMM f32 via bf16 split, narrow
+// Narrow updates (N <= 64, the tall panels inside a block): 128 x 32 tile per
+// workgroup of 4 waves (one 32 x 32 MFMA block each), so narrow matrices do
+// not pay for 128-wide tiles and four workgroups fit per CU.  C is loaded into
+// the accumulators at the start together with the first operand stage (A is
+// staged negated: acc = C - A B), which overlaps the C read with the k loop.
+constexpr int GT_BM = 128, GT_BN = 32;
+
+__global__ __launch_bounds__(256, 4) void gemm_c32_tsb_kernel(LuGroups G, int rowC, int colC,
+                                                              int colA, int rowB, int rowEnd,
+                                                              int colEnd, int K, int tiles_n) {
+  __shared__ uint4 Ah[2][GB_KG][GT_BM], Al[2][GB_KG][GT_BM];
+  __shared__ uint4 Brh[2][GB_KG][GT_BN], Brl[2][GB_KG][GT_BN];
+  GemmView<float2> gv;
+  if (!gemm_view(G, rowC, colC, colA, rowB, rowEnd, colEnd, gv)) return;
+  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  const int m0 = tm * GT_BM, n0 = tn * GT_BN;
+  const int M = gv.M, N = gv.N;
+  if (m0 >= M || n0 >= N) return;
+  const int ld = (int)gv.ld;   // n * ld < 2^31 is checked on the host
+  const GLOBAL float2* A = gv.A;
+  const GLOBAL float2* B = gv.B;
+  GLOBAL float2* C = gv.Cm;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int h = lane >> 5, l32 = lane & 31;
+  // this wave's C block: rows m0 + 32 wid + 8 (v/4) + 4 h + v%4, column n0 + l32
+  floatx16 acc_re, acc_im;
+  const int ccol = n0 + l32;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int row = m0 + 32 * wid + 8 * (v >> 2) + 4 * h + (v & 3);
+    const float2 c = C[min(row, M - 1) * ld + min(ccol, N - 1)];
+    acc_re[v] = c.x;
+    acc_im[v] = c.y;
+  }
+  // staging: two A chunks (row e / 4, k group e % 4) per thread, one B chunk
+  // (col tid % 32, k group tid / 32) for the first 128 threads; 4 complex each
+  float2 ra[2][4], rb[4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int e = tid + 256 * c, row = e / GB_KG, akg = e % GB_KG;
+      const GLOBAL float2* Ap = A + min(m0 + row, M - 1) * ld;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) ra[c][q] = Ap[min(k0 + 4 * akg + q, K - 1)];
+    }
+    if (tid < GT_BN * GB_KG) {
+      const int col = tid % GT_BN, bkg = tid / GT_BN;
+      const GLOBAL float2* Bp = B + min(n0 + col, N - 1);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) rb[q] = Bp[min(k0 + 4 * bkg + q, K - 1) * ld];
+    }
+  };
+  auto sstore = [&](int buf, int k0) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int e = tid + 256 * c, row = e / GB_KG, akg = e % GB_KG;
+      const bool rok = m0 + row < M;
+      float xa[8];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const unsigned ma = (rok && k0 + 4 * akg + q < K) ? 0xffffffffu : 0u;
+        xa[2 * q] = __uint_as_float(__float_as_uint(-ra[c][q].x) & ma);
+        xa[2 * q + 1] = __uint_as_float(__float_as_uint(-ra[c][q].y) & ma);
+      }
+      uint4 hi, lo;
+      split8(xa, hi, lo);
+      Ah[buf][akg][row] = hi;
+      Al[buf][akg][row] = lo;
+    }
+    if (tid < GT_BN * GB_KG) {
+      const int col = tid % GT_BN, bkg = tid / GT_BN;
+      const bool cok = n0 + col < N;
+      float xr[8];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const unsigned mb = (cok && k0 + 4 * bkg + q < K) ? 0xffffffffu : 0u;
+        xr[2 * q] = __uint_as_float(__float_as_uint(rb[q].x) & mb);
+        xr[2 * q + 1] = __uint_as_float(__float_as_uint(-rb[q].y) & mb);
+      }
+      uint4 hi, lo;
+      split8(xr, hi, lo);
+      Brh[buf][bkg][col] = hi;
+      Brl[buf][bkg][col] = lo;
+    }
+  };
+  const int nk = (K + GB_KB - 1) / GB_KB;
+  gload(0);
+  sstore(0, 0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * GB_KB);
+#pragma unroll
+    for (int s2 = 0; s2 < GB_KG / 2; ++s2) {
+      const int g = 2 * s2 + h;
+      Pack8 ah, al, bh, bl, bih, bil;
+      ah.u = Ah[cur][g][32 * wid + l32];
+      al.u = Al[cur][g][32 * wid + l32];
+      bh.u = Brh[cur][g][l32];
+      bl.u = Brl[cur][g][l32];
+      bih.u = re_to_im(bh.u);
+      bil.u = re_to_im(bl.u);
+      acc_re = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.v, bh.v, acc_re, 0, 0, 0);
+      acc_im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al.v, bih.v, acc_im, 0, 0, 0);
+      acc_re = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.v, bl.v, acc_re, 0, 0, 0);
+      acc_im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.v, bil.v, acc_im, 0, 0, 0);
+      acc_re = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.v, bh.v, acc_re, 0, 0, 0);
+      acc_im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah.v, bih.v, acc_im, 0, 0, 0);
+    }
+    if (kt + 1 < nk) sstore(cur ^ 1, (kt + 1) * GB_KB);
+    __syncthreads();
+  }
+  if (ccol < N) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int row = m0 + 32 * wid + 8 * (v >> 2) + 4 * h + (v & 3);
+      if (row < M) C[row * ld + ccol] = make_float2(acc_re[v], acc_im[v]);
+    }
+  }
+}
+
 // ============================================================== GEMM f64
 // Same contraction in float64 on MFMA 16x16x4 f64: one MFMA covers two
 // complex k (four interleaved real k).  64 x 64 tile, 4 waves of 32 x 32.
@@ -1200,7 +1322,7 @@ struct Fac {
     const int M = std::min(rowEnd, maxn) - rowC, N = std::min(colEnd, maxn) - colC;
     if (M <= 0 || N <= 0) return;
     const char* kname = prec == BEM_C128 ? "gemm_c64"
-                        : gkind == kGemmBf16x3 ? "gemm_b3"
+                        : gkind == kGemmBf16x3 ? (N <= 64 ? "gemm_b3_narrow" : "gemm_b3")
                         : gkind == kGemm3M ? "gemm_3m" : "gemm_c32";
     const int pi = prof_begin(ctx, kname);
     if (prec == BEM_C128) {
@@ -1209,7 +1331,11 @@ struct Fac {
                          colC, colA, rowB, rowEnd, colEnd, K, tn);
     } else {
       const int tn = (N + G32_BN - 1) / G32_BN, tm = (M + G32_BM - 1) / G32_BM;
-      if (gkind == kGemmBf16x3) {
+      if (gkind == kGemmBf16x3 && N <= 64) {
+        const int tmt = (M + GT_BM - 1) / GT_BM, tnt = (N + GT_BN - 1) / GT_BN;
+        hipLaunchKernelGGL(gemm_c32_tsb_kernel, dim3(tmt * tnt, total), dim3(256), 0, ctx->stream,
+                           G, rowC, colC, colA, rowB, rowEnd, colEnd, K, tnt);
+      } else if (gkind == kGemmBf16x3) {
         const int tmb = (M + GB_BM - 1) / GB_BM, tnb = (N + GB_BN - 1) / GB_BN;
         const int gx = (tmb * tnb + 7) / 8 * 8;
         hipLaunchKernelGGL(gemm_c32_b3_kernel, dim3(gx, total), dim3(256), 0, ctx->stream, G,
