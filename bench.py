@@ -44,10 +44,14 @@ def main():
     ap.add_argument("--cpu-k", type=int, default=1)
     ap.add_argument("--mode", choices=["b3", "4m", "3m"], default="b3",
                     help="complex GEMM form of the float32 factorisation")
-    ap.add_argument("--workload", choices=["spheres", "surrogate", "uneven"], default="spheres",
+    ap.add_argument("--workload", choices=["spheres", "surrogate", "uneven", "spacetime"],
+                    default="spheres",
                     help="spheres: the headline sweep; surrogate: the learned-fill gain "
                          "test (256 training / 4096 predicted wavenumbers, N = 5124); "
-                         "uneven: eight bodies of 642 to 10242 nodes solved together")
+                         "uneven: eight bodies of 642 to 10242 nodes solved together; "
+                         "spacetime: 2048 solves, field on a 1024^2 grid, 4 pulses")
+    ap.add_argument("--st-grid", type=int, default=1024,
+                    help="points per side of the field grid for --workload spacetime")
     ap.add_argument("--uneven-k", type=int, default=64,
                     help="wavenumbers per body for --workload uneven")
     ap.add_argument("--nb", type=int, default=0, help="LU block width (0 = library default)")
@@ -73,6 +77,9 @@ def main():
         return
     if args.workload == "uneven":
         run_uneven(args)
+        return
+    if args.workload == "spacetime":
+        run_spacetime(args)
         return
 
     from paper_1706_07919_amd import DeviceSurface, native
@@ -223,6 +230,72 @@ def main():
         "synth_hbm_frac": (sb / (sms * 1e-3)) / PEAK_HBM if sms > 0 else None,
         "cpu_baseline": cpu,
     }
+    print(json.dumps(out))
+
+
+def run_spacetime(args):
+    """Whole space-time path at full size: 2048 frequency solves of the two
+    spheres, closest node + field at a grid of points on x = 0 for every
+    frequency, and synthesis of four pulses (T = 4096).  One JSON line with
+    the field rate (point x frequency evaluations/s) as the value."""
+    import torch
+
+    from paper_1706_07919_amd import DeviceSurface, native
+    from workloads import config5
+
+    w = config5(n_grid=args.st_grid)
+    ctx = native.Context(0)
+    dev = torch.device("cuda:0")
+    ds = DeviceSurface.from_bodies(w.bodies)
+    n, nk, T = ds.n, len(w.k), w.T
+    xp = torch.as_tensor(w.points).to(dev)
+    m = xp.shape[0]
+    U = torch.empty((1, m, nk), dtype=torch.complex64, device=dev)
+    p = torch.empty((len(w.pulses), m, T), dtype=torch.float32, device=dev)
+    i0 = torch.empty(m, dtype=torch.int32, device=dev)
+    ins = torch.empty(m, dtype=torch.uint8, device=dev)
+    kinds = {"gauss": ["sigma"], "ricker": ["sigma"], "nwave": ["sigma"], "chirp": ["ka", "kb", "D"]}
+    c = np.stack([native.bem_pulse_coeffs(pu.kind, [pu.params[q] for q in kinds[pu.kind]], w.dk, nk, T,
+                                          w.z_shift) for pu in w.pulses])
+    cd = torch.as_tensor(c).to(dev)
+    kd = torch.as_tensor(w.k).to(dev)
+    y = torch.empty((nk, 1, n), dtype=torch.complex128, device=dev)
+    x = torch.zeros((nk, 1, n), dtype=torch.complex128, device=dev)
+    phi = torch.empty_like(x)
+    psi = torch.empty_like(x)
+    opts = native.bem_solve_opts_default()
+    opts.mode = native.BEM_FP32_IR_B3
+
+    def stamp():
+        torch.cuda.synchronize()
+        return time.perf_counter()
+
+    t0 = stamp()
+    native.bem_incident(ctx, ds.struct, nk, kd, (0.0, 0.0, 1.0), y)
+    info = native.bem_solve_batched(ctx, [(ds.struct, nk, kd, 1, y)], opts, [x])
+    native.bem_split_unknowns(ctx, ds.struct, nk, 1, x, y, phi, psi)
+    t1 = stamp()
+    print(f"{nk} solves: {t1 - t0:.2f} s", file=sys.stderr, flush=True)
+    native.bem_field_eval(ctx, ds.struct, nk, kd, 1, phi, psi, m, xp, i0, 0, ins, native.BEM_C64, U)
+    t2 = stamp()
+    print(f"field {m} x {nk}: {t2 - t1:.2f} s", file=sys.stderr, flush=True)
+    native.pulse_synthesize(ctx, m, nk, U[0], len(w.pulses), cd, T, 1, xp, w.dk, p)
+    t3 = stamp()
+    print(f"synthesis: {t3 - t2:.2f} s", file=sys.stderr, flush=True)
+    syn_bytes = 8.0 * m * nk + 4.0 * len(w.pulses) * m * T
+    out = {"metric": "field pt*freq evals/sec (space-time path at full size)",
+           "value": m * nk / (t2 - t1), "unit": "pt*freq/s", "higher_is_better": True,
+           "data": "synthetic", "dtype": "c64 field kernel (f64-centred geometry), f32 synthesis",
+           "config": {"workload": w.name, "n": n, "n_k": nk, "points": m, "pulses": len(w.pulses),
+                      "T": T},
+           "solve_s": t1 - t0, "solves_per_s": nk / (t1 - t0), "field_s": t2 - t1,
+           "field_terms_per_s": m * nk * n / (t2 - t1),
+           "inside_points": int(ins.sum().item()),
+           "synthesis_s": t3 - t2, "synthesis_GBps": syn_bytes / (t3 - t2) / 1e9,
+           "synthesis_hbm_frac": syn_bytes / (t3 - t2) / PEAK_HBM,
+           "ir_iters_max": max(info[q].iters for q in range(nk)),
+           "max_rel_resid": max(info[q].rel_resid for q in range(nk)),
+           "total_s": t3 - t0}
     print(json.dumps(out))
 
 

@@ -127,6 +127,18 @@ __global__ __launch_bounds__(kFT) void field_kernel(
   double kk[FCH];
 #pragma unroll
   for (int f = 0; f < FCH; ++f) kk[f] = f < nf ? kv[m0 + f] : kv[m0];
+  R kinv[FCH];
+#pragma unroll
+  for (int f = 0; f < FCH; ++f) kinv[f] = (R)(1.0 / kk[f]);
+  // float32 kernels on an evenly spaced chunk of wavenumbers advance both
+  // phases by a rotation (e^{i k_f t} = e^{i k_0 t} (e^{i dk t})^f): two phase
+  // evaluations per node instead of 2 FCH; about one float32 rounding per step
+  // (a few 1e-7 over a chunk of 8)
+  const double dkk = nf > 1 ? (kk[nf - 1] - kk[0]) / (nf - 1) : 0.0;
+  bool uni = sizeof(R) == 4 && nf > 1;
+#pragma unroll
+  for (int f = 1; f < FCH; ++f)
+    if (f < nf && !(fabs(kk[f] - (kk[0] + f * dkk)) <= 4e-16 * fabs(kk[f]))) uni = false;
   C A1[FCH], A2[FCH], A3[FCH];
 #pragma unroll
   for (int f = 0; f < FCH; ++f) {
@@ -159,21 +171,52 @@ __global__ __launch_bounds__(kFT) void field_kernel(
     for (int jj = 0; jj < cnt; ++jj) {
       if (j0 + jj == a) continue;
       const double dx = sx[jj][0] - px, dy = sx[jj][1] - py, dz = sx[jj][2] - pz;
+      // r and the phase argument n_a.(x_j - x_a) stay in float64 (they enter
+      // k r and k s); magnitudes (1/r, d.n, n_a.n_j) only need the kernel's
+      // precision: float32 reciprocal and dot products in the float32 kernel
       const double r = sqrt(dx * dx + dy * dy + dz * dz);
-      const double rinv = 1.0 / r;
-      const double dn = (dx * sn[jj][0] + dy * sn[jj][1] + dz * sn[jj][2]) * rinv * rinv;
+      R rinv, dn, nn;
+      if (sizeof(R) == 4) {
+        rinv = (R)__builtin_amdgcn_rcpf((float)r);
+        const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
+        dn = (R)((fdx * (float)sn[jj][0] + fdy * (float)sn[jj][1] + fdz * (float)sn[jj][2]) *
+                 ((float)rinv * (float)rinv));
+        nn = (R)((float)anx * (float)sn[jj][0] + (float)any * (float)sn[jj][1] +
+                 (float)anz * (float)sn[jj][2]);
+      } else {
+        const double ri = 1.0 / r;
+        rinv = (R)ri;
+        dn = (R)((dx * sn[jj][0] + dy * sn[jj][1] + dz * sn[jj][2]) * ri * ri);
+        nn = (R)(anx * sn[jj][0] + any * sn[jj][1] + anz * sn[jj][2]);
+      }
       const R wj = sw[jj];
-      const R wg = wj * (R)rinv;             // w/r
-      const R wh2 = -wj * (R)(dn * rinv);    // -w (d.n)/r^3
-      const R wh1 = wj * (R)dn;              // w (d.n)/r^2 (times k)
+      const R wg = wj * rinv;               // w/r
+      const R wh2 = -wj * (dn * rinv);      // -w (d.n)/r^3
+      const R wh1 = wj * dn;                // w (d.n)/r^2 (times k)
       const double sa = anx * (sx[jj][0] - ax) + any * (sx[jj][1] - ay) + anz * (sx[jj][2] - az);
-      const R nn = (R)(anx * sn[jj][0] + any * sn[jj][1] + anz * sn[jj][2]);
+      R es, ec, ss, cs, des = R(0), dec = R(1), dss = R(0), dcs = R(1);
+      phase<R>(kk[0] * r, es, ec);
+      phase<R>(kk[0] * sa, ss, cs);
+      if (uni) {
+        phase<R>(dkk * r, des, dec);
+        phase<R>(dkk * sa, dss, dcs);
+      }
 #pragma unroll
       for (int f = 0; f < FCH; ++f) {
         const R k = (R)kk[f];
-        R es, ec, ss, cs;
-        phase<R>(kk[f] * r, es, ec);
-        phase<R>(kk[f] * sa, ss, cs);
+        if (f > 0) {
+          if (uni) {
+            const R e1 = ec * des + es * dec, e0 = ec * dec - es * des;
+            es = e1;
+            ec = e0;
+            const R s1 = cs * dss + ss * dcs, s0 = cs * dcs - ss * dss;
+            ss = s1;
+            cs = s0;
+          } else {
+            phase<R>(kk[f] * r, es, ec);
+            phase<R>(kk[f] * sa, ss, cs);
+          }
+        }
         // wG = (w/r) E ; wH = E (-w dn/r^3 + i k w dn/r^2)
         const R gr = wg * ec, gi = wg * es;
         const R hb = k * wh1;
@@ -182,7 +225,7 @@ __global__ __launch_bounds__(kFT) void field_kernel(
         A1[f].x += (ph.x * hr - ph.y * hi) - (ps.x * gr - ps.y * gi);
         A1[f].y += (ph.x * hi + ph.y * hr) - (ps.x * gi + ps.y * gr);
         const R g = cs, gp = -k * ss * nn;
-        const R fv = ss / k, fp = cs * nn;
+        const R fv = ss * kinv[f], fp = cs * nn;
         A2[f].x += g * hr - gp * gr;
         A2[f].y += g * hi - gp * gi;
         A3[f].x += fv * hr - fp * gr;

@@ -117,12 +117,13 @@ constexpr int kPanelThreads = 512;
 template <typename R, int W, int RPT>
 __global__ __launch_bounds__(kPanelThreads) void panel_kernel(LuGroups G, int c0, int w_all) {
   using C = typename Cx<R>::T;
-  constexpr int NT = kPanelThreads;
-  __shared__ C pivrow[W];
-  __shared__ C toprow[W];
-  __shared__ R rv[NT / 64];
-  __shared__ int ri[NT / 64];
-  __shared__ int sel;
+  constexpr int NT = kPanelThreads, NW = NT / 64;
+  // pivot and top rows are double-buffered by column parity, so one column's
+  // readers never race the next column's writers; two barriers per column
+  __shared__ C pivrow[2][W];
+  __shared__ C toprow[2][W];
+  __shared__ R rv[NW];
+  __shared__ int ri[NW];
   LuGroup grp;
   int b = 0;
   if (!locate(G, blockIdx.x, grp, b)) return;
@@ -145,6 +146,8 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(LuGroups G, int c0
   }
   for (int c = 0; c < w; ++c) {
     const int pr = c0 + c;
+    const int buf = c & 1;
+    // candidate of this thread, then of its wave
     R best = R(-1);
     int bidx = 0x7fffffff;
 #pragma unroll
@@ -165,32 +168,28 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(LuGroups G, int c0
     }
     if (lane == 0) { rv[wid] = best; ri[wid] = bidx; }
     __syncthreads();
+    // every thread reduces the wave partials (same order, same result)
+    R bb = rv[0];
+    int bi = ri[0];
+#pragma unroll
+    for (int q = 1; q < NW; ++q)
+      if (rv[q] > bb || (rv[q] == bb && ri[q] < bi)) { bb = rv[q]; bi = ri[q]; }
+    const bool singular = !(bb > R(0));   // exactly zero (or NaN) column: no interchange
+    const int p = singular ? pr : bi;
     if (t == 0) {
-      R bb = rv[0];
-      int bi = ri[0];
-      for (int q = 1; q < NT / 64; ++q)
-        if (rv[q] > bb || (rv[q] == bb && ri[q] < bi)) { bb = rv[q]; bi = ri[q]; }
-      if (!(bb > R(0))) {  // exactly zero (or NaN) column: record, do not swap
-        if (info[b] == 0) info[b] = pr + 1;
-        bi = -1 - pr;
-      }
-      sel = bi;
-      piv[(int64_t)b * n + pr] = bi < 0 ? pr : bi;
+      if (singular && info[b] == 0) info[b] = pr + 1;
+      piv[(int64_t)b * n + pr] = p;
     }
-    __syncthreads();
-    const int s = sel;
-    const bool singular = s < 0;
-    const int p = singular ? pr : s;
-    // exchange rows pr and p through LDS
+    // the owners of rows p and pr publish them
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       const int r = c0 + t + q * NT;
       if (r == p)
 #pragma unroll
-        for (int cc = 0; cc < W; ++cc) pivrow[cc] = a[q][cc];
+        for (int cc = 0; cc < W; ++cc) pivrow[buf][cc] = a[q][cc];
       if (r == pr && p != pr)
 #pragma unroll
-        for (int cc = 0; cc < W; ++cc) toprow[cc] = a[q][cc];
+        for (int cc = 0; cc < W; ++cc) toprow[buf][cc] = a[q][cc];
     }
     __syncthreads();
     if (p != pr) {
@@ -199,16 +198,16 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(LuGroups G, int c0
         const int r = c0 + t + q * NT;
         if (r == p)
 #pragma unroll
-          for (int cc = 0; cc < W; ++cc) a[q][cc] = toprow[cc];
+          for (int cc = 0; cc < W; ++cc) a[q][cc] = toprow[buf][cc];
         if (r == pr)
 #pragma unroll
-          for (int cc = 0; cc < W; ++cc) a[q][cc] = pivrow[cc];
+          for (int cc = 0; cc < W; ++cc) a[q][cc] = pivrow[buf][cc];
       }
     }
     if (!singular) {
       C u[W];
 #pragma unroll
-      for (int cc = 0; cc < W; ++cc) u[cc] = pivrow[cc];
+      for (int cc = 0; cc < W; ++cc) u[cc] = pivrow[buf][cc];
       C pv = u[0];
 #pragma unroll
       for (int cc = 1; cc < W; ++cc)
@@ -228,7 +227,6 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(LuGroups G, int c0
         }
       }
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {

@@ -428,9 +428,13 @@ def _field_setup(ctx, bodies, k, xp):
 
 
 @pytest.mark.parametrize("prec", [native.BEM_C128, native.BEM_C64])
-def test_field_eval_vs_oracle(ctx, prec):
+@pytest.mark.parametrize("kset", ["scattered", "grid"])
+def test_field_eval_vs_oracle(ctx, prec, kset):
     bodies = [Body((0.0, 0.0, -1.3), 1.0, 1.0, 2, HARD), Body((0.0, 0.0, 1.3), 1.0, 1.0, 2, HARD)]
-    k = np.array([0.4, 3.3, 7.7, 11.9, 5.0, 2.2, 9.1, 1.1, 6.0, 10.5])   # ragged frequency tail
+    if kset == "scattered":
+        k = np.array([0.4, 3.3, 7.7, 11.9, 5.0, 2.2, 9.1, 1.1, 6.0, 10.5])   # ragged frequency tail
+    else:   # evenly spaced (phase rotation in the float32 kernel), ragged last chunk
+        k = 0.6 * np.arange(1, 20)
     rng = np.random.default_rng(11)
     xp = np.concatenate([rng.uniform(-4, 4, (300, 3)), ring_points(2.5, 16),
                          np.array([[0.0, 0.0, 0.0], [0.0, 0.0, -1.3 - 1.0005]])])
