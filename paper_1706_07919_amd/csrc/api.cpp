@@ -183,6 +183,7 @@ struct Chunk {
   double* scale;   // [kc*nr]
   double* dn2;     // [kc*nr]
   double* xn2;     // [kc*nr]
+  double* rn2;     // [kc*nr] |r|^2 of the last evaluated residual
   uint8_t* active; // [kc*nr]
 };
 
@@ -217,6 +218,7 @@ Chunk carve(void* base, int n, int64_t ld, int nr, int kc, bool c128, size_t* us
   c.scale = (double*)take((size_t)kc * nr * 8);
   c.dn2 = (double*)take((size_t)kc * nr * 8);
   c.xn2 = (double*)take((size_t)kc * nr * 8);
+  c.rn2 = (double*)take((size_t)kc * nr * 8);
   c.active = (uint8_t*)take((size_t)kc * nr);
   if (used) *used = (size_t)(p - (char*)base);
   return c;
@@ -507,6 +509,11 @@ bem_status solve_fp64_chunk(SolveRun& R, const Chunk& c, int k0, int kc, int64_t
 // After the float32 factorisation: refinement against the float64 operator.
 bem_status chunk_finish_ir(SolveRun& R, const Chunk& c, int k0, int kc, int64_t ld,
                            std::vector<int>& unconverged) {
+  // Refinement: x_0 = 0, r_0 = b; each sweep solves d = LU^{-1} r (float32,
+  // scaled), and stops an item when ||d|| / ||x + d|| <= tol_step; otherwise
+  // x += d and r = b - A x is evaluated in float64.  The returned x of a
+  // converged item is its last iterate whose float64 residual is known (the
+  // final correction only certifies it), so rel_resid needs no extra pass.
   bem_ctx* ctx = R.ctx;
   const bem_surface* s = R.pr->s;
   const int n = s->n, nr = R.pr->n_rhs;
@@ -516,17 +523,19 @@ bem_status chunk_finish_ir(SolveRun& R, const Chunk& c, int k0, int kc, int64_t 
   bem_status st;
   if ((st = lu_perm(ctx, n, kc, c.piv, c.perm)) != BEM_OK) return st;
   if ((st = fill_zero(ctx, c.x, (size_t)nv * n * 16)) != BEM_OK) return st;
+  if ((st = launch_norm2(ctx, nv, n, c.b, c.rn2)) != BEM_OK) return st;   // r_0 = b
   void* hp = nullptr;
-  if ((st = pinned(ctx, (size_t)nv * 16 + (size_t)kc * 4 + (size_t)nv, &hp)) != BEM_OK) return st;
+  if ((st = pinned(ctx, (size_t)nv * 24 + (size_t)kc * 4 + (size_t)nv, &hp)) != BEM_OK) return st;
   double* h_dn = (double*)hp;
   double* h_xn = h_dn + nv;
-  int32_t* h_info = (int32_t*)(h_xn + nv);
+  double* h_rn = h_xn + nv;
+  int32_t* h_info = (int32_t*)(h_rn + nv);
   uint8_t* h_act = (uint8_t*)(h_info + kc);
-  std::vector<uint8_t> act(nv, 1);
-  std::vector<double> step(nv, 1.0);
+  std::vector<uint8_t> act(nv, 1), fresh(nv, 1);   // fresh: residual of the current x known
+  std::vector<double> step(nv, 1.0), bn(nv, 0.0), rn(nv, 0.0);
   std::vector<int> iters(nv, 0);
   BEM_HIP_TRY(ctx, hipMemcpyAsync(h_info, c.info, 4 * kc, hipMemcpyDeviceToHost, ctx->stream));
-  const double2* rsrc = c.b;  // first sweep: r = b (x = 0)
+  const double2* rsrc = c.b;
   const int max_it = std::max(1, R.o->max_iter);
   for (int it = 0; it < max_it; ++it) {
     std::memcpy(h_act, act.data(), nv);
@@ -535,32 +544,53 @@ bem_status chunk_finish_ir(SolveRun& R, const Chunk& c, int k0, int kc, int64_t 
     if ((st = lu_solve_perm(ctx, BEM_C64, n, ld, (int64_t)n * ld, kc, c.A, c.perm, nr, c.r32,
                             c.d32, (int64_t)nr * n)) != BEM_OK)
       return st;
-    if ((st = launch_ir_update(ctx, nv, n, c.d32, c.scale, c.active, c.x, c.dn2, c.xn2)) != BEM_OK)
+    if ((st = launch_ir_update(ctx, nv, n, c.d32, c.scale, c.active, c.x, c.dn2, c.xn2, 0)) != BEM_OK)
       return st;
     BEM_HIP_TRY(ctx, hipMemcpyAsync(h_dn, c.dn2, 8 * nv, hipMemcpyDeviceToHost, ctx->stream));
     BEM_HIP_TRY(ctx, hipMemcpyAsync(h_xn, c.xn2, 8 * nv, hipMemcpyDeviceToHost, ctx->stream));
+    BEM_HIP_TRY(ctx, hipMemcpyAsync(h_rn, c.rn2, 8 * nv, hipMemcpyDeviceToHost, ctx->stream));
     BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     int live = 0;
     for (int v = 0; v < nv; ++v) {
       if (!act[v]) continue;
+      if (it == 0) bn[v] = h_rn[v];
+      rn[v] = h_rn[v];
       iters[v] = it + 1;
       const double sx = h_xn[v] > 0 ? std::sqrt(h_dn[v] / h_xn[v]) : (h_dn[v] > 0 ? 1.0 : 0.0);
       step[v] = sx;
-      if (!(sx > R.o->tol_step) && std::isfinite(sx)) act[v] = 0;
-      else ++live;
+      if (it > 0 && !(sx > R.o->tol_step) && std::isfinite(sx)) {
+        act[v] = 0;            // converged: keep x (its residual is rn)
+      } else {
+        ++live;
+      }
     }
     if (live == 0) break;
+    // take the correction of the items still refining, then their residual
+    std::memcpy(h_act, act.data(), nv);
+    BEM_HIP_TRY(ctx, hipMemcpyAsync(c.active, h_act, nv, hipMemcpyHostToDevice, ctx->stream));
+    if ((st = launch_ir_update(ctx, nv, n, c.d32, c.scale, c.active, c.x, c.dn2, c.xn2, 1)) != BEM_OK)
+      return st;
+    for (int v = 0; v < nv; ++v)
+      if (act[v]) fresh[v] = 0;
     if (it + 1 < max_it) {
       if ((st = launch_residual(ctx, s, kc, kk, nr, y, c.x, c.diag, c.r)) != BEM_OK) return st;
+      if ((st = launch_norm2(ctx, nv, n, c.r, c.rn2)) != BEM_OK) return st;
+      for (int v = 0; v < nv; ++v)
+        if (act[v]) fresh[v] = 1;
       rsrc = c.r;
     }
   }
-  // final residual of the float64 operator for the report
-  if ((st = launch_residual(ctx, s, kc, kk, nr, y, c.x, c.diag, c.r)) != BEM_OK) return st;
-  if ((st = launch_norm2(ctx, nv, n, c.r, c.dn2)) != BEM_OK) return st;
-  if ((st = launch_norm2(ctx, nv, n, c.b, c.xn2)) != BEM_OK) return st;
-  BEM_HIP_TRY(ctx, hipMemcpyAsync(h_dn, c.dn2, 8 * nv, hipMemcpyDeviceToHost, ctx->stream));
-  BEM_HIP_TRY(ctx, hipMemcpyAsync(h_xn, c.xn2, 8 * nv, hipMemcpyDeviceToHost, ctx->stream));
+  // items that ran out of sweeps with an unevaluated last correction
+  bool stale = false;
+  for (int v = 0; v < nv; ++v) stale = stale || !fresh[v];
+  if (stale) {
+    if ((st = launch_residual(ctx, s, kc, kk, nr, y, c.x, c.diag, c.r)) != BEM_OK) return st;
+    if ((st = launch_norm2(ctx, nv, n, c.r, c.rn2)) != BEM_OK) return st;
+    BEM_HIP_TRY(ctx, hipMemcpyAsync(h_rn, c.rn2, 8 * nv, hipMemcpyDeviceToHost, ctx->stream));
+    BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (int v = 0; v < nv; ++v)
+      if (!fresh[v]) rn[v] = h_rn[v];
+  }
   double2* xo = R.xout + (size_t)k0 * nr * n;
   BEM_HIP_TRY(ctx, hipMemcpyAsync(xo, c.x, (size_t)nv * n * 16, hipMemcpyDeviceToDevice, ctx->stream));
   BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -573,7 +603,7 @@ bem_status chunk_finish_ir(SolveRun& R, const Chunk& c, int k0, int kc, int64_t 
       I.used_fp64 = 0;
       I.singular = h_info[v / nr] != 0;
       I.converged = conv ? 1 : 0;
-      I.rel_resid = h_xn[v] > 0 ? std::sqrt(h_dn[v] / h_xn[v]) : 0.0;
+      I.rel_resid = bn[v] > 0 ? std::sqrt(rn[v] / bn[v]) : 0.0;
       I.rel_step = step[v];
     }
   }

@@ -129,7 +129,8 @@ bem_status lu_autotune(bem_ctx* ctx, bem_prec prec, int n, int batch, int gemm_k
 // ------------------------------------------------------------------ iterative refinement
 bem_status launch_ir_scale(bem_ctx*, int nvec, int n, const void* r, void* r32, double* scale);
 bem_status launch_ir_update(bem_ctx*, int nvec, int n, const void* d32, const double* scale,
-                            const uint8_t* active, void* x, double* dnorm2, double* xnorm2);
+                            const uint8_t* active, void* x, double* dnorm2, double* xnorm2,
+                            int apply = 1);
 bem_status launch_norm2(bem_ctx*, int nvec, int n, const void* v, double* out);
 bem_status launch_c128_to_c64(bem_ctx*, int64_t count, const void* in, void* out);
 bem_status fill_zero(bem_ctx*, void* p, size_t bytes);

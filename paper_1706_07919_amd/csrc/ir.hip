@@ -49,12 +49,14 @@ __global__ __launch_bounds__(kT) void ir_scale_kernel(int n, const double2* __re
   if (threadIdx.x == 0) scale[blockIdx.x] = s;
 }
 
+// d = scale * d32; dn2 = |d|^2, xn2 = |x + d|^2; x += d only when apply != 0
+// (apply == 0 sizes the correction before deciding whether to take it).
 __global__ __launch_bounds__(kT) void ir_update_kernel(int n, const float2* __restrict__ d32,
                                                        const double* __restrict__ scale,
                                                        const uint8_t* __restrict__ active,
                                                        double2* __restrict__ x,
                                                        double* __restrict__ dn2,
-                                                       double* __restrict__ xn2) {
+                                                       double* __restrict__ xn2, int apply) {
   __shared__ double sh[kT / 64];
   const int v = blockIdx.x;
   if (active && !active[v]) return;
@@ -67,7 +69,7 @@ __global__ __launch_bounds__(kT) void ir_update_kernel(int n, const float2* __re
     double2 xv = x[off + i];
     xv.x += dr;
     xv.y += di;
-    x[off + i] = xv;
+    if (apply) x[off + i] = xv;
     dd += dr * dr + di * di;
     xx += xv.x * xv.x + xv.y * xv.y;
   }
@@ -123,10 +125,11 @@ bem_status launch_ir_scale(bem_ctx* ctx, int nvec, int n, const void* r, void* r
 }
 
 bem_status launch_ir_update(bem_ctx* ctx, int nvec, int n, const void* d32, const double* scale,
-                            const uint8_t* active, void* x, double* dnorm2, double* xnorm2) {
+                            const uint8_t* active, void* x, double* dnorm2, double* xnorm2,
+                            int apply) {
   if (nvec <= 0) return BEM_OK;
   hipLaunchKernelGGL(ir_update_kernel, dim3(nvec), dim3(kT), 0, ctx->stream, n,
-                     (const float2*)d32, scale, active, (double2*)x, dnorm2, xnorm2);
+                     (const float2*)d32, scale, active, (double2*)x, dnorm2, xnorm2, apply);
   BEM_CHECK_LAUNCH(ctx);
   return BEM_OK;
 }
