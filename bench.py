@@ -116,7 +116,7 @@ def main():
     p = torch.zeros((1, m, T), dtype=torch.float32, device=dev)
     opts = native.bem_solve_opts_default()
     mode = {"b3": native.BEM_FP32_IR_B3, "4m": native.BEM_FP32_IR_4M, "3m": native.BEM_FP32_IR_3M}[args.mode]
-    gname = {"b3": "gemm_b3", "4m": "gemm_c32", "3m": "gemm_3m"}[args.mode]
+    gname = {"b3": "gemm_b3_packed", "4m": "gemm_c32", "3m": "gemm_3m"}[args.mode]
     opts.mode = mode
     opts.nb = args.nb
     tuned = None
@@ -148,8 +148,8 @@ def main():
     t1 = time.perf_counter()
     elapsed = t1 - t0
     stats = {kname: ctx.kernel_stats(kname) for kname in
-             (gname, "gemm_b3_narrow", "panel", "laswp", "trsm", "assemble", "residual",
-              "getrs", "field", "synth")}
+             (gname, "gemm_b3", "gemm_b3_narrow", "pack", "panel", "laswp", "trsm", "assemble",
+              "residual", "getrs", "field", "synth")}
     ctx.set_profiling(False)
     solves_per_s = n_k * args.steps / elapsed
     info = infos[-1]
@@ -213,12 +213,14 @@ def main():
         "ir_iters_max": max(iters),
         "ir_fallbacks": fallbacks,
         "max_rel_resid": max_resid,
-        "roofline": {"kernel": {"b3": "gemm_c32_b3_kernel (LU updates, bf16x3 split on MFMA bf16)",
+        "roofline": {"kernel": {"b3": "gemm_c32_b3p_kernel (LU trailing updates, bf16x3 split on "
+                                      "MFMA bf16, operands pre-split)",
                                 "4m": "gemm_c32_kernel (LU updates, complex 4M on MFMA f32)",
                                 "3m": "gemm_c32_3m_kernel (LU updates, complex 3M on MFMA f32)"}[args.mode],
                      "bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": (measured_traffic("gemm_c32_b3", args.nb or (tuned[0] if tuned else "default"))
+                     "traffic": (measured_traffic("gemm_c32_b3p", args.nb or (tuned[0] if tuned else "default"),
+                                                  gl // args.steps)
                                  if args.mode == "b3" else None),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                      "scaled by a copy kernel)",
@@ -417,21 +419,30 @@ def run_surrogate(args):
     print(json.dumps(out))
 
 
-def kernel_source_sha256():
-    """Hash of the bf16x3 GEMM's source section of lu.hip (its block comment,
-    helpers and kernel, up to the narrow variant's section)."""
+# lu.hip section (from its header to the next) holding each profiled kernel
+KERNEL_SECTIONS = {
+    "gemm_c32_b3p": ("GEMM f32 via bf16 split, packed operands", "GEMM f64"),
+    "gemm_c32_b3": ("GEMM f32 via bf16 split\n", "GEMM f32 via bf16 split, narrow"),
+}
+
+
+def kernel_source_sha256(kernel="gemm_c32_b3p"):
+    """Hash of the kernel's source section of lu.hip (its block comment,
+    helpers and kernels, up to the next section header)."""
     import hashlib
     src = open(os.path.join(ROOT, "paper_1706_07919_amd", "csrc", "lu.hip")).read()
-    a = src.index("// ============================================================== GEMM f32 via bf16 split")
-    b = src.index("// ============================================================== GEMM f32 via bf16 split, narrow")
+    head = "// ============================================================== "
+    first, last = KERNEL_SECTIONS[kernel]
+    a = src.index(head + first)
+    b = src.index(head + last)
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
-def measured_traffic(kernel, block_width="default"):
+def measured_traffic(kernel, block_width="default", launches_per_step=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, or None when there is none, the kernel's source changed since the
-    counters were taken, or the factorisation's block width differs (it sets
-    the launch sizes)."""
+    counters were taken, or the factorisation's block width or the number of
+    launches per step differs (they set the launch sizes)."""
     path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_two_spheres_N5124_nk512.txt")
     if not os.path.exists(path):
         return None
@@ -440,8 +451,10 @@ def measured_traffic(kernel, block_width="default"):
         if ":" in line:
             key, _, val = line.partition(":")
             vals[key.strip()] = val.strip()
-    if vals.get("kernel_source_sha256") != kernel_source_sha256() or \
+    if vals.get("kernel_source_sha256") != kernel_source_sha256(kernel) or \
             vals.get("block_width") != str(block_width) or "traffic_bytes_per_launch" not in vals:
+        return None
+    if launches_per_step is not None and vals.get("dispatches_per_step") != str(launches_per_step):
         return None
     return float(vals["traffic_bytes_per_launch"])
 

@@ -55,7 +55,8 @@ void bem_ctx_destroy(bem_ctx* ctx);
 /* Message of the last failed call on this context ("" if none). */
 const char* bem_last_error(const bem_ctx* ctx);
 /* Upper bound (bytes) of device workspace bem_solve_batched may hold; 0 = 75%
- * of the free device memory at the time of the call. */
+ * of the free device memory at the time of the call.  A nonzero limit also caps
+ * the packing buffer of BEM_GEMM_BF16X3 factorisations at a quarter of it. */
 bem_status bem_ctx_set_workspace_limit(bem_ctx* ctx, uint64_t bytes);
 
 /* Per-kernel accounting for roofline reports.  With profiling on, each launch
@@ -162,8 +163,19 @@ typedef enum {
   BEM_FP32_IR_B3 = 3
 } bem_mode;
 
-/* complex GEMM form of a c64 factorisation (last argument of bem_getrf_batched) */
-typedef enum { BEM_GEMM_4M = 0, BEM_GEMM_3M = 1, BEM_GEMM_BF16X3 = 2 } bem_gemm_kind;
+/* complex GEMM form of a c64 factorisation (last argument of bem_getrf_batched).
+ * BEM_GEMM_BF16X3 runs the trailing update of each block column on operands
+ * split once into bf16 words by a packing pass (the context keeps a packing
+ * buffer of at most 4 GiB and packs larger batches in slices; if it cannot be
+ * allocated the unpacked kernel runs).  BEM_GEMM_BF16X3_UNPACKED is the same
+ * arithmetic, bit for bit, with the split done inside every GEMM tile and no
+ * packing buffer. */
+typedef enum {
+  BEM_GEMM_4M = 0,
+  BEM_GEMM_3M = 1,
+  BEM_GEMM_BF16X3 = 2,
+  BEM_GEMM_BF16X3_UNPACKED = 3
+} bem_gemm_kind;
 
 typedef struct {
   const bem_surface* s;   /* [host] struct holding [dev] arrays */

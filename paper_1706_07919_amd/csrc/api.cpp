@@ -249,6 +249,7 @@ extern "C" void bem_ctx_destroy(bem_ctx* ctx) {
   drop_graphs(ctx);
   if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->pack) (void)hipFree(ctx->pack);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   resolve_stats(ctx);
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
@@ -395,7 +396,7 @@ extern "C" bem_status bem_getrf_batched(bem_ctx* ctx, bem_prec prec, int32_t n, 
   if (!ctx) return BEM_EINVAL;
   if (n <= 0 || ld < n || stride < (int64_t)n * ld || batch <= 0 || !A || !piv || !info ||
       (prec != BEM_C64 && prec != BEM_C128) || nb < 0 || gemm_kind < BEM_GEMM_4M ||
-      gemm_kind > BEM_GEMM_BF16X3)
+      gemm_kind > BEM_GEMM_BF16X3_UNPACKED)
     return fail(ctx, BEM_EINVAL, "bem_getrf_batched: bad argument");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
   LuPlan plan;
@@ -408,7 +409,7 @@ extern "C" bem_status bem_autotune_lu(bem_ctx* ctx, bem_prec prec, int32_t n, in
                                       int32_t* best_nb, double* best_ms) {
   if (!ctx) return BEM_EINVAL;
   if (n <= 0 || batch <= 0 || (prec != BEM_C64 && prec != BEM_C128) ||
-      gemm_kind < BEM_GEMM_4M || gemm_kind > BEM_GEMM_BF16X3)
+      gemm_kind < BEM_GEMM_4M || gemm_kind > BEM_GEMM_BF16X3_UNPACKED)
     return fail(ctx, BEM_EINVAL, "bem_autotune_lu: bad argument");
   if (candidates)
     for (int c = 0; candidates[c] != 0; ++c)

@@ -47,6 +47,9 @@ struct bem_ctx {
   };
   std::vector<LuGraph> lu_graphs;
   hipStream_t capture_stream = nullptr;
+  // operands of the trailing updates split into bf16 words (grown on demand)
+  void* pack = nullptr;
+  size_t pack_size = 0;
 };
 
 namespace bem {
@@ -92,7 +95,7 @@ bem_status launch_split(bem_ctx*, const bem_surface*, int n_k, int n_rhs, const 
 // info_b = info + b: 0, or 1 + first zero pivot column.
 // complex GEMM forms of the c64 factorisation (the last argument of
 // bem_getrf_batched)
-enum { kGemm4M = 0, kGemm3M = 1, kGemmBf16x3 = 2 };
+enum { kGemm4M = 0, kGemm3M = 1, kGemmBf16x3 = 2, kGemmBf16x3Unpacked = 3 };
 
 struct LuPlan {
   int nb = 0;          // top-level panel width (0 = recursive halving)

@@ -967,6 +967,205 @@ __global__ __launch_bounds__(256, 4) void gemm_c32_tsb_kernel(LuGroups G, int ro
   }
 }
 
+// ============================================================== GEMM f32 via bf16 split, packed operands
+// The trailing update after each block column takes its operands split once:
+// a packing pass converts the block column of L below the block (A) and the
+// block row of U right of it (B, in the real-part pattern (Re, -Im)) into bf16
+// hi/lo words laid out as the GEMM's LDS stage buffers -- per 128-row (or
+// -column) tile and 16-k stage, [hi/lo][k group][row] 16-byte words,
+// zero-padded past the edges.  The GEMM's staging is then a plain 16-byte
+// copy and each element is split once rather than once per tile reading it.
+// The products and their order are those of gemm_c32_b3_kernel, so the
+// update is bit-identical to it.
+constexpr int GP_STG = 2 * GB_KG * GB_BM;   // 16-byte words per tile and stage
+// largest packing buffer a context holds; bigger batches are packed in slices
+constexpr size_t kPackLimit = (size_t)4 << 30;
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// bytes of the packed A and B of one matrix for an M x N update of depth K
+inline int64_t pack_words(int M, int N, int K) {
+  const int64_t S = (K + GB_KB - 1) / GB_KB;
+  return ((int64_t)(M + GB_BM - 1) / GB_BM + (N + GB_BN - 1) / GB_BN) * S * GP_STG;
+}
+
+// A = rows [rowC, min(rowEnd, n)) x cols [colA, colA + K) -> out + y * ms
+__global__ __launch_bounds__(256) void pack_a_kernel(LuGroups G, int rowC, int colA, int rowEnd,
+                                                     int K, int tiles_m, int64_t ms,
+                                                     uint4* __restrict__ out) {
+  LuGroup grp;
+  int b = 0;
+  if (!locate(G, blockIdx.y, grp, b)) return;
+  const int M = min(rowEnd, grp.n) - rowC;
+  if (M <= 0) return;
+  const int S = (K + GB_KB - 1) / GB_KB;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;   // (tile, stage, k group, row)
+  if (idx >= (int64_t)tiles_m * S * (GP_STG / 2)) return;
+  const int row = (int)(idx % GB_BM), kg = (int)((idx / GB_BM) % GB_KG);
+  const int64_t ts = idx / (GB_BM * GB_KG);
+  const int s = (int)(ts % S);
+  const int gr = (int)(ts / S) * GB_BM + row, k0 = s * GB_KB + 4 * kg;
+  const GLOBAL float2* A = gmat<float2>(grp, b) + (int64_t)(rowC + min(gr, M - 1)) * grp.ld + colA;
+  float x[8];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    float2 a = make_float2(0.f, 0.f);
+    if (gr < M && k0 + q < K) a = A[k0 + q];
+    x[2 * q] = a.x;
+    x[2 * q + 1] = a.y;
+  }
+  uint4 hi, lo;
+  split8(x, hi, lo);
+  uint4* o = out + blockIdx.y * ms + ts * GP_STG;
+  o[kg * GB_BM + row] = hi;
+  o[GP_STG / 2 + kg * GB_BM + row] = lo;
+}
+
+// B = rows [rowB, rowB + K) x cols [colC, min(colEnd, n)) -> out + y * ms
+__global__ __launch_bounds__(256) void pack_b_kernel(LuGroups G, int rowB, int colC, int colEnd,
+                                                     int K, int tiles_n, int64_t ms,
+                                                     uint4* __restrict__ out) {
+  LuGroup grp;
+  int b = 0;
+  if (!locate(G, blockIdx.y, grp, b)) return;
+  const int N = min(colEnd, grp.n) - colC;
+  if (N <= 0) return;
+  const int S = (K + GB_KB - 1) / GB_KB;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;   // (tile, stage, k group, col)
+  if (idx >= (int64_t)tiles_n * S * (GP_STG / 2)) return;
+  const int col = (int)(idx % GB_BN), kg = (int)((idx / GB_BN) % GB_KG);
+  const int64_t ts = idx / (GB_BN * GB_KG);
+  const int s = (int)(ts % S);
+  const int gc = (int)(ts / S) * GB_BN + col, k0 = s * GB_KB + 4 * kg;
+  const GLOBAL float2* B = gmat<float2>(grp, b) + (int64_t)rowB * grp.ld + colC + min(gc, N - 1);
+  float x[8];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    float2 v = make_float2(0.f, 0.f);
+    if (gc < N && k0 + q < K) v = B[(int64_t)(k0 + q) * grp.ld];
+    x[2 * q] = v.x;
+    x[2 * q + 1] = -v.y;
+  }
+  uint4 hi, lo;
+  split8(x, hi, lo);
+  uint4* o = out + blockIdx.y * ms + ts * GP_STG;
+  o[kg * GB_BN + col] = hi;
+  o[GP_STG / 2 + kg * GB_BN + col] = lo;
+}
+
+__device__ inline bf16x8 re_to_im8(bf16x8 b) {
+  const u32x4 r = __builtin_bit_cast(u32x4, b);
+  return __builtin_bit_cast(bf16x8, ((r >> 16) | (r << 16)) ^ 0x8000u);
+}
+
+__global__ __launch_bounds__(256, 2) void gemm_c32_b3p_kernel(LuGroups G, int rowC, int colC,
+                                                              int rowEnd, int colEnd, int K,
+                                                              int tiles_m, int tiles_n,
+                                                              const uint4* __restrict__ Ap,
+                                                              int64_t a_ms,
+                                                              const uint4* __restrict__ Bp,
+                                                              int64_t b_ms) {
+  __shared__ u32x4 As[2][GP_STG], Bs[2][GP_STG];
+  const int per = gridDim.x / 8;
+  const int t = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (t >= tiles_m * tiles_n) return;
+  const int grp = t / (GB_GM * tiles_n), first = grp * GB_GM;
+  const int gsz = min(tiles_m - first, GB_GM);
+  const int tm = first + (t % (GB_GM * tiles_n)) % gsz;
+  const int tn = (t % (GB_GM * tiles_n)) / gsz;
+  GemmView<float2> gv;
+  if (!gemm_view(G, rowC, colC, 0, 0, rowEnd, colEnd, gv)) return;
+  const int m0 = tm * GB_BM, n0 = tn * GB_BN;
+  const int M = gv.M, N = gv.N;
+  if (m0 >= M || n0 >= N) return;
+  const int ld = (int)gv.ld;   // n * ld < 2^31 is checked on the host
+  GLOBAL float2* C = gv.Cm;
+  const int S = (K + GB_KB - 1) / GB_KB;
+  const GLOBAL u32x4* Ag = (const GLOBAL u32x4*)Ap + blockIdx.y * a_ms + (int64_t)tm * S * GP_STG;
+  const GLOBAL u32x4* Bg = (const GLOBAL u32x4*)Bp + blockIdx.y * b_ms + (int64_t)tn * S * GP_STG;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  const int h = lane >> 5, l32 = lane & 31;
+  floatx16 acc_re[2][2], acc_im[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) { acc_re[i][j][v] = 0.f; acc_im[i][j][v] = 0.f; }
+  constexpr int NW = GP_STG / 256;   // 16-byte words per thread per operand and stage
+  u32x4 ra[NW], rb[NW];
+  auto gload = [&](int s) {
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      ra[q] = Ag[(int64_t)s * GP_STG + tid + 256 * q];
+      rb[q] = Bg[(int64_t)s * GP_STG + tid + 256 * q];
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      As[buf][tid + 256 * q] = ra[q];
+      Bs[buf][tid + 256 * q] = rb[q];
+    }
+  };
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < S; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < S) gload(kt + 1);
+#pragma unroll
+    for (int s2 = 0; s2 < GB_KG / 2; ++s2) {
+      const int g = 2 * s2 + h;
+      bf16x8 ah[2], al[2], brh[2], brl[2], bih[2], bil[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        ah[i] = __builtin_bit_cast(bf16x8, As[cur][g * GB_BM + wm * 64 + i * 32 + l32]);
+        al[i] = __builtin_bit_cast(bf16x8, As[cur][GP_STG / 2 + g * GB_BM + wm * 64 + i * 32 + l32]);
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        brh[j] = __builtin_bit_cast(bf16x8, Bs[cur][g * GB_BN + wn * 64 + j * 32 + l32]);
+        brl[j] = __builtin_bit_cast(bf16x8, Bs[cur][GP_STG / 2 + g * GB_BN + wn * 64 + j * 32 + l32]);
+        bih[j] = re_to_im8(brh[j]);
+        bil[j] = re_to_im8(brl[j]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], brh[j], acc_re[i][j], 0, 0, 0);
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], brl[j], acc_re[i][j], 0, 0, 0);
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], brh[j], acc_re[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bih[j], acc_im[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bil[j], acc_im[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bih[j], acc_im[i][j], 0, 0, 0);
+        }
+    }
+    if (kt + 1 < S) sstore(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn * 64 + j * 32 + l32;
+      if (col >= N) continue;
+      float2 c[16];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        c[v] = C[min(row, M - 1) * ld + col];
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        if (row < M) C[row * ld + col] = make_float2(c[v].x - acc_re[i][j][v], c[v].y - acc_im[i][j][v]);
+      }
+    }
+}
+
 // ============================================================== GEMM f64
 // Same contraction in float64 on MFMA 16x16x4 f64: one MFMA covers two
 // complex k (four interleaved real k).  64 x 64 tile, 4 waves of 32 x 32.
@@ -1223,6 +1422,9 @@ struct Fac {
   int base = 8;
   int gkind = kGemm4M;           // complex GEMM form for c64 (bem_gemm_kind)
   int nmax = 0;
+  bool use_pack = false;         // trailing updates through the packed bf16x3 GEMM
+  void* pack = nullptr;          // packing buffer (context-owned) and its size
+  size_t pack_bytes = 0;
 
   size_t esz() const { return prec == BEM_C128 ? 16 : 8; }
 
@@ -1358,6 +1560,85 @@ struct Fac {
                return es * (m * K + (double)K * nn + 2.0 * m * nn);
              }));
   }
+  // matrices [b0, b1) of the concatenation of G's groups
+  static LuGroups slice(const LuGroups& G, int b0, int b1, size_t es) {
+    LuGroups S{};
+    S.ng = 0;
+    int base = 0;
+    for (int i = 0; i < G.ng; ++i) {
+      const LuGroup& g = G.g[i];
+      const int lo = std::max(b0, base), hi = std::min(b1, base + g.count);
+      if (lo < hi) {
+        LuGroup t = g;
+        const int off = lo - base;
+        t.A = (char*)g.A + (size_t)off * g.stride * es;
+        t.piv = g.piv + (size_t)off * g.n;
+        t.info = g.info + off;
+        t.count = hi - lo;
+        S.g[S.ng++] = t;
+      }
+      base += g.count;
+    }
+    return S;
+  }
+  // packing buffer bytes that would let every trailing update run in one slice
+  size_t pack_need(int nb) const {
+    size_t need = 0;
+    for (int c = 0; c < nmax; c += nb) {
+      const int e = std::min(c + nb, nmax);
+      int total, maxn;
+      active(e, &total, &maxn);
+      if (total == 0) continue;
+      need = std::max(need, (size_t)pack_words(maxn - e, maxn - e, e - c) * 16 * total);
+    }
+    return need;
+  }
+  // C -= A B through the pre-split operands, in slices of the batch that fit
+  // the packing buffer; false (nothing launched) when not even one matrix fits
+  // or the update is narrow enough for the narrow kernel
+  bool gemm_packed(int rowC, int colC, int colA, int rowB, int rowEnd, int colEnd, int K) {
+    if (K <= 0) return true;
+    int total, maxn;
+    const LuGroups G = active(std::max(rowC, colC), &total, &maxn);
+    if (total == 0) return true;
+    const int M = std::min(rowEnd, maxn) - rowC, N = std::min(colEnd, maxn) - colC;
+    if (M <= 0 || N <= 0) return true;
+    if (N <= 64) return false;
+    const size_t per = (size_t)pack_words(M, N, K) * 16;
+    const int fit = (int)std::min<size_t>((size_t)total, pack ? pack_bytes / per : 0);
+    if (fit <= 0) return false;
+    const int tiles_m = (M + GB_BM - 1) / GB_BM, tiles_n = (N + GB_BN - 1) / GB_BN;
+    const int S = (K + GB_KB - 1) / GB_KB;
+    const int64_t a_ms = (int64_t)tiles_m * S * GP_STG, b_ms = (int64_t)tiles_n * S * GP_STG;
+    uint4* Ap = (uint4*)pack;
+    uint4* Bp = Ap + a_ms * fit;
+    const int64_t ta = (int64_t)tiles_m * S * (GP_STG / 2), tb = (int64_t)tiles_n * S * (GP_STG / 2);
+    const int gx = (tiles_m * tiles_n + 7) / 8 * 8;
+    for (int b0 = 0; b0 < total; b0 += fit) {
+      const int nbat = std::min(fit, total - b0);
+      const LuGroups Gs = slice(G, b0, b0 + nbat, esz());
+      double mk = 0.0, kn = 0.0, mn = 0.0;
+      for (int i = 0; i < Gs.ng; ++i) {
+        const double m = std::max(0, std::min(rowEnd, Gs.g[i].n) - rowC);
+        const double nn = std::max(0, std::min(colEnd, Gs.g[i].n) - colC);
+        mk += m * K * Gs.g[i].count;
+        kn += nn * K * Gs.g[i].count;
+        mn += m * nn * Gs.g[i].count;
+      }
+      int pi = prof_begin(ctx, "pack");
+      hipLaunchKernelGGL(pack_a_kernel, dim3((unsigned)((ta + 255) / 256), nbat), dim3(256), 0,
+                         ctx->stream, Gs, rowC, colA, rowEnd, K, tiles_m, a_ms, Ap);
+      hipLaunchKernelGGL(pack_b_kernel, dim3((unsigned)((tb + 255) / 256), nbat), dim3(256), 0,
+                         ctx->stream, Gs, rowB, colC, colEnd, K, tiles_n, b_ms, Bp);
+      // float32 operands read, split words written (8 bytes per complex element each way)
+      prof_end(ctx, "pack", pi, 0.0, 16.0 * (mk + kn));
+      pi = prof_begin(ctx, "gemm_b3_packed");
+      hipLaunchKernelGGL(gemm_c32_b3p_kernel, dim3(gx, nbat), dim3(256), 0, ctx->stream, Gs, rowC,
+                         colC, rowEnd, colEnd, K, tiles_m, tiles_n, Ap, a_ms, Bp, b_ms);
+      prof_end(ctx, "gemm_b3_packed", pi, 8.0 * mn * K, 8.0 * (mk + kn + 2.0 * mn));
+    }
+    return true;
+  }
   // X = L^{-1} X for rows [r0, r0+m1) and columns [col0, col1)
   void trsm(int r0, int m1, int col0, int col1) {
     if (col1 <= col0 || m1 <= 1) return;
@@ -1408,7 +1689,8 @@ struct Fac {
       rec(c, e);
       laswp(c, e, 0, c, e, nmax);
       trsm(c, e - c, e, nmax);
-      gemm(e, e, c, c, INT32_MAX, nmax, e - c);
+      if (!(use_pack && gemm_packed(e, e, c, c, INT32_MAX, nmax, e - c)))
+        gemm(e, e, c, c, INT32_MAX, nmax, e - c);
     }
   }
 };
@@ -1427,13 +1709,15 @@ int lu_plan_nb(bem_ctx* ctx, bem_prec prec, int gemm_kind, int n) {
   return it != ctx->tuned_nb.end() ? it->second : lu_default_nb(prec, n);
 }
 
-bem_status lu_factor_groups(bem_ctx* ctx, bem_prec prec, const std::vector<LuMatrixSet>& sets,
-                            const LuPlan& plan, int gemm_kind) {
-  Fac f;
+// Validate the sets and set up the driver: groups sorted by size, base panel
+// width and top-level block width.
+static bem_status build_fac(bem_ctx* ctx, bem_prec prec, const std::vector<LuMatrixSet>& sets,
+                            const LuPlan& plan, int gemm_kind, Fac& f, int& nb) {
   f.ctx = ctx;
   f.prec = prec;
   f.plan = plan;
-  f.gkind = prec == BEM_C64 ? gemm_kind : kGemm4M;
+  f.gkind = prec == BEM_C64 ? (gemm_kind == kGemmBf16x3Unpacked ? kGemmBf16x3 : gemm_kind) : kGemm4M;
+  f.use_pack = prec == BEM_C64 && gemm_kind == kGemmBf16x3;
   for (const LuMatrixSet& s : sets) {
     if (s.count <= 0 || s.n <= 0) continue;
     if (s.n > 24 * kPanelThreads)
@@ -1451,8 +1735,6 @@ bem_status lu_factor_groups(bem_ctx* ctx, bem_prec prec, const std::vector<LuMat
     g.n = s.n;
     g.count = s.count;
     f.groups.push_back(g);
-    hipLaunchKernelGGL(fill_i32_kernel, dim3((s.count + 255) / 256), dim3(256), 0, ctx->stream,
-                       (int64_t)s.count, s.info, 0);
   }
   if (f.groups.empty()) return BEM_OK;
   if ((int)f.groups.size() > kMaxGroups)
@@ -1464,7 +1746,52 @@ bem_status lu_factor_groups(bem_ctx* ctx, bem_prec prec, const std::vector<LuMat
   else f.base = rows_per_thread <= 11 ? 8 : 4;
   if (plan.base > 0 && plan.base < f.base) f.base = plan.base;
   // block width (the interchange passes are split into ranges of kSwapRows rows)
-  const int nb = plan.nb > 0 ? std::min(plan.nb, 4 * kSwapRows) : kSwapRows;
+  nb = plan.nb > 0 ? std::min(plan.nb, 4 * kSwapRows) : kSwapRows;
+  return BEM_OK;
+}
+
+// Grow the context's packing buffer towards what the factorisation would use
+// (at most pack_cap); on allocation failure the buffer stays empty and the
+// trailing updates take the unpacked kernel.
+static size_t pack_cap(const bem_ctx* ctx) {
+  return ctx->ws_limit ? std::min<size_t>(kPackLimit, ctx->ws_limit / 4) : kPackLimit;
+}
+static void reserve_pack(bem_ctx* ctx, const Fac& f, int nb) {
+  const size_t want = std::min(f.pack_need(nb), pack_cap(ctx));
+  if (want <= ctx->pack_size) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  drop_graphs(ctx);   // captured factorisations point into the old buffer
+  if (ctx->pack) (void)hipFree(ctx->pack);
+  ctx->pack = nullptr;
+  ctx->pack_size = 0;
+  if (hipMalloc(&ctx->pack, want) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->pack = nullptr;
+    return;
+  }
+  ctx->pack_size = want;
+}
+
+static bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
+bem_status lu_factor_groups(bem_ctx* ctx, bem_prec prec, const std::vector<LuMatrixSet>& sets,
+                            const LuPlan& plan, int gemm_kind) {
+  Fac f;
+  int nb = 0;
+  bem_status st = build_fac(ctx, prec, sets, plan, gemm_kind, f, nb);
+  if (st != BEM_OK || f.groups.empty()) return st;
+  for (const LuGroup& g : f.groups)
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((g.count + 255) / 256), dim3(256), 0, ctx->stream,
+                       (int64_t)g.count, g.info, 0);
+  if (f.use_pack) {
+    // under capture the buffer was reserved before the capture began
+    if (!capturing(ctx->stream)) reserve_pack(ctx, f, nb);
+    f.pack = ctx->pack;
+    f.pack_bytes = std::min(ctx->pack_size, pack_cap(ctx));
+  }
   f.blocked(nb);
   BEM_CHECK_LAUNCH(ctx);
   return BEM_OK;
@@ -1571,6 +1898,14 @@ bem_status lu_factor_groups_graph(bem_ctx* ctx, bem_prec prec, const std::vector
       BEM_HIP_TRY(ctx, hipGraphLaunch(g.exec, ctx->stream));
       return BEM_OK;
     }
+  {
+    // the packing buffer must exist before capture (no allocation while capturing)
+    Fac f;
+    int nb = 0;
+    const bem_status st = build_fac(ctx, prec, sets, plan, gemm_kind, f, nb);
+    if (st != BEM_OK) return st;
+    if (!f.groups.empty() && f.use_pack) reserve_pack(ctx, f, nb);
+  }
   if (!ctx->capture_stream)
     BEM_HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
   // record the launch sequence on the side stream (nothing executes), then

@@ -19,7 +19,7 @@ BEM_OK, BEM_EINVAL, BEM_ENOMEM, BEM_EHIP, BEM_ESINGULAR, BEM_ENOCONV, BEM_EUNSUP
 BEM_C64, BEM_C128 = 0, 1
 BEM_BC_HARD, BEM_BC_SOFT = 0, 1
 BEM_FP64_DIRECT, BEM_FP32_IR_4M, BEM_FP32_IR_3M, BEM_FP32_IR_B3 = 0, 1, 2, 3
-BEM_GEMM_4M, BEM_GEMM_3M, BEM_GEMM_BF16X3 = 0, 1, 2
+BEM_GEMM_4M, BEM_GEMM_3M, BEM_GEMM_BF16X3, BEM_GEMM_BF16X3_UNPACKED = 0, 1, 2, 3
 PULSE_KINDS = {"paper": 0, "gauss": 1, "ricker": 2, "nwave": 3, "chirp": 4, "gsine": 5, "gaussk": 6}
 
 EXPORTED = [

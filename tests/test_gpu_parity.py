@@ -206,6 +206,33 @@ def test_getrf_3m_and_split_gemm(ctx, n, kind):
             assert bwd < 3e-5
 
 
+@pytest.mark.parametrize("n,nb,batch,limit", [
+    (777, 64, 3, 0),                     # every trailing update in one packed launch
+    (1100, 256, 5, 4 * 8 * 1024 * 1024),  # 8 MiB packing buffer: batches packed in slices
+    (530, 128, 2, 4096),                 # buffer too small for one matrix: unpacked kernel
+])
+def test_packed_trailing_update_matches_unpacked(ctx, n, nb, batch, limit):
+    """The pre-split operands feed the same products in the same order, so the
+    factors and pivots equal those of the unpacked kernel bit for bit, with a
+    ragged last tile and block, in slices, and when nothing can be packed."""
+    rng = np.random.default_rng(n + nb)
+    M = seeded_complex(rng, (batch, n, n)) + 0.5 * np.sqrt(n) * np.eye(n)[None]
+    out = {}
+    ctx.set_workspace_limit(limit)
+    try:
+        for kind in (native.BEM_GEMM_BF16X3, native.BEM_GEMM_BF16X3_UNPACKED):
+            A = dev(M, torch.complex64)
+            piv = torch.zeros((batch, n), dtype=torch.int32, device="cuda")
+            info = torch.ones(batch, dtype=torch.int32, device="cuda")
+            native.bem_getrf_batched(ctx, native.BEM_C64, n, n, n * n, batch, A, piv, info, nb, kind)
+            out[kind] = (A.cpu().numpy(), piv.cpu().numpy(), info.cpu().numpy())
+    finally:
+        ctx.set_workspace_limit(0)
+    a, b = out[native.BEM_GEMM_BF16X3], out[native.BEM_GEMM_BF16X3_UNPACKED]
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2]) and not a[2].any()
+    assert np.array_equal(a[0].view(np.uint32), b[0].view(np.uint32))
+
+
 def test_autotune_block_width_then_factor(ctx):
     """The tuner times each candidate width on pseudo-random matrices and keeps
     the fastest for the size class; a later nb = 0 factorisation of that class
