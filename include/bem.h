@@ -164,8 +164,9 @@ typedef enum {
 } bem_mode;
 
 /* complex GEMM form of a c64 factorisation (last argument of bem_getrf_batched).
- * BEM_GEMM_BF16X3 runs the trailing update of each block column on operands
- * split once into bf16 words by a packing pass (the context keeps a packing
+ * BEM_GEMM_BF16X3 runs the updates of at least 512 x 512 (the trailing update
+ * of each block column among them) on operands split once into bf16 words by
+ * a packing pass (the context keeps a packing
  * buffer of at most 4 GiB and packs larger batches in slices; if it cannot be
  * allocated the unpacked kernel runs).  BEM_GEMM_BF16X3_UNPACKED is the same
  * arithmetic, bit for bit, with the split done inside every GEMM tile and no
@@ -187,7 +188,10 @@ typedef struct {
 
 typedef struct {
   int32_t mode;           /* bem_mode */
-  double tol_step;        /* stop when ||dx||_2/||x||_2 <= tol_step (default 1e-8) */
+  double tol_step;        /* stop an item when ||dx||_2/||x||_2 <= tol_step (x is then kept
+                             without dx), or when the ratio rho < 1/2 of the last two
+                             correction norms bounds the error left after applying dx by
+                             rho/(1-rho) ||dx||_2/||x+dx||_2 <= tol_step (default 1e-8) */
   int32_t max_iter;       /* refinement sweeps (default 10) */
   int32_t fallback;       /* 1: re-solve non-converged items in FP64 */
   int32_t use_graph;      /* 1 (default): replay the factorisation as a hipGraph captured

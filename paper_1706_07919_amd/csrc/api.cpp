@@ -511,16 +511,21 @@ bem_status solve_fp64_chunk(SolveRun& R, const Chunk& c, int k0, int kc, int64_t
 bem_status chunk_finish_ir(SolveRun& R, const Chunk& c, int k0, int kc, int64_t ld,
                            std::vector<int>& unconverged) {
   // Refinement: x_0 = 0, r_0 = b; each sweep solves d = LU^{-1} r (float32,
-  // scaled), and stops an item when ||d|| / ||x + d|| <= tol_step; otherwise
-  // x += d and r = b - A x is evaluated in float64.  The returned x of a
-  // converged item is its last iterate whose float64 residual is known (the
-  // final correction only certifies it), so rel_resid needs no extra pass.
+  // scaled).  An item stops
+  //  - when ||d|| / ||x + d|| <= tol_step: x is kept without this last
+  //    correction (its float64 residual is already known), or
+  //  - when the contraction rho = ||d_i|| / ||d_{i-1}|| < 1/2 bounds the error
+  //    left after applying d by rho / (1 - rho) * ||d|| / ||x + d|| <= tol_step
+  //    (geometric convergence): x += d and its residual is evaluated for the
+  //    report, with no further sweep.
+  // Otherwise x += d and r = b - A x is evaluated in float64.
   bem_ctx* ctx = R.ctx;
   const bem_surface* s = R.pr->s;
   const int n = s->n, nr = R.pr->n_rhs;
   const int nv = kc * nr;
   const double2* y = (const double2*)R.pr->y + (size_t)k0 * nr * n;
   const double* kk = R.pr->k + k0;
+  const double tol = R.o->tol_step;
   bem_status st;
   if ((st = lu_perm(ctx, n, kc, c.piv, c.perm)) != BEM_OK) return st;
   if ((st = fill_zero(ctx, c.x, (size_t)nv * n * 16)) != BEM_OK) return st;
@@ -532,8 +537,10 @@ bem_status chunk_finish_ir(SolveRun& R, const Chunk& c, int k0, int kc, int64_t 
   double* h_rn = h_xn + nv;
   int32_t* h_info = (int32_t*)(h_rn + nv);
   uint8_t* h_act = (uint8_t*)(h_info + kc);
-  std::vector<uint8_t> act(nv, 1), fresh(nv, 1);   // fresh: residual of the current x known
-  std::vector<double> step(nv, 1.0), bn(nv, 0.0), rn(nv, 0.0);
+  // act: takes another sweep; fin: stops once the current correction is applied;
+  // fresh: the float64 residual of the current x has been evaluated
+  std::vector<uint8_t> act(nv, 1), fin(nv, 0), fresh(nv, 1);
+  std::vector<double> step(nv, 1.0), bn(nv, 0.0), dprev(nv, 0.0);
   std::vector<int> iters(nv, 0);
   BEM_HIP_TRY(ctx, hipMemcpyAsync(h_info, c.info, 4 * kc, hipMemcpyDeviceToHost, ctx->stream));
   const double2* rsrc = c.b;
@@ -549,37 +556,54 @@ bem_status chunk_finish_ir(SolveRun& R, const Chunk& c, int k0, int kc, int64_t 
       return st;
     BEM_HIP_TRY(ctx, hipMemcpyAsync(h_dn, c.dn2, 8 * nv, hipMemcpyDeviceToHost, ctx->stream));
     BEM_HIP_TRY(ctx, hipMemcpyAsync(h_xn, c.xn2, 8 * nv, hipMemcpyDeviceToHost, ctx->stream));
-    BEM_HIP_TRY(ctx, hipMemcpyAsync(h_rn, c.rn2, 8 * nv, hipMemcpyDeviceToHost, ctx->stream));
+    if (it == 0)
+      BEM_HIP_TRY(ctx, hipMemcpyAsync(h_rn, c.rn2, 8 * nv, hipMemcpyDeviceToHost, ctx->stream));
     BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    int live = 0;
+    int more = 0, nfin = 0;
     for (int v = 0; v < nv; ++v) {
       if (!act[v]) continue;
       if (it == 0) bn[v] = h_rn[v];
-      rn[v] = h_rn[v];
       iters[v] = it + 1;
       const double sx = h_xn[v] > 0 ? std::sqrt(h_dn[v] / h_xn[v]) : (h_dn[v] > 0 ? 1.0 : 0.0);
       step[v] = sx;
-      if (it > 0 && !(sx > R.o->tol_step) && std::isfinite(sx)) {
-        act[v] = 0;            // converged: keep x (its residual is rn)
+      if (!std::isfinite(sx)) {
+        ++more;
+        continue;
+      }
+      if (it > 0 && !(sx > tol)) {
+        act[v] = 0;            // converged: keep x
+        continue;
+      }
+      const double rho = it > 0 && dprev[v] > 0 ? std::sqrt(h_dn[v] / dprev[v]) : 1.0;
+      dprev[v] = h_dn[v];
+      if (it > 0 && rho < 0.5 && rho / (1.0 - rho) * sx <= tol) {
+        fin[v] = 1;
+        step[v] = rho / (1.0 - rho) * sx;
+        ++nfin;
       } else {
-        ++live;
+        ++more;
       }
     }
-    if (live == 0) break;
-    // take the correction of the items still refining, then their residual
+    if (more + nfin == 0) break;
+    // take the corrections, then the residual of the new iterates
     std::memcpy(h_act, act.data(), nv);
     BEM_HIP_TRY(ctx, hipMemcpyAsync(c.active, h_act, nv, hipMemcpyHostToDevice, ctx->stream));
     if ((st = launch_ir_update(ctx, nv, n, c.d32, c.scale, c.active, c.x, c.dn2, c.xn2, 1)) != BEM_OK)
       return st;
     for (int v = 0; v < nv; ++v)
       if (act[v]) fresh[v] = 0;
-    if (it + 1 < max_it) {
+    if (nfin > 0 || (more > 0 && it + 1 < max_it)) {
       if ((st = launch_residual(ctx, s, kc, kk, nr, y, c.x, c.diag, c.r)) != BEM_OK) return st;
       if ((st = launch_norm2(ctx, nv, n, c.r, c.rn2)) != BEM_OK) return st;
-      for (int v = 0; v < nv; ++v)
-        if (act[v]) fresh[v] = 1;
+      std::fill(fresh.begin(), fresh.end(), 1);
       rsrc = c.r;
     }
+    for (int v = 0; v < nv; ++v)
+      if (fin[v]) {
+        fin[v] = 0;
+        act[v] = 0;
+      }
+    if (more == 0) break;
   }
   // items that ran out of sweeps with an unevaluated last correction
   bool stale = false;
@@ -587,16 +611,14 @@ bem_status chunk_finish_ir(SolveRun& R, const Chunk& c, int k0, int kc, int64_t 
   if (stale) {
     if ((st = launch_residual(ctx, s, kc, kk, nr, y, c.x, c.diag, c.r)) != BEM_OK) return st;
     if ((st = launch_norm2(ctx, nv, n, c.r, c.rn2)) != BEM_OK) return st;
-    BEM_HIP_TRY(ctx, hipMemcpyAsync(h_rn, c.rn2, 8 * nv, hipMemcpyDeviceToHost, ctx->stream));
-    BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    for (int v = 0; v < nv; ++v)
-      if (!fresh[v]) rn[v] = h_rn[v];
   }
+  // c.rn2 now holds |b - A x|^2 of every item's returned x
+  BEM_HIP_TRY(ctx, hipMemcpyAsync(h_rn, c.rn2, 8 * nv, hipMemcpyDeviceToHost, ctx->stream));
   double2* xo = R.xout + (size_t)k0 * nr * n;
   BEM_HIP_TRY(ctx, hipMemcpyAsync(xo, c.x, (size_t)nv * n * 16, hipMemcpyDeviceToDevice, ctx->stream));
   BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   for (int v = 0; v < nv; ++v) {
-    const bool conv = !act[v] && h_info[v / nr] == 0;
+    const bool conv = !act[v] && h_info[v / nr] == 0 && std::isfinite(step[v]);
     if (!conv) unconverged.push_back(k0 + v / nr);
     if (R.info) {
       bem_solve_info& I = R.info[(size_t)k0 * nr + v];
@@ -604,7 +626,7 @@ bem_status chunk_finish_ir(SolveRun& R, const Chunk& c, int k0, int kc, int64_t 
       I.used_fp64 = 0;
       I.singular = h_info[v / nr] != 0;
       I.converged = conv ? 1 : 0;
-      I.rel_resid = bn[v] > 0 ? std::sqrt(rn[v] / bn[v]) : 0.0;
+      I.rel_resid = bn[v] > 0 ? std::sqrt(h_rn[v] / bn[v]) : 0.0;
       I.rel_step = step[v];
     }
   }

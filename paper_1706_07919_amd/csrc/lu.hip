@@ -144,7 +144,12 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(LuGroups G, int c0
     for (int c = 0; c < W; ++c)
       a[q][c] = (r < n && c < w) ? Ab[(int64_t)r * ld + c0 + c] : cmk<C>(R(0), R(0));
   }
-  for (int c = 0; c < w; ++c) {
+  // The column loop is unrolled so that every register index is static.  Row
+  // c0 + c is held by thread c in slot 0; a row r > c0 + c is below the
+  // diagonal unless it sits in slot 0 of a thread t <= c.
+#pragma unroll
+  for (int c = 0; c < W; ++c) {
+    if (c >= w) break;
     const int pr = c0 + c;
     const int buf = c & 1;
     // candidate of this thread, then of its wave
@@ -153,12 +158,8 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(LuGroups G, int c0
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       const int r = c0 + t + q * NT;
-      C v = a[q][0];
-#pragma unroll
-      for (int cc = 1; cc < W; ++cc)
-        if (cc == c) v = a[q][cc];
-      const R m = fabs(v.x) + fabs(v.y);
-      if (r >= pr && r < n && m > best) { best = m; bidx = r; }
+      const R m = fabs(a[q][c].x) + fabs(a[q][c].y);
+      if ((q > 0 || t >= c) && r < n && m > best) { best = m; bidx = r; }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -181,50 +182,43 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(LuGroups G, int c0
       piv[(int64_t)b * n + pr] = p;
     }
     // the owners of rows p and pr publish them
+    const int op = (p - c0) % NT, qp = (p - c0) / NT;
+    if (t == op) {
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r = c0 + t + q * NT;
-      if (r == p)
+      for (int q = 0; q < RPT; ++q)
+        if (q == qp)
 #pragma unroll
-        for (int cc = 0; cc < W; ++cc) pivrow[buf][cc] = a[q][cc];
-      if (r == pr && p != pr)
-#pragma unroll
-        for (int cc = 0; cc < W; ++cc) toprow[buf][cc] = a[q][cc];
+          for (int cc = 0; cc < W; ++cc) pivrow[buf][cc] = a[q][cc];
     }
+    if (t == c && p != pr)
+#pragma unroll
+      for (int cc = 0; cc < W; ++cc) toprow[buf][cc] = a[0][cc];
     __syncthreads();
     if (p != pr) {
+      if (t == op) {
 #pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        const int r = c0 + t + q * NT;
-        if (r == p)
+        for (int q = 0; q < RPT; ++q)
+          if (q == qp)
 #pragma unroll
-          for (int cc = 0; cc < W; ++cc) a[q][cc] = toprow[buf][cc];
-        if (r == pr)
-#pragma unroll
-          for (int cc = 0; cc < W; ++cc) a[q][cc] = pivrow[buf][cc];
+            for (int cc = 0; cc < W; ++cc) a[q][cc] = toprow[buf][cc];
       }
+      if (t == c)
+#pragma unroll
+        for (int cc = 0; cc < W; ++cc) a[0][cc] = pivrow[buf][cc];
     }
     if (!singular) {
       C u[W];
 #pragma unroll
-      for (int cc = 0; cc < W; ++cc) u[cc] = pivrow[buf][cc];
-      C pv = u[0];
-#pragma unroll
-      for (int cc = 1; cc < W; ++cc)
-        if (cc == c) pv = u[cc];
-      const C inv = crecip(pv);
+      for (int cc = c; cc < W; ++cc) u[cc] = pivrow[buf][cc];
+      const C inv = crecip(u[c]);
+      // rows past n hold zeros and are never stored
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
-        const int r = c0 + t + q * NT;
-        if (r > pr && r < n) {
-          C l = cmk<C>(R(0), R(0));
+        if (q == 0 && t <= c) continue;
+        const C l = cmul(a[q][c], inv);
+        a[q][c] = l;
 #pragma unroll
-          for (int cc = 0; cc < W; ++cc)
-            if (cc == c) { l = cmul(a[q][cc], inv); a[q][cc] = l; }
-#pragma unroll
-          for (int cc = 0; cc < W; ++cc)
-            if (cc > c) a[q][cc] = csub(a[q][cc], cmul(l, u[cc]));
-        }
+        for (int cc = c + 1; cc < W; ++cc) a[q][cc] = csub(a[q][cc], cmul(l, u[cc]));
       }
     }
   }
@@ -968,9 +962,9 @@ __global__ __launch_bounds__(256, 4) void gemm_c32_tsb_kernel(LuGroups G, int ro
 }
 
 // ============================================================== GEMM f32 via bf16 split, packed operands
-// The trailing update after each block column takes its operands split once:
-// a packing pass converts the block column of L below the block (A) and the
-// block row of U right of it (B, in the real-part pattern (Re, -Im)) into bf16
+// Updates of at least 512 x 512 take their operands split once: a packing
+// pass converts A (a block column of L, e.g. below the block just factored)
+// and B (a block row of U, in the real-part pattern (Re, -Im)) into bf16
 // hi/lo words laid out as the GEMM's LDS stage buffers -- per 128-row (or
 // -column) tile and 16-k stage, [hi/lo][k group][row] 16-byte words,
 // zero-padded past the edges.  The GEMM's staging is then a plain 16-byte
@@ -1516,6 +1510,7 @@ struct Fac {
   // C = rows [rowC, rowEnd) x cols [colC, colEnd) -= A(rows, [colA, colA+K)) B([rowB, rowB+K), cols)
   void gemm(int rowC, int colC, int colA, int rowB, int rowEnd, int colEnd, int K) {
     if (K <= 0) return;
+    if (use_pack && gemm_packed(rowC, colC, colA, rowB, rowEnd, colEnd, K)) return;
     int total, maxn;
     const LuGroups G = active(std::max(rowC, colC), &total, &maxn);
     if (total == 0) return;
@@ -1594,8 +1589,8 @@ struct Fac {
     return need;
   }
   // C -= A B through the pre-split operands, in slices of the batch that fit
-  // the packing buffer; false (nothing launched) when not even one matrix fits
-  // or the update is narrow enough for the narrow kernel
+  // the packing buffer; false (nothing launched) when not even one matrix
+  // fits or the update is too small for packing to pay
   bool gemm_packed(int rowC, int colC, int colA, int rowB, int rowEnd, int colEnd, int K) {
     if (K <= 0) return true;
     int total, maxn;
@@ -1603,7 +1598,9 @@ struct Fac {
     if (total == 0) return true;
     const int M = std::min(rowEnd, maxn) - rowC, N = std::min(colEnd, maxn) - colC;
     if (M <= 0 || N <= 0) return true;
-    if (N <= 64) return false;
+    // each packed operand must be read by at least four tiles to repay its
+    // pass (measured: at two or three, the pass costs more than it saves)
+    if (M < 4 * GB_BM || N < 4 * GB_BN) return false;
     const size_t per = (size_t)pack_words(M, N, K) * 16;
     const int fit = (int)std::min<size_t>((size_t)total, pack ? pack_bytes / per : 0);
     if (fit <= 0) return false;
@@ -1689,8 +1686,7 @@ struct Fac {
       rec(c, e);
       laswp(c, e, 0, c, e, nmax);
       trsm(c, e - c, e, nmax);
-      if (!(use_pack && gemm_packed(e, e, c, c, INT32_MAX, nmax, e - c)))
-        gemm(e, e, c, c, INT32_MAX, nmax, e - c);
+      gemm(e, e, c, c, INT32_MAX, nmax, e - c);
     }
   }
 };
