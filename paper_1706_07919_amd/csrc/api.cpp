@@ -185,6 +185,7 @@ struct Chunk {
   double* xn2;     // [kc*nr]
   double* rn2;     // [kc*nr] |r|^2 of the last evaluated residual
   uint8_t* active; // [kc*nr]
+  void* rparts;    // residual partial sums (refinement chunks only)
 };
 
 Chunk carve(void* base, int n, int64_t ld, int nr, int kc, bool c128, size_t* used = nullptr);
@@ -220,6 +221,7 @@ Chunk carve(void* base, int n, int64_t ld, int nr, int kc, bool c128, size_t* us
   c.xn2 = (double*)take((size_t)kc * nr * 8);
   c.rn2 = (double*)take((size_t)kc * nr * 8);
   c.active = (uint8_t*)take((size_t)kc * nr);
+  c.rparts = c128 ? nullptr : take(residual_parts_bytes(n, kc, nr));
   if (used) *used = (size_t)(p - (char*)base);
   return c;
 }
@@ -445,6 +447,7 @@ struct SolveRun {
   const bem_solve_opts* o;
   double2* xout;
   bem_solve_info* info;  // [n_k * n_rhs] for this problem, or NULL
+  std::vector<double> hk;  // the wavenumbers, host copy
 };
 
 bem_status chunk_assemble(SolveRun& R, const Chunk& c, int k0, int kc, int64_t ld, bem_prec prec) {
@@ -527,6 +530,8 @@ bem_status chunk_finish_ir(SolveRun& R, const Chunk& c, int k0, int kc, int64_t 
   const double* kk = R.pr->k + k0;
   const double tol = R.o->tol_step;
   bem_status st;
+  // the residual passes advance phases along the wavenumbers when they form an even grid
+  const double dk = even_grid_step(R.hk.data() + k0, kc);
   if ((st = lu_perm(ctx, n, kc, c.piv, c.perm)) != BEM_OK) return st;
   if ((st = fill_zero(ctx, c.x, (size_t)nv * n * 16)) != BEM_OK) return st;
   if ((st = launch_norm2(ctx, nv, n, c.b, c.rn2)) != BEM_OK) return st;   // r_0 = b
@@ -593,7 +598,7 @@ bem_status chunk_finish_ir(SolveRun& R, const Chunk& c, int k0, int kc, int64_t 
     for (int v = 0; v < nv; ++v)
       if (act[v]) fresh[v] = 0;
     if (nfin > 0 || (more > 0 && it + 1 < max_it)) {
-      if ((st = launch_residual(ctx, s, kc, kk, nr, y, c.x, c.diag, c.r)) != BEM_OK) return st;
+      if ((st = launch_residual_b(ctx, s, kc, kk, dk, nr, y, c.b, c.x, c.diag, c.r, c.rparts)) != BEM_OK) return st;
       if ((st = launch_norm2(ctx, nv, n, c.r, c.rn2)) != BEM_OK) return st;
       std::fill(fresh.begin(), fresh.end(), 1);
       rsrc = c.r;
@@ -609,7 +614,7 @@ bem_status chunk_finish_ir(SolveRun& R, const Chunk& c, int k0, int kc, int64_t 
   bool stale = false;
   for (int v = 0; v < nv; ++v) stale = stale || !fresh[v];
   if (stale) {
-    if ((st = launch_residual(ctx, s, kc, kk, nr, y, c.x, c.diag, c.r)) != BEM_OK) return st;
+    if ((st = launch_residual_b(ctx, s, kc, kk, dk, nr, y, c.b, c.x, c.diag, c.r, c.rparts)) != BEM_OK) return st;
     if ((st = launch_norm2(ctx, nv, n, c.r, c.rn2)) != BEM_OK) return st;
   }
   // c.rn2 now holds |b - A x|^2 of every item's returned x
@@ -699,8 +704,13 @@ extern "C" bem_status bem_solve_batched(bem_ctx* ctx, const bem_problem* probs, 
     plan.nb = o.nb > 0 ? o.nb : lu_plan_nb(ctx, prec, fp64 ? 0 : gk0, nmax);
   }
   std::vector<SolveRun> runs;
-  for (int p = 0; p < n_probs; ++p)
-    runs.push_back(SolveRun{ctx, &probs[p], &o, (double2*)x_out[p], info ? info + info_off[p] : nullptr});
+  for (int p = 0; p < n_probs; ++p) {
+    runs.push_back(SolveRun{ctx, &probs[p], &o, (double2*)x_out[p], info ? info + info_off[p] : nullptr, {}});
+    runs.back().hk.resize(probs[p].n_k);
+    BEM_HIP_TRY(ctx, hipMemcpyAsync(runs.back().hk.data(), probs[p].k, 8 * (size_t)probs[p].n_k,
+                                    hipMemcpyDeviceToHost, ctx->stream));
+  }
+  BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
 
   for (int r = 0; r < rounds; ++r) {
     struct Slice { int p, k0, kc; Chunk c; };

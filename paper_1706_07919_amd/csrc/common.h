@@ -86,6 +86,17 @@ bem_status launch_assemble(bem_ctx*, const bem_surface*, int n_k, const double* 
 bem_status launch_residual(bem_ctx*, const bem_surface*, int n_k, const double* k, int n_rhs,
                            const void* y, const void* x, const void* diag64, void* r,
                            const int32_t* kidx = nullptr, int n_sel = 0);
+// The same residual from the float64 right-hand side b of the assembly
+// (r = b - A x) for wavenumbers on the even grid k_q = k_0 + q dk (dk > 0, as
+// even_grid_step reports); y is used only by the fallback (dk <= 0 or surfaces
+// under 1024 nodes).  parts: device staging of residual_parts_bytes bytes.
+size_t residual_parts_bytes(int n, int n_k, int n_rhs);
+bem_status launch_residual_b(bem_ctx*, const bem_surface*, int n_k, const double* k, double dk,
+                             int n_rhs, const void* y, const void* b, const void* x,
+                             const void* diag64, void* r, void* parts);
+// dk of an even grid k_q = k_0 + q dk (to 4e-16 relative per entry, host
+// values), else 0
+double even_grid_step(const double* k_host, int n_k);
 bem_status launch_split(bem_ctx*, const bem_surface*, int n_k, int n_rhs, const void* x,
                         const void* y, void* phi, void* psi);
 

@@ -11,6 +11,8 @@
 // matrix rows.
 #include "common.h"
 
+#include <cmath>
+
 namespace bem {
 namespace {
 
@@ -25,6 +27,32 @@ __device__ inline double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   return v;
+}
+
+// Wave sums of 8 values by recursive halving: lanes l and l ^ 32 trade halves
+// of the values (each keeps the half picked by bit 5 of its lane), then
+// quarters across 16 and pairs across 8, then the single value left is summed
+// across lanes l ^ 4, l ^ 2, l ^ 1.  Afterwards every lane whose bits 3..5
+// spell q holds the wave sum of value q (10 shuffles instead of 48).
+__device__ inline double wave_reduce8(const double (&v)[8]) {
+  const int lane = threadIdx.x & 63;
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+  double h4[4], h2[2];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const double keep = b5 ? v[4 + m] : v[m], give = b5 ? v[m] : v[4 + m];
+    h4[m] = keep + __shfl_xor(give, 32, 64);
+  }
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const double keep = b4 ? h4[2 + m] : h4[m], give = b4 ? h4[m] : h4[2 + m];
+    h2[m] = keep + __shfl_xor(give, 16, 64);
+  }
+  double h = (b3 ? h2[1] : h2[0]) + __shfl_xor(b3 ? h2[0] : h2[1], 8, 64);
+  h += __shfl_xor(h, 4, 64);
+  h += __shfl_xor(h, 2, 64);
+  h += __shfl_xor(h, 1, 64);
+  return h;
 }
 
 // Block-wide sum of a [R][C] array held per thread; result valid in thread 0.
@@ -282,6 +310,161 @@ __global__ __launch_bounds__(kThreads) void residual_kc_kernel(
   }
 }
 
+// ---------------------------------------------------------------- residual sweep
+// r = b - A x with the float64 right-hand side b of the assembly, for one row
+// i and every wavenumber of the launch per workgroup, for wavenumbers on an
+// even grid k_q = k_0 + q dk (checked on the host).  Thread t holds the pairs
+// (i, j) of its columns and carries e^{i k r_ij} and the step e^{i dk r_ij}
+// in registers from one chunk of kSweepKc wavenumbers to the next; every
+// kReanchor wavenumbers the phases start afresh from the stored k with
+// sincos, which bounds the recurrence's rounding drift (about one rounding
+// per step).  Only the coefficient of the unknown is formed (-w H for a hard
+// node, w G for a soft one).  Chunk partial sums are reduced across the
+// workgroup through a parity-double-buffered LDS array, one barrier per chunk.
+constexpr int kSweepThreads = 512;
+constexpr int kSweepKc = 4;
+constexpr int kReanchor = 64;
+constexpr int kSweepSlots = 6;   // columns per thread and part
+
+// Part p = blockIdx.y covers the columns j = t + kSweepThreads (p JPT + s);
+// part 0 writes r = b - a_ii x_i - (its sum), part p > 0 writes its sum to
+// part_out[p - 1] (subtracted by residual_parts_kernel).
+template <int JPT>
+__global__ __launch_bounds__(kSweepThreads) void residual_sweep_kernel(
+    int n, const double* __restrict__ x, const double* __restrict__ nrm,
+    const double* __restrict__ w, const uint8_t* __restrict__ bc, const double* __restrict__ kv,
+    double dk, int nk, int n_rhs, int rhs, const double2* __restrict__ bvec,
+    const double2* __restrict__ xs, const double2* __restrict__ diag64, double2* __restrict__ r_out,
+    double2* __restrict__ part_out) {
+  constexpr int KC = kSweepKc, NW = kSweepThreads / 64;
+  __shared__ double red[2][NW][KC][2];
+  const int i = blockIdx.x, part = blockIdx.y;
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const int64_t plane = (int64_t)nk * n_rhs * n;
+  const bool hard_i = bc[i] == BEM_BC_HARD;
+  // per slot: r, the coefficient factor cf (coefficient = cf E for a soft node,
+  // cf (-E.x - kr E.y, kr E.x - E.y) for a hard one; 0 for j = i and j >= n),
+  // the clamped column, and the phase state
+  double rr[JPT], cf[JPT];
+  int jj[JPT];
+  unsigned hmask = 0;
+  double2 e[JPT], d[JPT];
+  {
+    const double xi = x[3 * i], yi = x[3 * i + 1], zi = x[3 * i + 2];
+#pragma unroll
+    for (int sl = 0; sl < JPT; ++sl) {
+      const int j = t + (part * JPT + sl) * kSweepThreads;
+      jj[sl] = min(j, n - 1);
+      rr[sl] = 0.0;
+      cf[sl] = 0.0;
+      if (j < n && j != i) {
+        const double dx = x[3 * j] - xi, dy = x[3 * j + 1] - yi, dz = x[3 * j + 2] - zi;
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        const double rinv = 1.0 / r;
+        rr[sl] = r;
+        if (bc[j] == BEM_BC_HARD) {
+          hmask |= 1u << sl;
+          cf[sl] = -w[j] * (dx * nrm[3 * j] + dy * nrm[3 * j + 1] + dz * nrm[3 * j + 2]) *
+                   (rinv * rinv * rinv);
+        } else {
+          cf[sl] = w[j] * rinv;
+        }
+      }
+    }
+  }
+  for (int c0 = 0, chunk = 0; c0 < nk; c0 += KC, ++chunk) {
+    const int kc = min(KC, nk - c0);
+    double kk[KC];
+#pragma unroll
+    for (int q = 0; q < KC; ++q) kk[q] = q < kc ? kv[c0 + q] : 0.0;
+    const bool go_on = c0 % kReanchor != 0;
+    double acc[KC][2];
+#pragma unroll
+    for (int q = 0; q < KC; ++q) { acc[q][0] = 0.0; acc[q][1] = 0.0; }
+    {
+      if (!go_on) {
+        // fresh phases (grid start, a break of the grid, or re-anchoring)
+#pragma clang loop unroll(full)
+        for (int sl = 0; sl < JPT; ++sl) {
+          double sn, cs;
+          sincos(kk[0] * rr[sl], &sn, &cs);
+          e[sl] = make_double2(cs, sn);
+          sincos(dk * rr[sl], &sn, &cs);
+          d[sl] = make_double2(cs, sn);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+#pragma clang loop unroll(full)
+      for (int sl = 0; sl < JPT; ++sl) {
+        const double r = rr[sl];
+        double2 u[KC];
+#pragma unroll
+        for (int q = 0; q < KC; ++q)
+          u[q] = xs[((int64_t)(q < kc ? c0 + q : c0) * n_rhs + rhs) * n + jj[sl]];
+        const bool hard = (hmask >> sl) & 1u;
+#pragma unroll
+        for (int q = 0; q < KC; ++q) {
+          const double2 E = e[sl];
+          e[sl] = cmul(e[sl], d[sl]);
+          const double kr = kk[q] * r;
+          const double2 P = hard ? make_double2(-E.x - kr * E.y, kr * E.x - E.y) : E;
+          const double ax = cf[sl] * P.x, ay = cf[sl] * P.y;
+          acc[q][0] += ax * u[q].x - ay * u[q].y;
+          acc[q][1] += ax * u[q].y + ay * u[q].x;
+        }
+        // keep the loads of one slot together (bounds the live registers)
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    const int buf = chunk & 1;
+    static_assert(KC * 2 == 8, "the chunk reduction sums 8 values per thread");
+    {
+      double v8[8];
+#pragma unroll
+      for (int q = 0; q < KC; ++q) { v8[2 * q] = acc[q][0]; v8[2 * q + 1] = acc[q][1]; }
+      const double v = wave_reduce8(v8);
+      if ((lane & 7) == 0) {
+        const int idx = lane >> 3;   // value index q * 2 + c
+        red[buf][wid][idx >> 1][idx & 1] = v;
+      }
+    }
+    __syncthreads();
+    if (t == 0) {
+#pragma unroll
+      for (int q = 0; q < KC; ++q) {
+        if (q >= kc) break;
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int v = 0; v < NW; ++v) { s0 += red[buf][v][q][0]; s1 += red[buf][v][q][1]; }
+        const int64_t kq = c0 + q;
+        const int64_t o = (kq * n_rhs + rhs) * n + i;
+        if (part > 0) {
+          part_out[(part - 1) * plane + o] = make_double2(s0, s1);
+        } else {
+          const double2 aii = diag64[(kq * n + i) * 2 + (hard_i ? 0 : 1)];
+          const double2 u = xs[o], bb = bvec[o];
+          const double2 au = cmul(aii, u);
+          r_out[o] = make_double2(bb.x - (s0 + au.x), bb.y - (s1 + au.y));
+        }
+      }
+    }
+  }
+}
+
+// r -= sum of the partial sums of parts 1..nparts-1
+__global__ void residual_parts_kernel(int64_t plane, int nparts, const double2* __restrict__ part_out,
+                                      double2* __restrict__ r_out) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= plane) return;
+  double2 v = r_out[o];
+  for (int p = 1; p < nparts; ++p) {
+    const double2 s = part_out[(int64_t)(p - 1) * plane + o];
+    v.x -= s.x;
+    v.y -= s.y;
+  }
+  r_out[o] = v;
+}
+
 __global__ void incident_kernel(int n, const double* __restrict__ x, const double* __restrict__ nrm,
                                 const uint8_t* __restrict__ bc, const double* __restrict__ kv,
                                 double dx, double dy, double dz, double2* __restrict__ y) {
@@ -406,6 +589,52 @@ bem_status launch_residual(bem_ctx* ctx, const bem_surface* s, int n_k, const do
       BEM_CHECK_LAUNCH(ctx);
     }
   }
+  return BEM_OK;
+}
+
+double even_grid_step(const double* k, int n_k) {
+  if (n_k < 2) return 0.0;
+  const double dk = (k[n_k - 1] - k[0]) / (n_k - 1);
+  if (!(dk > 0.0)) return 0.0;
+  for (int q = 0; q < n_k; ++q)
+    if (!(std::fabs(k[q] - (k[0] + q * dk)) <= 4e-16 * std::fabs(k[q]))) return 0.0;
+  return dk;
+}
+
+// r = b - A x through the sweep kernel: ceil(N / 3072) parts per row, the
+// partial sums of parts past the first staged in `parts` (residual_parts_bytes);
+// surfaces under 1024 nodes and wavenumbers off an even grid (dk <= 0) take
+// residual_kc_kernel with the known data y.
+int residual_parts(int n) { return (n + kSweepSlots * kSweepThreads - 1) / (kSweepSlots * kSweepThreads); }
+
+size_t residual_parts_bytes(int n, int n_k, int n_rhs) {
+  if (n < 1024) return 0;
+  return (size_t)(residual_parts(n) - 1) * n_k * n_rhs * n * 16;
+}
+
+bem_status launch_residual_b(bem_ctx* ctx, const bem_surface* s, int n_k, const double* k,
+                             double dk, int n_rhs, const void* y, const void* b, const void* x,
+                             const void* diag64, void* r, void* parts) {
+  if (s->n < 1024 || !(dk > 0.0)) return launch_residual(ctx, s, n_k, k, n_rhs, y, x, diag64, r);
+  const int np = residual_parts(s->n);
+  if (np > 65535 || (np > 1 && !parts))
+    return fail(ctx, BEM_EINVAL, "residual: %d parts need a staging buffer", np);
+  const int64_t plane = (int64_t)n_k * n_rhs * s->n;
+  const int pi = prof_begin(ctx, "residual");
+  for (int rh = 0; rh < n_rhs; ++rh)
+    hipLaunchKernelGGL((residual_sweep_kernel<kSweepSlots>), dim3(s->n, np), dim3(kSweepThreads), 0,
+                       ctx->stream, s->n, s->x, s->nrm, s->w, s->bc, k, dk, n_k, n_rhs, rh,
+                       reinterpret_cast<const double2*>(b), reinterpret_cast<const double2*>(x),
+                       reinterpret_cast<const double2*>(diag64), reinterpret_cast<double2*>(r),
+                       reinterpret_cast<double2*>(parts));
+  if (np > 1)
+    hipLaunchKernelGGL(residual_parts_kernel, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0,
+                       ctx->stream, plane, np, reinterpret_cast<const double2*>(parts),
+                       reinterpret_cast<double2*>(r));
+  // one complex multiply-add per pair; x read once per pair from L2
+  prof_end(ctx, "residual", pi, 8.0 * s->n * s->n * (double)n_k * n_rhs,
+           16.0 * s->n * s->n * (double)n_k * n_rhs);
+  BEM_CHECK_LAUNCH(ctx);
   return BEM_OK;
 }
 

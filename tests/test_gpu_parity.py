@@ -524,3 +524,39 @@ def test_synthesis_vs_oracle(ctx, T, n_k, add):
     for q in range(2):
         ref = opulse.synthesize(U.astype(np.complex128), c[q], T, xp, dk, add_incident=bool(add))
         assert rel(got[q], ref) < 1e-5, rel(got[q], ref)
+
+
+@pytest.mark.parametrize("levels,nk", [((3, 3), 70), ((4, 3), 9)])
+def test_residual_sweep_on_even_grid(ctx, levels, nk):
+    """Refinement residuals on an even wavenumber grid (phases carried across
+    the grid, r = b - A x; 70 wavenumbers re-anchor past 64 and end on a ragged
+    chunk; 3204 nodes split each row into two parts) converge to the same
+    solutions as the same wavenumbers in scattered order (one sincos per pair
+    and wavenumber), and to the FP64 oracle."""
+    bodies = [Body((0.0, 0.0, -1.6), 1.0, 1.0, levels[0], HARD),
+              Body((0.2, 0.0, 1.7), 0.9, 1.0, levels[1], SOFT)]
+    ds = DeviceSurface.from_bodies(bodies)
+    n = ds.n
+    assert n >= 1024
+    k = 0.3 + 0.11 * np.arange(nk)
+    perm = np.random.default_rng(nk).permutation(nk)
+    out = []
+    for kk in (k, k[perm]):
+        kd = dev(kk)
+        y = torch.empty((nk, 1, n), dtype=torch.complex128, device="cuda")
+        native.bem_incident(ctx, ds.struct, nk, kd, (0.0, 0.0, 1.0), y)
+        x = torch.zeros((nk, 1, n), dtype=torch.complex128, device="cuda")
+        info = native.bem_solve_batched(ctx, [(ds.struct, nk, kd, 1, y)],
+                                        native.bem_solve_opts_default(), [x])
+        for q in range(nk):
+            assert info[q].converged == 1 and info[q].used_fp64 == 0 and info[q].rel_resid < 1e-9
+        out.append(x.cpu().numpy()[:, 0])
+    even, scattered = out[0], np.empty_like(out[1])
+    scattered[perm] = out[1]
+    for q in range(nk):
+        assert rel(even[q], scattered[q]) < 1e-8
+    s = Surface(bodies)
+    q = nk // 2
+    p, dp = bie.incident_plane_wave(s, k[q])
+    _, _, xs = bie.solve(s, k[q], bie.known_data(s, p, dp))
+    assert rel(even[q], xs) < 1e-8
