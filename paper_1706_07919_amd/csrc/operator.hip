@@ -321,7 +321,7 @@ __global__ __launch_bounds__(kThreads) void residual_kc_kernel(
 // per step).  Only the coefficient of the unknown is formed (-w H for a hard
 // node, w G for a soft one).  Chunk partial sums are reduced across the
 // workgroup through a parity-double-buffered LDS array, one barrier per chunk.
-constexpr int kSweepThreads = 512;
+constexpr int kSweepThreads = 256;
 constexpr int kSweepKc = 4;
 constexpr int kReanchor = 64;
 constexpr int kSweepSlots = 6;   // columns per thread and part
@@ -601,7 +601,7 @@ double even_grid_step(const double* k, int n_k) {
   return dk;
 }
 
-// r = b - A x through the sweep kernel: ceil(N / 3072) parts per row, the
+// r = b - A x through the sweep kernel: ceil(N / 1536) parts per row, the
 // partial sums of parts past the first staged in `parts` (residual_parts_bytes);
 // surfaces under 1024 nodes and wavenumbers off an even grid (dk <= 0) take
 // residual_kc_kernel with the known data y.

@@ -526,11 +526,12 @@ def test_synthesis_vs_oracle(ctx, T, n_k, add):
         assert rel(got[q], ref) < 1e-5, rel(got[q], ref)
 
 
-@pytest.mark.parametrize("levels,nk", [((3, 3), 70), ((4, 3), 9)])
+@pytest.mark.parametrize("levels,nk", [((3, 3), 70), ((4, 3), 9), ((4, 4), 5)])
 def test_residual_sweep_on_even_grid(ctx, levels, nk):
     """Refinement residuals on an even wavenumber grid (phases carried across
     the grid, r = b - A x; 70 wavenumbers re-anchor past 64 and end on a ragged
-    chunk; 3204 nodes split each row into two parts) converge to the same
+    chunk; rows are split into parts of 1536 columns: 1284, 3204 and 5124
+    nodes take 1, 3 and 4 parts) converge to the same
     solutions as the same wavenumbers in scattered order (one sincos per pair
     and wavenumber), and to the FP64 oracle."""
     bodies = [Body((0.0, 0.0, -1.6), 1.0, 1.0, levels[0], HARD),
