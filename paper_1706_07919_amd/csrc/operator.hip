@@ -10,6 +10,7 @@
 // coalesced loads of the node arrays and coalesced stores of the row-major
 // matrix rows.
 #include "common.h"
+#include "phase.h"
 
 #include <cmath>
 
@@ -129,10 +130,10 @@ struct Phase {
   template <int KC>
   __device__ inline void start(const KChunk<KC>& c, double t) {
     double s, co;
-    sincos(c.k[0] * t, &s, &co);
+    phase_sincos(c.k[0] * t, &s, &co);
     e = make_double2(co, s);
     if (c.uniform) {
-      sincos(c.dk * t, &s, &co);
+      phase_sincos(c.dk * t, &s, &co);
       d = make_double2(co, s);
     }
   }
@@ -142,7 +143,7 @@ struct Phase {
       e = make_double2(e.x * d.x - e.y * d.y, e.x * d.y + e.y * d.x);
     } else {
       double s, co;
-      sincos(c.k[q] * t, &s, &co);
+      phase_sincos(c.k[q] * t, &s, &co);
       e = make_double2(co, s);
     }
   }
@@ -474,7 +475,7 @@ __global__ void incident_kernel(int n, const double* __restrict__ x, const doubl
   const double k = kv[kq];
   const double ph = k * (x[3 * j] * dx + x[3 * j + 1] * dy + x[3 * j + 2] * dz);
   double sn, cs;
-  sincos(ph, &sn, &cs);
+  phase_sincos(ph, &sn, &cs);
   double2 out;
   if (bc[j] == BEM_BC_HARD) {
     const double kd = k * (nrm[3 * j] * dx + nrm[3 * j + 1] * dy + nrm[3 * j + 2] * dz);

@@ -561,3 +561,23 @@ def test_residual_sweep_on_even_grid(ctx, levels, nk):
     p, dp = bie.incident_plane_wave(s, k[q])
     _, _, xs = bie.solve(s, k[q], bie.known_data(s, p, dp))
     assert rel(even[q], xs) < 1e-8
+
+
+def test_phase_sincos_accuracy_through_incident_wave(ctx):
+    """The phases e^{i theta} of the operator kernels (reduction by pi/2 and
+    Taylor series) agree with the libm sine and cosine to 2 ulp for theta up to
+    about 3000: a soft surface under a plane wave along z has y_j = -e^{i k z_j}
+    with theta = k * z_j a single rounded product, reproduced here exactly."""
+    bodies = [Body((0.0, 0.0, 0.0), 1.0, 1.0, 2, SOFT), Body((0.0, 0.0, 2.6), 0.5, 1.0, 1, SOFT)]
+    ds = DeviceSurface.from_bodies(bodies)
+    s = Surface(bodies)
+    k = np.array([0.37, 11.0, 97.5, 512.25, 1000.0 + 1.0 / 3.0])
+    kd = dev(k)
+    y = torch.empty((k.size, 1, ds.n), dtype=torch.complex128, device="cuda")
+    native.bem_incident(ctx, ds.struct, k.size, kd, (0.0, 0.0, 1.0), y)
+    got = y.cpu().numpy()[:, 0]
+    z = s.x[:, 2]
+    for q in range(k.size):
+        theta = k[q] * z
+        assert np.max(np.abs(got[q].real + np.cos(theta))) <= 2.3e-16
+        assert np.max(np.abs(got[q].imag + np.sin(theta))) <= 2.3e-16
