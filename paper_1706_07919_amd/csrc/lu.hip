@@ -28,8 +28,10 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 // only exists in the device pass; the host pass sees plain pointers.)
 #if defined(__HIP_DEVICE_COMPILE__)
 #define GLOBAL __attribute__((address_space(1)))
+#define LDS_AS __attribute__((address_space(3)))
 #else
 #define GLOBAL
+#define LDS_AS
 #endif
 
 template <typename R> struct Cx;
@@ -966,20 +968,23 @@ __global__ __launch_bounds__(256, 4) void gemm_c32_tsb_kernel(LuGroups G, int ro
 // pass converts A (a block column of L, e.g. below the block just factored)
 // and B (a block row of U, in the real-part pattern (Re, -Im)) into bf16
 // hi/lo words laid out as the GEMM's LDS stage buffers -- per 128-row (or
-// -column) tile and 16-k stage, [hi/lo][k group][row] 16-byte words,
-// zero-padded past the edges.  The GEMM's staging is then a plain 16-byte
-// copy and each element is split once rather than once per tile reading it.
-// The products and their order are those of gemm_c32_b3_kernel, so the
-// update is bit-identical to it.
-constexpr int GP_STG = 2 * GB_KG * GB_BM;   // 16-byte words per tile and stage
+// -column) tile and 8-k block, [k group of 4][hi/lo][row] 16-byte words,
+// zero-padded past the edges -- so each element is split once rather than
+// once per tile reading it.  The GEMM streams 16-k stages (two 8-k blocks,
+// contiguous) straight from global memory into LDS with global_load_lds
+// (no register staging), one stage ahead into the other of two LDS buffers,
+// with an explicit wait on the load counter and a barrier per stage.  The
+// products and their order are those of gemm_c32_b3_kernel, so the update
+// is bit-identical to it.
+constexpr int GP_BLK = 2 * 2 * GB_BM;   // 16-byte words per tile and 8-k block
 // largest packing buffer a context holds; bigger batches are packed in slices
 constexpr size_t kPackLimit = (size_t)4 << 30;
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
-// bytes of the packed A and B of one matrix for an M x N update of depth K
+// 16-byte words of the packed A and B of one matrix for an M x N update of depth K
 inline int64_t pack_words(int M, int N, int K) {
-  const int64_t S = (K + GB_KB - 1) / GB_KB;
-  return ((int64_t)(M + GB_BM - 1) / GB_BM + (N + GB_BN - 1) / GB_BN) * S * GP_STG;
+  const int64_t S8 = (K + 7) / 8;
+  return ((int64_t)(M + GB_BM - 1) / GB_BM + (N + GB_BN - 1) / GB_BN) * S8 * GP_BLK;
 }
 
 // A = rows [rowC, min(rowEnd, n)) x cols [colA, colA + K) -> out + y * ms
@@ -991,13 +996,13 @@ __global__ __launch_bounds__(256) void pack_a_kernel(LuGroups G, int rowC, int c
   if (!locate(G, blockIdx.y, grp, b)) return;
   const int M = min(rowEnd, grp.n) - rowC;
   if (M <= 0) return;
-  const int S = (K + GB_KB - 1) / GB_KB;
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;   // (tile, stage, k group, row)
-  if (idx >= (int64_t)tiles_m * S * (GP_STG / 2)) return;
-  const int row = (int)(idx % GB_BM), kg = (int)((idx / GB_BM) % GB_KG);
-  const int64_t ts = idx / (GB_BM * GB_KG);
-  const int s = (int)(ts % S);
-  const int gr = (int)(ts / S) * GB_BM + row, k0 = s * GB_KB + 4 * kg;
+  const int S8 = (K + 7) / 8;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;   // (tile, block, k group, row)
+  if (idx >= (int64_t)tiles_m * S8 * (GP_BLK / 2)) return;
+  const int row = (int)(idx % GB_BM), kg = (int)((idx / GB_BM) % 2);
+  const int64_t tb = idx / (2 * GB_BM);                           // tile * S8 + block
+  const int s8 = (int)(tb % S8);
+  const int gr = (int)(tb / S8) * GB_BM + row, k0 = s8 * 8 + 4 * kg;
   const GLOBAL float2* A = gmat<float2>(grp, b) + (int64_t)(rowC + min(gr, M - 1)) * grp.ld + colA;
   float x[8];
 #pragma unroll
@@ -1009,9 +1014,9 @@ __global__ __launch_bounds__(256) void pack_a_kernel(LuGroups G, int rowC, int c
   }
   uint4 hi, lo;
   split8(x, hi, lo);
-  uint4* o = out + blockIdx.y * ms + ts * GP_STG;
-  o[kg * GB_BM + row] = hi;
-  o[GP_STG / 2 + kg * GB_BM + row] = lo;
+  uint4* o = out + blockIdx.y * ms + tb * GP_BLK + kg * 2 * GB_BM;
+  o[row] = hi;
+  o[GB_BM + row] = lo;
 }
 
 // B = rows [rowB, rowB + K) x cols [colC, min(colEnd, n)) -> out + y * ms
@@ -1023,13 +1028,13 @@ __global__ __launch_bounds__(256) void pack_b_kernel(LuGroups G, int rowB, int c
   if (!locate(G, blockIdx.y, grp, b)) return;
   const int N = min(colEnd, grp.n) - colC;
   if (N <= 0) return;
-  const int S = (K + GB_KB - 1) / GB_KB;
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;   // (tile, stage, k group, col)
-  if (idx >= (int64_t)tiles_n * S * (GP_STG / 2)) return;
-  const int col = (int)(idx % GB_BN), kg = (int)((idx / GB_BN) % GB_KG);
-  const int64_t ts = idx / (GB_BN * GB_KG);
-  const int s = (int)(ts % S);
-  const int gc = (int)(ts / S) * GB_BN + col, k0 = s * GB_KB + 4 * kg;
+  const int S8 = (K + 7) / 8;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;   // (tile, block, k group, col)
+  if (idx >= (int64_t)tiles_n * S8 * (GP_BLK / 2)) return;
+  const int col = (int)(idx % GB_BN), kg = (int)((idx / GB_BN) % 2);
+  const int64_t tb = idx / (2 * GB_BN);
+  const int s8 = (int)(tb % S8);
+  const int gc = (int)(tb / S8) * GB_BN + col, k0 = s8 * 8 + 4 * kg;
   const GLOBAL float2* B = gmat<float2>(grp, b) + (int64_t)rowB * grp.ld + colC + min(gc, N - 1);
   float x[8];
 #pragma unroll
@@ -1041,14 +1046,23 @@ __global__ __launch_bounds__(256) void pack_b_kernel(LuGroups G, int rowB, int c
   }
   uint4 hi, lo;
   split8(x, hi, lo);
-  uint4* o = out + blockIdx.y * ms + ts * GP_STG;
-  o[kg * GB_BN + col] = hi;
-  o[GP_STG / 2 + kg * GB_BN + col] = lo;
+  uint4* o = out + blockIdx.y * ms + tb * GP_BLK + kg * 2 * GB_BN;
+  o[col] = hi;
+  o[GB_BN + col] = lo;
 }
 
 __device__ inline bf16x8 re_to_im8(bf16x8 b) {
   const u32x4 r = __builtin_bit_cast(u32x4, b);
   return __builtin_bit_cast(bf16x8, ((r >> 16) | (r << 16)) ^ 0x8000u);
+}
+
+// One 16-byte word per lane from global memory straight into LDS at
+// lds_wave + 16 * lane (lds_wave wave-uniform, in M0).  The compiler does not
+// order these loads against later LDS reads; the kernel waits on the load
+// counter itself before each barrier.
+__device__ inline void lds_dma16(const GLOBAL u32x4* src, unsigned lds_wave) {
+  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off"
+               :: "v"(src), "s"(lds_wave) : "memory", "m0");
 }
 
 __global__ __launch_bounds__(256, 2) void gemm_c32_b3p_kernel(LuGroups G, int rowC, int colC,
@@ -1058,7 +1072,7 @@ __global__ __launch_bounds__(256, 2) void gemm_c32_b3p_kernel(LuGroups G, int ro
                                                               int64_t a_ms,
                                                               const uint4* __restrict__ Bp,
                                                               int64_t b_ms) {
-  __shared__ u32x4 As[2][GP_STG], Bs[2][GP_STG];
+  __shared__ u32x4 As[2][2 * GP_BLK], Bs[2][2 * GP_BLK];
   const int per = gridDim.x / 8;
   const int t = (blockIdx.x % 8) * per + blockIdx.x / 8;
   if (t >= tiles_m * tiles_n) return;
@@ -1073,9 +1087,9 @@ __global__ __launch_bounds__(256, 2) void gemm_c32_b3p_kernel(LuGroups G, int ro
   if (m0 >= M || n0 >= N) return;
   const int ld = (int)gv.ld;   // n * ld < 2^31 is checked on the host
   GLOBAL float2* C = gv.Cm;
-  const int S = (K + GB_KB - 1) / GB_KB;
-  const GLOBAL u32x4* Ag = (const GLOBAL u32x4*)Ap + blockIdx.y * a_ms + (int64_t)tm * S * GP_STG;
-  const GLOBAL u32x4* Bg = (const GLOBAL u32x4*)Bp + blockIdx.y * b_ms + (int64_t)tn * S * GP_STG;
+  const int S8 = (K + 7) / 8, S = (S8 + 1) / 2;
+  const GLOBAL u32x4* Ag = (const GLOBAL u32x4*)Ap + blockIdx.y * a_ms + (int64_t)tm * S8 * GP_BLK;
+  const GLOBAL u32x4* Bg = (const GLOBAL u32x4*)Bp + blockIdx.y * b_ms + (int64_t)tn * S8 * GP_BLK;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
@@ -1087,41 +1101,43 @@ __global__ __launch_bounds__(256, 2) void gemm_c32_b3p_kernel(LuGroups G, int ro
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int v = 0; v < 16; ++v) { acc_re[i][j][v] = 0.f; acc_im[i][j][v] = 0.f; }
-  constexpr int NW = GP_STG / 256;   // 16-byte words per thread per operand and stage
-  u32x4 ra[NW], rb[NW];
-  auto gload = [&](int s) {
+  // LDS byte offsets of this wave's 64 words in buffer 0
+  const unsigned a_lds = (unsigned)(uintptr_t)(LDS_AS void*)&As[0][tid & ~63];
+  const unsigned b_lds = (unsigned)(uintptr_t)(LDS_AS void*)&Bs[0][tid & ~63];
+  // stage s = 8-k blocks 2s and 2s + 1 (only the first when S8 is odd and s is last)
+  auto load_stage = [&](int s) {
+    const unsigned boff = (unsigned)(s & 1) * (2 * GP_BLK * 16);
+    const int nw = 2 * s + 1 < S8 ? 4 : 2;
 #pragma unroll
-    for (int q = 0; q < NW; ++q) {
-      ra[q] = Ag[(int64_t)s * GP_STG + tid + 256 * q];
-      rb[q] = Bg[(int64_t)s * GP_STG + tid + 256 * q];
-    }
+    for (int q = 0; q < 4; ++q)
+      if (q < nw) {
+        lds_dma16(Ag + (int64_t)s * 2 * GP_BLK + tid + 256 * q,
+                  __builtin_amdgcn_readfirstlane(a_lds + boff + q * 4096));
+        lds_dma16(Bg + (int64_t)s * 2 * GP_BLK + tid + 256 * q,
+                  __builtin_amdgcn_readfirstlane(b_lds + boff + q * 4096));
+      }
   };
-  auto sstore = [&](int buf) {
+  load_stage(0);
+  for (int s = 0; s < S; ++s) {
+    // stage s has landed, and every wave is past its reads of stage s - 1,
+    // whose buffer the next load reuses
+    asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+    if (s + 1 < S) load_stage(s + 1);
+    const int cur = s & 1;
 #pragma unroll
-    for (int q = 0; q < NW; ++q) {
-      As[buf][tid + 256 * q] = ra[q];
-      Bs[buf][tid + 256 * q] = rb[q];
-    }
-  };
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  for (int kt = 0; kt < S; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < S) gload(kt + 1);
-#pragma unroll
-    for (int s2 = 0; s2 < GB_KG / 2; ++s2) {
-      const int g = 2 * s2 + h;
+    for (int s2 = 0; s2 < 2; ++s2) {
+      if (2 * s + s2 >= S8) break;
+      const int base = s2 * GP_BLK + h * 2 * GB_BM;   // lanes 32-63 take the second k group
       bf16x8 ah[2], al[2], brh[2], brl[2], bih[2], bil[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        ah[i] = __builtin_bit_cast(bf16x8, As[cur][g * GB_BM + wm * 64 + i * 32 + l32]);
-        al[i] = __builtin_bit_cast(bf16x8, As[cur][GP_STG / 2 + g * GB_BM + wm * 64 + i * 32 + l32]);
+        ah[i] = __builtin_bit_cast(bf16x8, As[cur][base + wm * 64 + i * 32 + l32]);
+        al[i] = __builtin_bit_cast(bf16x8, As[cur][base + GB_BM + wm * 64 + i * 32 + l32]);
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        brh[j] = __builtin_bit_cast(bf16x8, Bs[cur][g * GB_BN + wn * 64 + j * 32 + l32]);
-        brl[j] = __builtin_bit_cast(bf16x8, Bs[cur][GP_STG / 2 + g * GB_BN + wn * 64 + j * 32 + l32]);
+        brh[j] = __builtin_bit_cast(bf16x8, Bs[cur][base + wn * 64 + j * 32 + l32]);
+        brl[j] = __builtin_bit_cast(bf16x8, Bs[cur][base + GB_BN + wn * 64 + j * 32 + l32]);
         bih[j] = re_to_im8(brh[j]);
         bil[j] = re_to_im8(brl[j]);
       }
@@ -1137,8 +1153,6 @@ __global__ __launch_bounds__(256, 2) void gemm_c32_b3p_kernel(LuGroups G, int ro
           acc_im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bih[j], acc_im[i][j], 0, 0, 0);
         }
     }
-    if (kt + 1 < S) sstore(cur ^ 1);
-    __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -1605,11 +1619,11 @@ struct Fac {
     const int fit = (int)std::min<size_t>((size_t)total, pack ? pack_bytes / per : 0);
     if (fit <= 0) return false;
     const int tiles_m = (M + GB_BM - 1) / GB_BM, tiles_n = (N + GB_BN - 1) / GB_BN;
-    const int S = (K + GB_KB - 1) / GB_KB;
-    const int64_t a_ms = (int64_t)tiles_m * S * GP_STG, b_ms = (int64_t)tiles_n * S * GP_STG;
+    const int S8 = (K + 7) / 8;
+    const int64_t a_ms = (int64_t)tiles_m * S8 * GP_BLK, b_ms = (int64_t)tiles_n * S8 * GP_BLK;
     uint4* Ap = (uint4*)pack;
     uint4* Bp = Ap + a_ms * fit;
-    const int64_t ta = (int64_t)tiles_m * S * (GP_STG / 2), tb = (int64_t)tiles_n * S * (GP_STG / 2);
+    const int64_t ta = (int64_t)tiles_m * S8 * (GP_BLK / 2), tb = (int64_t)tiles_n * S8 * (GP_BLK / 2);
     const int gx = (tiles_m * tiles_n + 7) / 8 * 8;
     for (int b0 = 0; b0 < total; b0 += fit) {
       const int nbat = std::min(fit, total - b0);

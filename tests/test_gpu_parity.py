@@ -210,6 +210,7 @@ def test_getrf_3m_and_split_gemm(ctx, n, kind):
     (777, 64, 3, 0),                     # every trailing update in one packed launch
     (1100, 256, 5, 4 * 8 * 1024 * 1024),  # 8 MiB packing buffer: batches packed in slices
     (530, 128, 2, 4096),                 # buffer too small for one matrix: unpacked kernel
+    (1300, 72, 2, 0),                    # depth 72: an odd number of 8-k blocks per stage pair
 ])
 def test_packed_trailing_update_matches_unpacked(ctx, n, nb, batch, limit):
     """The pre-split operands feed the same products in the same order, so the
