@@ -139,12 +139,34 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(LuGroups G, int c0
   const int t = threadIdx.x;
   const int lane = t & 63, wid = t >> 6;
   C a[RPT][W];
+  // full-width panels with 16-byte aligned rows move whole rows as 16-byte
+  // words; rows past n are read clamped and zeroed, never stored
+  const bool vec = w == W && (sizeof(C) == 16 || ((ld | c0) & 1) == 0);
+  if (vec) {
+    constexpr int PER = 16 / sizeof(C);   // complex values per 16-byte word
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int r = c0 + t + q * NT;
+    for (int q = 0; q < RPT; ++q) {
+      const int r = c0 + t + q * NT;
+      const GLOBAL uint4* src = (const GLOBAL uint4*)(Ab + (int64_t)min(r, n - 1) * ld + c0);
+      uint4 v[W / PER];
 #pragma unroll
-    for (int c = 0; c < W; ++c)
-      a[q][c] = (r < n && c < w) ? Ab[(int64_t)r * ld + c0 + c] : cmk<C>(R(0), R(0));
+      for (int m = 0; m < W / PER; ++m) v[m] = src[m];
+#pragma unroll
+      for (int m = 0; m < W / PER; ++m) {
+        C e[PER];
+        __builtin_memcpy(e, &v[m], 16);
+#pragma unroll
+        for (int u = 0; u < PER; ++u) a[q][m * PER + u] = r < n ? e[u] : cmk<C>(R(0), R(0));
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = c0 + t + q * NT;
+#pragma unroll
+      for (int c = 0; c < W; ++c)
+        a[q][c] = (r < n && c < w) ? Ab[(int64_t)r * ld + c0 + c] : cmk<C>(R(0), R(0));
+    }
   }
   // The column loop is unrolled so that every register index is static.  Row
   // c0 + c is held by thread c in slot 0; a row r > c0 + c is below the
@@ -224,13 +246,30 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(LuGroups G, int c0
       }
     }
   }
+  if (vec) {
+    constexpr int PER = 16 / sizeof(C);
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int r = c0 + t + q * NT;
-    if (r < n)
+    for (int q = 0; q < RPT; ++q) {
+      const int r = c0 + t + q * NT;
+      if (r < n) {
+        GLOBAL uint4* dst = (GLOBAL uint4*)(Ab + (int64_t)r * ld + c0);
 #pragma unroll
-      for (int c = 0; c < W; ++c)
-        if (c < w) Ab[(int64_t)r * ld + c0 + c] = a[q][c];
+        for (int m = 0; m < W / PER; ++m) {
+          uint4 v;
+          __builtin_memcpy(&v, &a[q][m * PER], 16);
+          dst[m] = v;
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = c0 + t + q * NT;
+      if (r < n)
+#pragma unroll
+        for (int c = 0; c < W; ++c)
+          if (c < w) Ab[(int64_t)r * ld + c0 + c] = a[q][c];
+    }
   }
 }
 
