@@ -1026,7 +1026,9 @@ inline int64_t pack_words(int M, int N, int K) {
   return ((int64_t)(M + GB_BM - 1) / GB_BM + (N + GB_BN - 1) / GB_BN) * S8 * GP_BLK;
 }
 
-// A = rows [rowC, min(rowEnd, n)) x cols [colA, colA + K) -> out + y * ms
+// A = rows [rowC, min(rowEnd, n)) x cols [colA, colA + K) -> out + y * ms.
+// One thread per (tile, 8-k block, row): the row's 8 values are read with
+// clamped addresses (16-byte words when aligned) and zeroed past the edges.
 __global__ __launch_bounds__(256) void pack_a_kernel(LuGroups G, int rowC, int colA, int rowEnd,
                                                      int K, int tiles_m, int64_t ms,
                                                      uint4* __restrict__ out) {
@@ -1036,29 +1038,52 @@ __global__ __launch_bounds__(256) void pack_a_kernel(LuGroups G, int rowC, int c
   const int M = min(rowEnd, grp.n) - rowC;
   if (M <= 0) return;
   const int S8 = (K + 7) / 8;
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;   // (tile, block, k group, row)
-  if (idx >= (int64_t)tiles_m * S8 * (GP_BLK / 2)) return;
-  const int row = (int)(idx % GB_BM), kg = (int)((idx / GB_BM) % 2);
-  const int64_t tb = idx / (2 * GB_BM);                           // tile * S8 + block
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;   // (tile, block, row)
+  if (idx >= (int64_t)tiles_m * S8 * GB_BM) return;
+  const int row = (int)(idx % GB_BM);
+  const int64_t tb = idx / GB_BM;                                 // tile * S8 + block
   const int s8 = (int)(tb % S8);
-  const int gr = (int)(tb / S8) * GB_BM + row, k0 = s8 * 8 + 4 * kg;
+  const int gr = (int)(tb / S8) * GB_BM + row, k0 = s8 * 8;
   const GLOBAL float2* A = gmat<float2>(grp, b) + (int64_t)(rowC + min(gr, M - 1)) * grp.ld + colA;
-  float x[8];
+  float x[16];
+  if (k0 + 8 <= K && ((grp.ld | colA) & 1) == 0) {
+    const GLOBAL float4* p4 = (const GLOBAL float4*)(A + k0);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    float2 a = make_float2(0.f, 0.f);
-    if (gr < M && k0 + q < K) a = A[k0 + q];
-    x[2 * q] = a.x;
-    x[2 * q + 1] = a.y;
+    for (int m = 0; m < 4; ++m) {
+      const float4 v = p4[m];
+      x[4 * m] = v.x;
+      x[4 * m + 1] = v.y;
+      x[4 * m + 2] = v.z;
+      x[4 * m + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const float2 v = A[min(k0 + q, K - 1)];
+      x[2 * q] = v.x;
+      x[2 * q + 1] = v.y;
+    }
   }
-  uint4 hi, lo;
-  split8(x, hi, lo);
-  uint4* o = out + blockIdx.y * ms + tb * GP_BLK + kg * 2 * GB_BM;
-  o[row] = hi;
-  o[GB_BM + row] = lo;
+  const bool rok = gr < M;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const bool ok = rok && k0 + q < K;
+    x[2 * q] = ok ? x[2 * q] : 0.f;
+    x[2 * q + 1] = ok ? x[2 * q + 1] : 0.f;
+  }
+  uint4* o = out + blockIdx.y * ms + tb * GP_BLK;
+#pragma unroll
+  for (int kg = 0; kg < 2; ++kg) {
+    uint4 hi, lo;
+    split8(x + 8 * kg, hi, lo);
+    o[kg * 2 * GB_BM + row] = hi;
+    o[kg * 2 * GB_BM + GB_BM + row] = lo;
+  }
 }
 
-// B = rows [rowB, rowB + K) x cols [colC, min(colEnd, n)) -> out + y * ms
+// B = rows [rowB, rowB + K) x cols [colC, min(colEnd, n)) -> out + y * ms.
+// One thread per (tile, 8-k block, k group, column); clamped loads, zeroed
+// past the edges.
 __global__ __launch_bounds__(256) void pack_b_kernel(LuGroups G, int rowB, int colC, int colEnd,
                                                      int K, int tiles_n, int64_t ms,
                                                      uint4* __restrict__ out) {
@@ -1078,10 +1103,10 @@ __global__ __launch_bounds__(256) void pack_b_kernel(LuGroups G, int rowB, int c
   float x[8];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    float2 v = make_float2(0.f, 0.f);
-    if (gc < N && k0 + q < K) v = B[(int64_t)(k0 + q) * grp.ld];
-    x[2 * q] = v.x;
-    x[2 * q + 1] = -v.y;
+    const float2 v = B[(int64_t)min(k0 + q, K - 1) * grp.ld];
+    const bool ok = gc < N && k0 + q < K;
+    x[2 * q] = ok ? v.x : 0.f;
+    x[2 * q + 1] = ok ? -v.y : 0.f;
   }
   uint4 hi, lo;
   split8(x, hi, lo);
@@ -1662,7 +1687,7 @@ struct Fac {
     const int64_t a_ms = (int64_t)tiles_m * S8 * GP_BLK, b_ms = (int64_t)tiles_n * S8 * GP_BLK;
     uint4* Ap = (uint4*)pack;
     uint4* Bp = Ap + a_ms * fit;
-    const int64_t ta = (int64_t)tiles_m * S8 * (GP_BLK / 2), tb = (int64_t)tiles_n * S8 * (GP_BLK / 2);
+    const int64_t ta = (int64_t)tiles_m * S8 * GB_BM, tb = (int64_t)tiles_n * S8 * (GP_BLK / 2);
     const int gx = (tiles_m * tiles_n + 7) / 8 * 8;
     for (int b0 = 0; b0 < total; b0 += fit) {
       const int nbat = std::min(fit, total - b0);
