@@ -401,9 +401,10 @@ __global__ __launch_bounds__(256) void trsm_kernel(LuGroups G, int r0, int m1_al
   const int col = col0 + blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= min(col1, n)) return;
   C x[32];
+  // rows past m1 are read clamped and never stored, so the loads and stores
+  // carry no per-row branches
 #pragma unroll
-  for (int i = 0; i < 32; ++i)
-    if (i < m1) x[i] = Ab[(int64_t)(r0 + i) * ld + col];
+  for (int i = 0; i < 32; ++i) x[i] = Ab[(int64_t)(r0 + min(i, m1 - 1)) * ld + col];
 #pragma unroll
   for (int i = 1; i < 32; ++i) {
     if (i < m1) {
@@ -414,9 +415,14 @@ __global__ __launch_bounds__(256) void trsm_kernel(LuGroups G, int r0, int m1_al
       x[i] = s;
     }
   }
+  if (m1 == 32) {
 #pragma unroll
-  for (int i = 1; i < 32; ++i)
-    if (i < m1) Ab[(int64_t)(r0 + i) * ld + col] = x[i];
+    for (int i = 1; i < 32; ++i) Ab[(int64_t)(r0 + i) * ld + col] = x[i];
+  } else {
+#pragma unroll
+    for (int i = 1; i < 32; ++i)
+      if (i < m1) Ab[(int64_t)(r0 + i) * ld + col] = x[i];
+  }
 }
 
 // ============================================================== GEMM f32 (4M)
