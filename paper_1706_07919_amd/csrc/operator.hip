@@ -161,6 +161,9 @@ __global__ __launch_bounds__(kThreads) void assemble_kc_kernel(
   const int i = blockIdx.x;
   const KChunk<kKcAssemble> kc = load_chunk<kKcAssemble>(kv, nk, nullptr);
   const int q0 = blockIdx.y * kKcAssemble;
+  double kinv[kKcAssemble];
+#pragma unroll
+  for (int q = 0; q < kKcAssemble; ++q) kinv[q] = q < kc.kc ? 1.0 / kc.k[q] : 0.0;
   const double xi = x[3 * i], yi = x[3 * i + 1], zi = x[3 * i + 2];
   const double nix = nrm[3 * i], niy = nrm[3 * i + 1], niz = nrm[3 * i + 2];
   // per wavenumber: Dphi (re, im), Dpsi (re, im), b (re, im)
@@ -195,7 +198,7 @@ __global__ __launch_bounds__(kThreads) void assemble_kc_kernel(
         // H = E (ikr - 1) (d.n_j) / r^3
         const double2 H = make_double2(qn * (-E.e.x - kr * E.e.y), qn * (kr * E.e.x - E.e.y));
         // g = cos(k s0), f = sin(k s0)/k, g' = -k sin(k s0) nn, f' = cos(k s0) nn
-        const double g = F.e.x, f = F.e.y / k, gp = -k * F.e.y * nn, fp = F.e.x * nn;
+        const double g = F.e.x, f = F.e.y * kinv[q], gp = -k * F.e.y * nn, fp = F.e.x * nn;
         acc[q][0] += wj * (gp * G.x - g * H.x);
         acc[q][1] += wj * (gp * G.y - g * H.y);
         acc[q][2] += wj * (fp * G.x - f * H.x);
