@@ -60,15 +60,21 @@ const char* bem_last_error(const bem_ctx* ctx);
 bem_status bem_ctx_set_workspace_limit(bem_ctx* ctx, uint64_t bytes);
 
 /* Per-kernel accounting for roofline reports.  With profiling on, each launch
- * of a counted kernel is bracketed by HIP events on the context stream and
+ * of a counted kernel is bracketed by HIP events on the stream it runs on and
  * credited with its algorithmic work; bem_ctx_kernel_stats returns the sums
  * (flops, bytes, milliseconds of device time, launch count) since profiling
  * was last switched (set_profiling resets them).  Kernel names: "gemm_c32",
- * "gemm_c64", "panel", "assemble", "residual", "getrs", "field", "synth".
+ * "gemm_3m", "gemm_b3", "gemm_b3_narrow", "gemm_b3_packed", "pack", "gemm_c64",
+ * "panel", "laswp", "trsm", "assemble", "residual", "getrs", "field", "synth".
  * For "assemble"/"residual" the flop slot counts node pairs and for "field"
  * kernel terms (point x frequency x node).  Unknown names report zeros.
- * Synchronises the stream. */
+ * Profiling turns the hipGraph replay of bem_solve_batched off.
+ * Synchronises the stream.
+ * bem_ctx_set_profiling_filter: count only the named kernels (a
+ * comma-separated list; NULL or "" = all), so that timing one kernel adds no
+ * events to the others; takes effect at the next set_profiling. */
 bem_status bem_ctx_set_profiling(bem_ctx* ctx, int32_t on);
+bem_status bem_ctx_set_profiling_filter(bem_ctx* ctx, const char* names);
 bem_status bem_ctx_kernel_stats(bem_ctx* ctx, const char* kernel, double* flops, double* bytes,
                                 double* ms, int64_t* launches);
 

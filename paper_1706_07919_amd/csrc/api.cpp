@@ -44,6 +44,9 @@ static hipEvent_t take_event(bem_ctx* ctx) {
 
 int prof_begin(bem_ctx* ctx, const char* kernel) {
   if (!ctx->profiling) return -1;
+  if (!ctx->prof_filter.empty() &&
+      ctx->prof_filter.find("," + std::string(kernel) + ",") == std::string::npos)
+    return -1;
   KernelStat& k = ctx->stats[kernel];
   hipEvent_t e = take_event(ctx);
   if (!e) return -1;
@@ -271,6 +274,18 @@ extern "C" bem_status bem_ctx_set_profiling(bem_ctx* ctx, int32_t on) {
   resolve_stats(ctx);
   ctx->stats.clear();
   ctx->profiling = on != 0;
+  return BEM_OK;
+}
+
+extern "C" bem_status bem_ctx_set_profiling_filter(bem_ctx* ctx, const char* names) {
+  if (!ctx) return BEM_EINVAL;
+  ctx->prof_filter.clear();
+  if (names && *names) {
+    ctx->prof_filter = ",";
+    for (const char* c = names; *c; ++c)
+      if (*c != ' ') ctx->prof_filter += *c;
+    ctx->prof_filter += ",";
+  }
   return BEM_OK;
 }
 

@@ -37,6 +37,7 @@ struct bem_ctx {
   std::map<std::pair<int, int>, int> tuned_nb;
   int num_cus = 256;
   bool profiling = false;
+  std::string prof_filter;   // ",name,name," of the counted kernels, or empty = all
   std::map<std::string, KernelStat> stats;
   std::vector<hipEvent_t> event_pool;
   // captured factorisations, keyed by every argument of the launch sequence

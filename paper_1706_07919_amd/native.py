@@ -24,7 +24,7 @@ PULSE_KINDS = {"paper": 0, "gauss": 1, "ricker": 2, "nwave": 3, "chirp": 4, "gsi
 
 EXPORTED = [
     "bem_ctx_create", "bem_ctx_destroy", "bem_last_error", "bem_ctx_set_workspace_limit",
-    "bem_ctx_set_profiling", "bem_ctx_kernel_stats",
+    "bem_ctx_set_profiling", "bem_ctx_set_profiling_filter", "bem_ctx_kernel_stats",
     "bem_mesh_counts", "bem_mesh_icosphere", "bem_incident", "bem_assemble", "bem_residual",
     "bem_solve_opts_default", "bem_solve_batched", "bem_getrf_batched", "bem_getrs_batched",
     "bem_autotune_lu",
@@ -79,6 +79,7 @@ def load(path: str = LIB_PATH):
         "bem_last_error": ([vp], C.c_char_p),
         "bem_ctx_set_workspace_limit": ([vp, C.c_uint64], C.c_int),
         "bem_ctx_set_profiling": ([vp, i32], C.c_int),
+        "bem_ctx_set_profiling_filter": ([vp, C.c_char_p], C.c_int),
         "bem_ctx_kernel_stats": ([vp, C.c_char_p, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl),
                                   C.POINTER(i64)], C.c_int),
         "bem_mesh_counts": ([i32, C.POINTER(i32), C.POINTER(i32)], C.c_int),
@@ -162,6 +163,13 @@ class Context:
 
     def set_profiling(self, on: bool):
         _check(load().bem_ctx_set_profiling(self.handle, int(bool(on))), self)
+
+    def set_profiling_filter(self, names=None):
+        """Count only the named kernels (an iterable or comma-separated string);
+        None or empty = all."""
+        if names is not None and not isinstance(names, str):
+            names = ",".join(names)
+        _check(load().bem_ctx_set_profiling_filter(self.handle, (names or "").encode()), self)
 
     def kernel_stats(self, name: str):
         """(flops, bytes, ms, launches) accumulated since profiling was switched."""
