@@ -1008,6 +1008,71 @@ __global__ __launch_bounds__(256, 4) void gemm_c32_tsb_kernel(LuGroups G, int ro
   }
 }
 
+// ============================================================== GEMM f32, small width and depth
+// The smallest updates inside the panels (N, K <= 16: the pairs of 8-column
+// panels and of 16-column halves) are bound by moving C: one thread per row
+// holds its row of A and C in registers and takes B (K x N, zero-padded) from
+// LDS, in float32 FMA.  Rows move as 16-byte words when they are aligned.
+template <int NK>
+__global__ __launch_bounds__(256) void gemm_c32_small_kernel(LuGroups G, int rowC, int colC,
+                                                             int colA, int rowB, int rowEnd,
+                                                             int colEnd, int K) {
+  __shared__ float2 Bs[NK][NK];
+  LuGroup grp;
+  int b = 0;
+  if (!locate(G, blockIdx.y, grp, b)) return;
+  const int M = min(rowEnd, grp.n) - rowC, N = min(colEnd, grp.n) - colC;
+  if (M <= 0 || N <= 0 || (int)(blockIdx.x * 256) >= M) return;
+  const int64_t ld = grp.ld;
+  GLOBAL float2* base = gmat<float2>(grp, b);
+  const int t = threadIdx.x;
+  for (int e = t; e < NK * NK; e += 256) {
+    const int kk = e / NK, j = e % NK;
+    Bs[kk][j] = (kk < K && j < N) ? base[(int64_t)(rowB + kk) * ld + colC + j] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const int row = blockIdx.x * 256 + t;
+  if (row >= M) return;
+  const GLOBAL float2* Ar = base + (int64_t)(rowC + row) * ld + colA;
+  GLOBAL float2* Cr = base + (int64_t)(rowC + row) * ld + colC;
+  const bool vec = ((ld | colA | colC) & 1) == 0;
+  float2 a[NK], c[NK];
+  if (vec && K == NK && N == NK) {
+#pragma unroll
+    for (int m = 0; m < NK / 2; ++m) {
+      const float4 va = ((const GLOBAL float4*)Ar)[m], vc = ((const GLOBAL float4*)Cr)[m];
+      a[2 * m] = make_float2(va.x, va.y);
+      a[2 * m + 1] = make_float2(va.z, va.w);
+      c[2 * m] = make_float2(vc.x, vc.y);
+      c[2 * m + 1] = make_float2(vc.z, vc.w);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < NK; ++q) {
+      a[q] = Ar[min(q, K - 1)];
+      if (q >= K) a[q] = make_float2(0.f, 0.f);
+      c[q] = Cr[min(q, N - 1)];
+    }
+  }
+#pragma unroll
+  for (int kk = 0; kk < NK; ++kk)
+#pragma unroll
+    for (int j = 0; j < NK; ++j) {
+      const float2 bv = Bs[kk][j];
+      c[j].x -= a[kk].x * bv.x - a[kk].y * bv.y;
+      c[j].y -= a[kk].x * bv.y + a[kk].y * bv.x;
+    }
+  if (vec && N == NK) {
+#pragma unroll
+    for (int m = 0; m < NK / 2; ++m)
+      ((GLOBAL float4*)Cr)[m] = make_float4(c[2 * m].x, c[2 * m].y, c[2 * m + 1].x, c[2 * m + 1].y);
+  } else {
+#pragma unroll
+    for (int j = 0; j < NK; ++j)
+      if (j < N) Cr[j] = c[j];
+  }
+}
+
 // ============================================================== GEMM f32 via bf16 split, packed operands
 // Updates of at least 512 x 512 take their operands split once: a packing
 // pass converts A (a block column of L, e.g. below the block just factored)
@@ -1601,6 +1666,7 @@ struct Fac {
     const int M = std::min(rowEnd, maxn) - rowC, N = std::min(colEnd, maxn) - colC;
     if (M <= 0 || N <= 0) return;
     const char* kname = prec == BEM_C128 ? "gemm_c64"
+                        : N <= 16 && K <= 16 ? "gemm_small"
                         : gkind == kGemmBf16x3 ? (N <= 64 ? "gemm_b3_narrow" : "gemm_b3")
                         : gkind == kGemm3M ? "gemm_3m" : "gemm_c32";
     const int pi = prof_begin(ctx, kname);
@@ -1610,7 +1676,15 @@ struct Fac {
                          colC, colA, rowB, rowEnd, colEnd, K, tn);
     } else {
       const int tn = (N + G32_BN - 1) / G32_BN, tm = (M + G32_BM - 1) / G32_BM;
-      if (gkind == kGemmBf16x3 && N <= 64) {
+      if (N <= 16 && K <= 16) {
+        const dim3 grid((unsigned)((M + 255) / 256), total);
+        if (N <= 8 && K <= 8)
+          hipLaunchKernelGGL(gemm_c32_small_kernel<8>, grid, dim3(256), 0, ctx->stream, G, rowC,
+                             colC, colA, rowB, rowEnd, colEnd, K);
+        else
+          hipLaunchKernelGGL(gemm_c32_small_kernel<16>, grid, dim3(256), 0, ctx->stream, G, rowC,
+                             colC, colA, rowB, rowEnd, colEnd, K);
+      } else if (gkind == kGemmBf16x3 && N <= 64) {
         const int tmt = (M + GT_BM - 1) / GT_BM, tnt = (N + GT_BN - 1) / GT_BN;
         hipLaunchKernelGGL(gemm_c32_tsb_kernel, dim3(tmt * tnt, total), dim3(256), 0, ctx->stream,
                            G, rowC, colC, colA, rowB, rowEnd, colEnd, K, tnt);

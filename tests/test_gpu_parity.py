@@ -159,13 +159,19 @@ def test_getrf_getrs_random(ctx, prec, n, nb):
     X = torch.zeros((batch, 2, n), dtype=cdt, device="cuda")
     native.bem_getrs_batched(ctx, prec, n, ld, n * ld, batch, A, piv, 2, dev(B, cdt), X, 2 * n)
     X = X.cpu().numpy().astype(np.complex128)
-    tol = 1e-11 if prec == native.BEM_C128 else 2e-4
+    # normwise backward error ||B - M X||_F / (||M||_F ||X||_F) of every
+    # matrix: the criterion a float32 factorisation meets whatever the
+    # conditioning (LAPACK's float32 factors reach 4-5e-7 at n = 1100)
+    eta = 1e-14 if prec == native.BEM_C128 else 1e-6
+    for b_ in range(batch):
+        res = np.linalg.norm(M[b_] @ X[b_].T - B[b_].T) / (np.linalg.norm(M[b_]) * np.linalg.norm(X[b_]))
+        assert res < eta, (b_, res)
+    # forward error of the shifted matrices; in float32 it scales with the
+    # condition number (about 9e3 for the first matrix at n = 1100, where
+    # LAPACK's float32 solve is off by 3e-4)
     for b_ in range(2):
         ref = np.linalg.solve(M[b_], B[b_].T).T
-        assert rel(X[b_], ref) < tol
-    # the Gaussian matrix is not well conditioned: judge it by the backward error
-    res = np.linalg.norm(M[2] @ X[2].T - B[2].T) / (np.linalg.norm(M[2]) * np.linalg.norm(X[2]))
-    assert res < (1e-14 if prec == native.BEM_C128 else 1e-6)
+        assert rel(X[b_], ref) < (1e-11 if prec == native.BEM_C128 else 2e-3)
     if n <= 600:  # P A = L U reconstruction
         LU = A.cpu().numpy()[:, :, :n].astype(np.complex128)
         p = piv.cpu().numpy()
@@ -525,6 +531,117 @@ def test_synthesis_vs_oracle(ctx, T, n_k, add):
     for q in range(2):
         ref = opulse.synthesize(U.astype(np.complex128), c[q], T, xp, dk, add_incident=bool(add))
         assert rel(got[q], ref) < 1e-5, rel(got[q], ref)
+
+
+@pytest.mark.parametrize("T,idx,add", [
+    (64, [1, 2, 5, 9, 31, 32], 0),                  # first bin and the Nyquist bin
+    (128, [3, 8, 9, 10, 17, 40, 63], 1),
+    (4096, list(range(5, 2048, 7)) + [2048], 1),    # 293 of 2048 bins, ragged
+])
+def test_sparse_synthesis_vs_oracle(ctx, T, idx, add):
+    """Synthesis over a listed subset of the frequencies equals the oracle's
+    inverse DFT with every other coefficient zero (Sec. IV, Table 1)."""
+    rng = np.random.default_rng(T + len(idx))
+    m, F = 29, T // 2
+    idx = np.array(idx, dtype=np.int32)
+    dk = 12.0 / F
+    Us = (seeded_complex(rng, (m, len(idx))) / idx[None, :] ** 0.5).astype(np.complex64)
+    pulses = [Pulse("gauss", {"sigma": 0.8}), Pulse("ricker", {"sigma": 1.1})]
+    c = np.stack([opulse.coefficients(p, F, dk, T, -5.0) for p in pulses])
+    cs = np.ascontiguousarray(c[:, idx - 1])
+    xp = rng.uniform(-5, 5, (m, 3))
+    out = torch.zeros((2, m, T), dtype=torch.float32, device="cuda")
+    native.pulse_synthesize_sparse(ctx, m, idx, dev(Us), 2, dev(cs), T, add, dev(xp), dk, out)
+    got = out.cpu().numpy()
+    Ufull = np.zeros((m, F), dtype=np.complex128)
+    Ufull[:, idx - 1] = Us
+    for q in range(2):
+        cz = np.zeros(F, dtype=np.complex128)
+        cz[idx - 1] = c[q, idx - 1]
+        ref = opulse.synthesize(Ufull, cz, T, xp, dk, add_incident=bool(add))
+        assert rel(got[q], ref) < 1e-5, rel(got[q], ref)
+    with pytest.raises(native.BemError):   # not increasing
+        native.pulse_synthesize_sparse(ctx, m, idx[::-1].copy(), dev(Us), 2, dev(cs), T, add,
+                                       dev(xp), dk, out)
+    with pytest.raises(native.BemError):   # beyond T/2
+        native.pulse_synthesize_sparse(ctx, m, np.array([1, F + 1], np.int32), dev(Us), 2,
+                                       dev(cs), T, add, dev(xp), dk, out)
+
+
+def scattered_field(ctx, ds, k, pts):
+    """U[m][n_k] (c64) of the field scattered from e^{ikz} at pts, through the
+    direct solve (refined FP32 factors) and the field kernel."""
+    nk, n, m = len(k), ds.n, len(pts)
+    kd = dev(np.asarray(k, dtype=np.float64))
+    y = torch.empty((nk, 1, n), dtype=torch.complex128, device="cuda")
+    native.bem_incident(ctx, ds.struct, nk, kd, (0.0, 0.0, 1.0), y)
+    x = torch.zeros((nk, 1, n), dtype=torch.complex128, device="cuda")
+    opts = native.bem_solve_opts_default()
+    opts.mode = native.BEM_FP32_IR_B3
+    info = native.bem_solve_batched(ctx, [(ds.struct, nk, kd, 1, y)], opts, [x])
+    assert all(info[q].converged == 1 for q in range(nk))
+    phi, psi = torch.empty_like(x), torch.empty_like(x)
+    native.bem_split_unknowns(ctx, ds.struct, nk, 1, x, y, phi, psi)
+    U = torch.zeros((1, m, nk), dtype=torch.complex64, device="cuda")
+    i0 = torch.zeros(m, dtype=torch.int32, device="cuda")
+    ins = torch.zeros(m, dtype=torch.uint8, device="cuda")
+    native.bem_field_eval(ctx, ds.struct, nk, kd, 1, phi, psi, m, dev(pts), i0, 0, ins,
+                          native.BEM_C64, U)
+    return U[0]
+
+
+@pytest.mark.parametrize("level", [3, 4])
+def test_dominant_frequency_truncation(ctx, level):
+    """Sec. IV A, Table 1: the soft sphere under the paper's pulse (2 N_c = 4,
+    alpha = 0.1, w = 20.1 a, 128 samples), its scattered wave at z = -1.1 a and
+    -4 a rebuilt from only the 5, 10 and 20 frequencies of largest |c_m|, each
+    solved on its own.  (i) The truncated wave matches the oracle's (FP64 BEM
+    at the same frequencies) to 1e-5; (ii) the sparse synthesis of the n
+    solved frequencies equals the full-grid synthesis with the other
+    coefficients zero; (iii) the % RMS errors reproduce the printed table."""
+    import json
+    import os
+    from workloads import paper_sphere_pulse
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table1.json")))
+    W, T, F = 20.1, 128, 63
+    dk = 2 * np.pi / W
+    c = native.bem_pulse_coeffs("paper", [2.0, 0.1, W], dk, F, T, -(1.0 + W / 4))
+    pts = np.array([[0.0, 0.0, -1.1], [0.0, 0.0, -4.0]])
+    bodies = [Body((0.0, 0.0, 0.0), 1.0, 1.0, level, SOFT)]
+    ds = DeviceSurface.from_bodies(bodies)
+    s = Surface(bodies)
+    xp = dev(pts)
+    Ufull = scattered_field(ctx, ds, dk * np.arange(1, F + 1), pts)
+    full = torch.zeros((1, 2, T), dtype=torch.float32, device="cuda")
+    native.pulse_synthesize(ctx, 2, F, Ufull, 1, dev(c[None, :]), T, 0, xp, dk, full)
+    full = full.cpu().numpy()[0]
+    for n, e11, e4 in zip(gold["n_terms"], gold["rms_percent_at_z_minus_1p1"],
+                          gold["rms_percent_at_z_minus_4"]):
+        idx = native.bem_pulse_dominant(c, n)
+        assert np.array_equal(idx, opulse.dominant(c, n) + 1)
+        Us = scattered_field(ctx, ds, dk * idx, pts)
+        cs = dev(np.ascontiguousarray(c[idx - 1])[None, :])
+        tr = torch.zeros((1, 2, T), dtype=torch.float32, device="cuda")
+        native.pulse_synthesize_sparse(ctx, 2, idx, Us, 1, cs, T, 0, xp, dk, tr)
+        tr = tr.cpu().numpy()[0]
+        # (ii) same as zeroing the other coefficients of the full grid
+        cz = np.zeros_like(c)
+        cz[idx - 1] = c[idx - 1]
+        zf = torch.zeros((1, 2, T), dtype=torch.float32, device="cuda")
+        native.pulse_synthesize(ctx, 2, F, Ufull, 1, dev(cz[None, :]), T, 0, xp, dk, zf)
+        assert rel(tr, zf.cpu().numpy()[0]) < 1e-5
+        if level == 3:
+            # (i) oracle: FP64 BEM at the selected frequencies only
+            Uo = np.zeros((2, F), dtype=np.complex128)
+            for mm in idx:
+                phi, psi = bie.scatter_plane_wave(s, dk * mm)
+                Uo[:, mm - 1] = ofield.field(s, dk * mm, phi, psi, pts)[0]
+            ref = opulse.synthesize(Uo, cz, T)
+            assert rel(tr, ref) < 1e-5, rel(tr, ref)
+        # (iii) Table 1 within the printed precision
+        tol = gold["printed_precision"] + 1e-9
+        assert abs(opulse.rms_error_percent(tr[0], full[0]) - e11) <= tol
+        assert abs(opulse.rms_error_percent(tr[1], full[1]) - e4) <= tol
 
 
 @pytest.mark.parametrize("levels,nk", [((3, 3), 70), ((4, 3), 9), ((4, 4), 5)])
