@@ -64,7 +64,7 @@ bem_status bem_ctx_set_workspace_limit(bem_ctx* ctx, uint64_t bytes);
  * credited with its algorithmic work; bem_ctx_kernel_stats returns the sums
  * (flops, bytes, milliseconds of device time, launch count) since profiling
  * was last switched (set_profiling resets them).  Kernel names: "gemm_c32",
- * "gemm_3m", "gemm_b3", "gemm_b3_narrow", "gemm_b3_packed", "pack", "gemm_c64",
+ * "gemm_3m", "gemm_b3", "gemm_b3_narrow", "gemm_b3_packed", "gemm_small", "pack", "gemm_c64",
  * "panel", "laswp", "trsm", "assemble", "residual", "getrs", "field", "synth".
  * For "assemble"/"residual" the flop slot counts node pairs and for "field"
  * kernel terms (point x frequency x node).  Unknown names report zeros.
@@ -314,6 +314,21 @@ bem_status pulse_synthesize(bem_ctx* ctx, int32_t m, int32_t n_k, const void* U,
                             int32_t n_pulse, const double* c, int32_t T, int32_t add_incident,
                             const double* xp, double dk, float* p);
 
+/* The same synthesis over a subset of the frequencies (Sec. IV, discussion of
+ * Fig. RMSerror and Table 1: the space-time field rebuilt from the solutions at
+ * only the wavenumbers whose incident amplitudes |c_m| are largest; every other
+ * bin is zero):
+ *   p_q(x, t_n) = sum_j alpha_{m_j} Re[ c_q,j X_j(x) e^{-2 pi i m_j n / T} ]
+ * with X_j = U_j(x) (+ e^{i m_j dk z} when add_incident != 0).
+ *   m_index[n_sel] [host] int32: 1-based frequency indices, strictly
+ *   increasing, at most T/2 (copied to the device before return);
+ *   U[m][n_sel] [dev] c64; c[n_pulse][n_sel] [dev] c128; xp, dk, T, p as for
+ *   pulse_synthesize.  EINVAL for an index list that breaks these rules. */
+bem_status pulse_synthesize_sparse(bem_ctx* ctx, int32_t m, int32_t n_sel,
+                                   const int32_t* m_index, const void* U, int32_t n_pulse,
+                                   const double* c, int32_t T, int32_t add_incident,
+                                   const double* xp, double dk, float* p);
+
 /* Fourier coefficients of a periodic incident pulse train F(z - t - z_shift)
  * sampled at T left-closed points s_n = -L/2 + n L/T, L = 2 pi/dk:
  *   c_m = (1/T) sum_n F(s_n) e^{-i k_m s_n} e^{-i k_m z_shift},  k_m = m dk,
@@ -327,6 +342,14 @@ bem_status pulse_synthesize(bem_ctx* ctx, int32_t m, int32_t n_k, const void* U,
  * c_out[n_k] [host] c128. */
 bem_status bem_pulse_coeffs(int32_t kind, const double* params, int32_t n_params, double dk,
                             int32_t n_k, int32_t T, double z_shift, double* c_out);
+
+/* The n_keep frequencies of largest incident amplitude (Sec. IV, Table 1:
+ * 5, 10 or 20 of the largest |P~(w_m)| kept).  Ranking by |c_m| (hypot of
+ * the float64 parts) descending, equal magnitudes by lower m; the selection
+ * is returned as 1-based indices m in increasing order.
+ *   c[n_k] [host] c128; m_index[n_keep] [host] int32 (output);
+ *   0 < n_keep <= n_k, else EINVAL. */
+bem_status bem_pulse_dominant(const double* c, int32_t n_k, int32_t n_keep, int32_t* m_index);
 
 /* ---------------------------------------------------------------- surrogate
  * A small network mapping a wavenumber to the surface unknowns of a fixed

@@ -255,6 +255,7 @@ extern "C" void bem_ctx_destroy(bem_ctx* ctx) {
   if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->pack) (void)hipFree(ctx->pack);
+  if (ctx->midx) (void)hipFree(ctx->midx);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   resolve_stats(ctx);
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
@@ -931,5 +932,43 @@ extern "C" bem_status pulse_synthesize(bem_ctx* ctx, int32_t m, int32_t n_k, con
       T < 64 || T > 8192 || (T & (T - 1)) != 0 || 2 * n_k > T || !(dk > 0.0) || !std::isfinite(dk))
     return fail(ctx, BEM_EINVAL, "pulse_synthesize: bad argument");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
-  return launch_synth(ctx, m, n_k, U, n_pulse, c, T, add_incident, xp, dk, p);
+  return launch_synth(ctx, m, n_k, U, nullptr, n_pulse, c, T, add_incident, xp, dk, p);
+}
+
+extern "C" bem_status pulse_synthesize_sparse(bem_ctx* ctx, int32_t m, int32_t n_sel,
+                                              const int32_t* m_index, const void* U,
+                                              int32_t n_pulse, const double* c, int32_t T,
+                                              int32_t add_incident, const double* xp, double dk,
+                                              float* p) {
+  if (!ctx) return BEM_EINVAL;
+  if (m < 0 || n_sel <= 0 || !m_index || n_pulse <= 0 || !c || (m > 0 && (!U || !p)) ||
+      (add_incident && !xp) || T < 64 || T > 8192 || (T & (T - 1)) != 0 || !(dk > 0.0) ||
+      !std::isfinite(dk))
+    return fail(ctx, BEM_EINVAL, "pulse_synthesize_sparse: bad argument");
+  for (int j = 0; j < n_sel; ++j)
+    if (m_index[j] < 1 || m_index[j] > T / 2 || (j > 0 && m_index[j] <= m_index[j - 1]))
+      return fail(ctx, BEM_EINVAL,
+                  "pulse_synthesize_sparse: m_index must increase strictly within 1..T/2 "
+                  "(entry %d is %d)", j, m_index[j]);
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
+  if (m == 0) return BEM_OK;
+  const size_t bytes = sizeof(int32_t) * (size_t)n_sel;
+  if (bytes > ctx->midx_cap) {
+    if (ctx->midx) {
+      BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      BEM_HIP_TRY(ctx, hipFree(ctx->midx));
+      ctx->midx = nullptr;
+      ctx->midx_cap = 0;
+    }
+    if (hipMalloc((void**)&ctx->midx, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->midx = nullptr;
+      return fail(ctx, BEM_ENOMEM, "pulse_synthesize_sparse: index buffer");
+    }
+    ctx->midx_cap = bytes;
+  }
+  BEM_HIP_TRY(ctx, hipMemcpyAsync(ctx->midx, m_index, bytes, hipMemcpyHostToDevice, ctx->stream));
+  // the host list may be reused as soon as the call returns
+  BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return launch_synth(ctx, m, n_sel, U, ctx->midx, n_pulse, c, T, add_incident, xp, dk, p);
 }

@@ -51,6 +51,9 @@ struct bem_ctx {
   // operands of the trailing updates split into bf16 words (grown on demand)
   void* pack = nullptr;
   size_t pack_size = 0;
+  // frequency indices of a sparse synthesis (grown on demand)
+  int32_t* midx = nullptr;
+  size_t midx_cap = 0;
 };
 
 namespace bem {
@@ -160,7 +163,10 @@ bem_status launch_inside(bem_ctx*, const bem_surface*, int m, const double* xp,
 bem_status launch_field(bem_ctx*, const bem_surface*, int n_k, const double* k, int n_rhs,
                         const void* phi, const void* psi, int m, const double* xp,
                         const int32_t* i0, const uint8_t* inside, bem_prec prec, void* U);
-bem_status launch_synth(bem_ctx*, int m, int n_k, const void* U, int n_pulse, const double* c,
-                        int T, int add_incident, const double* xp, double dk, float* p);
+// m_index (device, or NULL for the dense grid m = 1..n_k): frequency index of
+// each column of U and c
+bem_status launch_synth(bem_ctx*, int m, int n_k, const void* U, const int32_t* m_index,
+                        int n_pulse, const double* c, int T, int add_incident, const double* xp,
+                        double dk, float* p);
 
 }  // namespace bem

@@ -2,6 +2,7 @@
 // fundamental pulse of Eq. pulse is replicated into an infinite train, sampled
 // at N_f points per period and transformed by a DFT; the time origin enters as
 // the phase factor e^{i beta}).  Host code; n_k * T complex exponentials.
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <vector>
@@ -82,5 +83,23 @@ extern "C" bem_status bem_pulse_coeffs(int32_t kind, const double* params, int32
     c_out[2 * (m - 1)] = c.real();
     c_out[2 * (m - 1) + 1] = c.imag();
   }
+  return BEM_OK;
+}
+
+extern "C" bem_status bem_pulse_dominant(const double* c, int32_t n_k, int32_t n_keep,
+                                         int32_t* m_index) {
+  if (!c || !m_index || n_k <= 0 || n_keep <= 0 || n_keep > n_k) return BEM_EINVAL;
+  std::vector<double> mag(n_k);
+  for (int m = 0; m < n_k; ++m) {
+    if (!std::isfinite(c[2 * m]) || !std::isfinite(c[2 * m + 1])) return BEM_EINVAL;
+    mag[m] = std::hypot(c[2 * m], c[2 * m + 1]);
+  }
+  std::vector<int32_t> order(n_k);
+  for (int m = 0; m < n_k; ++m) order[m] = m;
+  // descending magnitude; the stable sort keeps equal magnitudes in index order
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return mag[a] > mag[b]; });
+  std::sort(order.begin(), order.begin() + n_keep);
+  for (int j = 0; j < n_keep; ++j) m_index[j] = order[j] + 1;
   return BEM_OK;
 }

@@ -10,6 +10,11 @@
 // whose output z_n gives p_{2n} = Re z_n, p_{2n+1} = Im z_n.
 // One workgroup per point: U is read once, every pulse is written as T
 // contiguous floats.  HBM traffic: 8F bytes read + 4 T n_pulse written per point.
+//
+// Sparse form (Sec. IV: the space-time field rebuilt from only the frequencies
+// of largest incident amplitude): U and c hold n_sel columns whose frequency
+// indices m_j are listed; every other bin of the half spectrum is zero.  An LDS
+// map from bin to column replaces the dense indexing, the FFT is unchanged.
 #include "common.h"
 
 namespace bem {
@@ -21,8 +26,11 @@ __device__ inline float2 cm(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// LDS: tw[T/2] = e^{2 pi i j/T}; buf0/buf1 ping-pong of length T/2; U row.
+// LDS: tw[T/2] = e^{2 pi i j/T}; buf0/buf1 ping-pong of length T/2; U row;
+// (sparse) col[T/2 + 1]: column of bin m, or -1.
+template <bool Sparse>
 __global__ __launch_bounds__(kST) void synth_kernel(int m, int n_k, const float2* __restrict__ U,
+                                                    const int32_t* __restrict__ midx,
                                                     int n_pulse, const double2* __restrict__ c,
                                                     int T, int logH, int add_incident,
                                                     const double* __restrict__ xp, double dk,
@@ -33,6 +41,7 @@ __global__ __launch_bounds__(kST) void synth_kernel(int m, int n_k, const float2
   float2* b0 = lds + H;
   float2* b1 = b0 + H;
   float2* X = b1 + H;  // [n_k] field of this point (scattered + incident)
+  int* col = reinterpret_cast<int*>(X + n_k);
   const int p = blockIdx.x;
   const int tid = threadIdx.x;
   for (int j = tid; j < H; j += kST) {
@@ -40,12 +49,19 @@ __global__ __launch_bounds__(kST) void synth_kernel(int m, int n_k, const float2
     sincospif(2.0f * (float)j / (float)T, &s, &co);
     tw[j] = make_float2(co, s);
   }
+  if (Sparse) {
+    for (int j = tid; j <= H; j += kST) col[j] = -1;
+    __syncthreads();
+    for (int j = tid; j < n_k; j += kST) col[midx[j]] = j;
+  }
   const double z = add_incident ? xp[3 * p + 2] : 0.0;
   for (int mm = tid; mm < n_k; mm += kST) {
     float2 u = U[(int64_t)p * n_k + mm];
     if (add_incident) {
-      // e^{i k_m z}, k_m = (mm+1) dk; phase reduced in float64
-      double t = (double)(mm + 1) * dk * z * 0.15915494309189533576888376337251;
+      // e^{i k_m z}, k_m = m dk (m = mm + 1, or the listed index); phase
+      // reduced in float64
+      const int mf = Sparse ? midx[mm] : mm + 1;
+      double t = (double)mf * dk * z * 0.15915494309189533576888376337251;
       t -= rint(t);
       float s, co;
       sincospif(2.0f * (float)t, &s, &co);
@@ -60,15 +76,17 @@ __global__ __launch_bounds__(kST) void synth_kernel(int m, int n_k, const float2
     // W_m for m = 0..H-1 from Y_m = conj(c_m X_m) (Y_0 = 0, Y_m = 0 for m > n_k)
     for (int mm = tid; mm < H; mm += kST) {
       float2 ya = make_float2(0.f, 0.f), yb = make_float2(0.f, 0.f);
-      if (mm >= 1 && mm <= n_k) {
-        const double2 cc = cq[mm - 1];
-        const float2 v = cm(make_float2((float)cc.x, (float)cc.y), X[mm - 1]);
+      const int ja = Sparse ? (mm >= 1 ? col[mm] : -1) : (mm >= 1 && mm <= n_k ? mm - 1 : -1);
+      if (ja >= 0) {
+        const double2 cc = cq[ja];
+        const float2 v = cm(make_float2((float)cc.x, (float)cc.y), X[ja]);
         ya = make_float2(v.x, -v.y);
       }
       const int mb = H - mm;  // Y_{H-m}; for m = 0 this is the Nyquist bin (real part only)
-      if (mb >= 1 && mb <= n_k) {
-        const double2 cc = cq[mb - 1];
-        const float2 v = cm(make_float2((float)cc.x, (float)cc.y), X[mb - 1]);
+      const int jb = Sparse ? (mb >= 1 ? col[mb] : -1) : (mb >= 1 && mb <= n_k ? mb - 1 : -1);
+      if (jb >= 0) {
+        const double2 cc = cq[jb];
+        const float2 v = cm(make_float2((float)cc.x, (float)cc.y), X[jb]);
         yb = mm == 0 ? make_float2(v.x, 0.f) : make_float2(v.x, -v.y);
       }
       // conj(yb)
@@ -110,22 +128,30 @@ __global__ __launch_bounds__(kST) void synth_kernel(int m, int n_k, const float2
 
 }  // namespace
 
-bem_status launch_synth(bem_ctx* ctx, int m, int n_k, const void* U, int n_pulse, const double* c,
-                        int T, int add_incident, const double* xp, double dk, float* p) {
+bem_status launch_synth(bem_ctx* ctx, int m, int n_k, const void* U, const int32_t* m_index,
+                        int n_pulse, const double* c, int T, int add_incident, const double* xp,
+                        double dk, float* p) {
   if (m <= 0 || n_pulse <= 0) return BEM_OK;
   int logH = 0;
   while ((1 << logH) < T / 2) ++logH;
-  const size_t lds = sizeof(float2) * (size_t)(3 * (T / 2) + n_k);
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipFuncSetAttribute((const void*)synth_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        160 * 1024);
-    attr_set = true;
+  const bool sparse = m_index != nullptr;
+  const size_t lds = sizeof(float2) * (size_t)(3 * (T / 2) + n_k) +
+                     (sparse ? sizeof(int) * (size_t)(T / 2 + 1) : 0);
+  static bool attr_set[2] = {false, false};
+  const void* fn = sparse ? (const void*)synth_kernel<true> : (const void*)synth_kernel<false>;
+  if (!attr_set[sparse]) {
+    hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set[sparse] = true;
   }
   const int pi = prof_begin(ctx, "synth");
-  hipLaunchKernelGGL(synth_kernel, dim3(m), dim3(kST), lds, ctx->stream, m, n_k,
-                     (const float2*)U, n_pulse, (const double2*)c, T, logH, add_incident, xp, dk,
-                     p);
+  if (sparse)
+    hipLaunchKernelGGL(synth_kernel<true>, dim3(m), dim3(kST), lds, ctx->stream, m, n_k,
+                       (const float2*)U, m_index, n_pulse, (const double2*)c, T, logH,
+                       add_incident, xp, dk, p);
+  else
+    hipLaunchKernelGGL(synth_kernel<false>, dim3(m), dim3(kST), lds, ctx->stream, m, n_k,
+                       (const float2*)U, nullptr, n_pulse, (const double2*)c, T, logH,
+                       add_incident, xp, dk, p);
   // algorithmic HBM traffic: U read once, every pulse written once
   prof_end(ctx, "synth", pi, 0.0, 8.0 * m * n_k + 4.0 * (double)n_pulse * m * T);
   BEM_CHECK_LAUNCH(ctx);

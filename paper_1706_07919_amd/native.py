@@ -28,7 +28,8 @@ EXPORTED = [
     "bem_mesh_counts", "bem_mesh_icosphere", "bem_incident", "bem_assemble", "bem_residual",
     "bem_solve_opts_default", "bem_solve_batched", "bem_getrf_batched", "bem_getrs_batched",
     "bem_autotune_lu",
-    "bem_split_unknowns", "bem_field_eval", "pulse_synthesize", "bem_pulse_coeffs",
+    "bem_split_unknowns", "bem_field_eval", "pulse_synthesize", "pulse_synthesize_sparse",
+    "bem_pulse_coeffs", "bem_pulse_dominant",
     "bem_residual_check", "bem_refine_batched", "bem_mlp_features", "bem_mlp_dense_fwd", "bem_mlp_dense_bwd",
     "bem_mlp_mse_grad", "bem_mlp_adam", "bem_mlp_pack", "bem_mlp_unpack",
 ]
@@ -98,7 +99,10 @@ def load(path: str = LIB_PATH):
         "bem_field_eval": ([vp, C.POINTER(bem_surface), i32, vp, i32, vp, vp, i32, vp, vp, i32, vp,
                             C.c_int, vp], C.c_int),
         "pulse_synthesize": ([vp, i32, i32, vp, i32, vp, i32, i32, vp, dbl, vp], C.c_int),
+        "pulse_synthesize_sparse": ([vp, i32, i32, vp, vp, i32, vp, i32, i32, vp, dbl, vp],
+                                    C.c_int),
         "bem_pulse_coeffs": ([i32, vp, i32, dbl, i32, i32, dbl, vp], C.c_int),
+        "bem_pulse_dominant": ([vp, i32, i32, vp], C.c_int),
         "bem_residual_check": ([vp, C.POINTER(bem_surface), i32, vp, i32, vp, vp, vp], C.c_int),
         "bem_refine_batched": ([vp, C.POINTER(bem_surface), i32, vp, i32, vp, vp, i32, i64, vp, i32,
                                 vp, dbl, i32, vp, C.POINTER(bem_solve_info)], C.c_int),
@@ -210,6 +214,14 @@ def bem_pulse_coeffs(kind, params, dk, n_k, T, z_shift):
     return out.view(np.complex128)
 
 
+def bem_pulse_dominant(c, n_keep):
+    """1-based indices of the n_keep largest |c_m|, in increasing order."""
+    cc = np.ascontiguousarray(c, dtype=np.complex128)
+    out = np.empty(int(n_keep), dtype=np.int32)
+    _check(load().bem_pulse_dominant(cc.ctypes.data, len(cc), int(n_keep), out.ctypes.data))
+    return out
+
+
 # ---------------------------------------------------------------- device entry points
 def surface_struct(n, x, nrm, w, bc):
     return bem_surface(int(n), _ptr(x), _ptr(nrm), _ptr(w), _ptr(bc))
@@ -287,6 +299,13 @@ def bem_field_eval(ctx, surf, n_k, k, n_rhs, phi, psi, m, xp, i0, i0_given, insi
 def pulse_synthesize(ctx, m, n_k, U, n_pulse, c, T, add_incident, xp, dk, p):
     _check(load().pulse_synthesize(ctx.handle, m, n_k, _ptr(U), n_pulse, _ptr(c), T,
                                    int(add_incident), _ptr(xp), float(dk), _ptr(p)), ctx)
+
+
+def pulse_synthesize_sparse(ctx, m, m_index, U, n_pulse, c, T, add_incident, xp, dk, p):
+    idx = np.ascontiguousarray(m_index, dtype=np.int32)
+    _check(load().pulse_synthesize_sparse(ctx.handle, m, len(idx), idx.ctypes.data, _ptr(U),
+                                          n_pulse, _ptr(c), T, int(add_incident), _ptr(xp),
+                                          float(dk), _ptr(p)), ctx)
 
 
 def bem_residual_check(ctx, surf, n_k, k, n_rhs, y, x):

@@ -97,3 +97,27 @@ def test_pulse_coefficients_invalid(lib):
         native.bem_pulse_coeffs("gauss", [0.5], -1.0, 8, 64, 0.0)
     with pytest.raises(native.BemError):
         native.bem_pulse_coeffs(9, [0.5], 1.0, 8, 64, 0.0)
+
+
+def test_dominant_selection_matches_oracle(lib):
+    c = opulse.coefficients(paper_sphere_pulse(), 63, 2 * np.pi / 20.1, 128, -(1.0 + 20.1 / 4))
+    for n in (1, 5, 10, 20, 63):
+        got = native.bem_pulse_dominant(c, n)
+        assert np.array_equal(got, opulse.dominant(c, n) + 1)
+    # equal magnitudes rank by lower index
+    tie = np.array([0.5, 1.0, 1j, -1.0, 0.25 + 0j, -1j])
+    assert list(native.bem_pulse_dominant(tie, 2)) == [2, 3]
+    assert list(native.bem_pulse_dominant(tie, 4)) == [2, 3, 4, 6]
+    assert np.array_equal(native.bem_pulse_dominant(tie, 3), opulse.dominant(tie, 3) + 1)
+    rng = np.random.default_rng(3)
+    r = rng.standard_normal(200) + 1j * rng.standard_normal(200)
+    assert np.array_equal(native.bem_pulse_dominant(r, 37), opulse.dominant(r, 37) + 1)
+
+
+def test_dominant_selection_invalid(lib):
+    with pytest.raises(native.BemError):
+        native.bem_pulse_dominant(np.ones(4, complex), 5)
+    with pytest.raises(native.BemError):
+        native.bem_pulse_dominant(np.ones(4, complex), 0)
+    with pytest.raises(native.BemError):
+        native.bem_pulse_dominant(np.array([1.0, np.nan]), 1)

@@ -108,3 +108,29 @@ def test_smooth_pulse_coefficients_match_continuous_transform(kind, params):
         a = lambda q: sg * np.sqrt(2 * np.pi) * np.exp(-0.5 * (q * sg) ** 2)
         ft = (a(k - k0) - a(k + k0)) / 2j
     assert np.max(np.abs(c - ft / L)) < 1e-12 * L
+
+
+def test_table1_from_oracle_bem():
+    """The oracle's own BEM (soft sphere, icosphere level 3, 642 nodes) in place
+    of the series: the same truncated reconstructions land within the printed
+    precision of Table 1 (Sec. IV A).  About 13 s of CPU."""
+    from oracle import bie, field
+    from oracle.mesh import Surface
+    from workloads import Body, SOFT
+    t1 = json.load(open(os.path.join(GOLD, "table1.json")))
+    P = paper_sphere_pulse()
+    c = pulse.coefficients(P, 63, DK, T, pulse.paper_time_shift(1.0, W))
+    s = Surface([Body((0.0, 0.0, 0.0), 1.0, 1.0, 3, SOFT)])
+    pts = np.array([[0.0, 0.0, -1.1], [0.0, 0.0, -4.0]])
+    U = np.zeros((2, 63), dtype=np.complex128)
+    for m in range(1, 64):
+        phi, psi = bie.scatter_plane_wave(s, DK * m)
+        U[:, m - 1] = field.field(s, DK * m, phi, psi, pts)[0]
+    full = pulse.synthesize(U, c, T)
+    for n, e11, e4 in zip(t1["n_terms"], t1["rms_percent_at_z_minus_1p1"], t1["rms_percent_at_z_minus_4"]):
+        idx = pulse.dominant(c, n)
+        ct = np.zeros_like(c)
+        ct[idx] = c[idx]
+        tr = pulse.synthesize(U, ct, T)
+        assert abs(pulse.rms_error_percent(tr[0], full[0]) - e11) <= t1["printed_precision"] + 1e-9
+        assert abs(pulse.rms_error_percent(tr[1], full[1]) - e4) <= t1["printed_precision"] + 1e-9
