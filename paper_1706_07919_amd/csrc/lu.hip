@@ -1010,19 +1010,23 @@ __global__ __launch_bounds__(256, 4) void gemm_c32_tsb_kernel(LuGroups G, int ro
 
 // ============================================================== GEMM f32, small width and depth
 // The smallest updates inside the panels (N, K <= 16: the pairs of 8-column
-// panels and of 16-column halves) are bound by moving C: one thread per row
-// holds its row of A and C in registers and takes B (K x N, zero-padded) from
-// LDS, in float32 FMA.  Rows move as 16-byte words when they are aligned.
+// panels and of 16-column halves) are bound by moving C.  NK/2 adjacent lanes
+// share a row, each holding two columns of A and of C (one 16-byte word when
+// aligned), so a wave reads whole row segments; the lanes of a row exchange
+// their A values by shuffles and take B (K x N, zero-padded) from LDS.
+// float32 FMA.
 template <int NK>
 __global__ __launch_bounds__(256) void gemm_c32_small_kernel(LuGroups G, int rowC, int colC,
                                                              int colA, int rowB, int rowEnd,
                                                              int colEnd, int K) {
-  __shared__ float2 Bs[NK][NK];
+  constexpr int LPR = NK / 2;           // lanes per row
+  constexpr int RPB = 256 / LPR;        // rows per workgroup
+  __shared__ __align__(16) float2 Bs[NK][NK];
   LuGroup grp;
   int b = 0;
   if (!locate(G, blockIdx.y, grp, b)) return;
   const int M = min(rowEnd, grp.n) - rowC, N = min(colEnd, grp.n) - colC;
-  if (M <= 0 || N <= 0 || (int)(blockIdx.x * 256) >= M) return;
+  if (M <= 0 || N <= 0 || (int)(blockIdx.x * RPB) >= M) return;
   const int64_t ld = grp.ld;
   GLOBAL float2* base = gmat<float2>(grp, b);
   const int t = threadIdx.x;
@@ -1031,45 +1035,48 @@ __global__ __launch_bounds__(256) void gemm_c32_small_kernel(LuGroups G, int row
     Bs[kk][j] = (kk < K && j < N) ? base[(int64_t)(rowB + kk) * ld + colC + j] : make_float2(0.f, 0.f);
   }
   __syncthreads();
-  const int row = blockIdx.x * 256 + t;
-  if (row >= M) return;
-  const GLOBAL float2* Ar = base + (int64_t)(rowC + row) * ld + colA;
-  GLOBAL float2* Cr = base + (int64_t)(rowC + row) * ld + colC;
+  const int l = t % LPR;                // this lane's columns: 2l, 2l + 1
+  const int row = blockIdx.x * RPB + t / LPR;
+  // rows past the end load the last row and store nothing; every lane stays
+  // in the shuffles
+  const bool live = row < M;
+  const int rr = min(row, M - 1);
+  const GLOBAL float2* Ar = base + (int64_t)(rowC + rr) * ld + colA;
+  GLOBAL float2* Cr = base + (int64_t)(rowC + rr) * ld + colC;
   const bool vec = ((ld | colA | colC) & 1) == 0;
-  float2 a[NK], c[NK];
+  float2 a0, a1, c0, c1;
   if (vec && K == NK && N == NK) {
-#pragma unroll
-    for (int m = 0; m < NK / 2; ++m) {
-      const float4 va = ((const GLOBAL float4*)Ar)[m], vc = ((const GLOBAL float4*)Cr)[m];
-      a[2 * m] = make_float2(va.x, va.y);
-      a[2 * m + 1] = make_float2(va.z, va.w);
-      c[2 * m] = make_float2(vc.x, vc.y);
-      c[2 * m + 1] = make_float2(vc.z, vc.w);
-    }
+    const float4 va = ((const GLOBAL float4*)Ar)[l], vc = ((const GLOBAL float4*)Cr)[l];
+    a0 = make_float2(va.x, va.y);
+    a1 = make_float2(va.z, va.w);
+    c0 = make_float2(vc.x, vc.y);
+    c1 = make_float2(vc.z, vc.w);
   } else {
-#pragma unroll
-    for (int q = 0; q < NK; ++q) {
-      a[q] = Ar[min(q, K - 1)];
-      if (q >= K) a[q] = make_float2(0.f, 0.f);
-      c[q] = Cr[min(q, N - 1)];
-    }
+    const int k0 = 2 * l, k1 = 2 * l + 1;
+    a0 = Ar[min(k0, K - 1)];
+    a1 = Ar[min(k1, K - 1)];
+    if (k0 >= K) a0 = make_float2(0.f, 0.f);
+    if (k1 >= K) a1 = make_float2(0.f, 0.f);
+    c0 = Cr[min(k0, N - 1)];
+    c1 = Cr[min(k1, N - 1)];
   }
+  const int g0 = (t % 64) - l;          // first lane of this row within the wave
 #pragma unroll
-  for (int kk = 0; kk < NK; ++kk)
-#pragma unroll
-    for (int j = 0; j < NK; ++j) {
-      const float2 bv = Bs[kk][j];
-      c[j].x -= a[kk].x * bv.x - a[kk].y * bv.y;
-      c[j].y -= a[kk].x * bv.y + a[kk].y * bv.x;
-    }
+  for (int kk = 0; kk < NK; ++kk) {
+    const float2 own = (kk & 1) ? a1 : a0;
+    const float ar = __shfl(own.x, g0 + kk / 2, 64), ai = __shfl(own.y, g0 + kk / 2, 64);
+    const float4 bv = *reinterpret_cast<const float4*>(&Bs[kk][2 * l]);
+    c0.x -= ar * bv.x - ai * bv.y;
+    c0.y -= ar * bv.y + ai * bv.x;
+    c1.x -= ar * bv.z - ai * bv.w;
+    c1.y -= ar * bv.w + ai * bv.z;
+  }
+  if (!live) return;
   if (vec && N == NK) {
-#pragma unroll
-    for (int m = 0; m < NK / 2; ++m)
-      ((GLOBAL float4*)Cr)[m] = make_float4(c[2 * m].x, c[2 * m].y, c[2 * m + 1].x, c[2 * m + 1].y);
+    ((GLOBAL float4*)Cr)[l] = make_float4(c0.x, c0.y, c1.x, c1.y);
   } else {
-#pragma unroll
-    for (int j = 0; j < NK; ++j)
-      if (j < N) Cr[j] = c[j];
+    if (2 * l < N) Cr[2 * l] = c0;
+    if (2 * l + 1 < N) Cr[2 * l + 1] = c1;
   }
 }
 
@@ -1677,13 +1684,14 @@ struct Fac {
     } else {
       const int tn = (N + G32_BN - 1) / G32_BN, tm = (M + G32_BM - 1) / G32_BM;
       if (N <= 16 && K <= 16) {
-        const dim3 grid((unsigned)((M + 255) / 256), total);
         if (N <= 8 && K <= 8)
-          hipLaunchKernelGGL(gemm_c32_small_kernel<8>, grid, dim3(256), 0, ctx->stream, G, rowC,
-                             colC, colA, rowB, rowEnd, colEnd, K);
+          hipLaunchKernelGGL(gemm_c32_small_kernel<8>, dim3((unsigned)((M + 63) / 64), total),
+                             dim3(256), 0, ctx->stream, G, rowC, colC, colA, rowB, rowEnd, colEnd,
+                             K);
         else
-          hipLaunchKernelGGL(gemm_c32_small_kernel<16>, grid, dim3(256), 0, ctx->stream, G, rowC,
-                             colC, colA, rowB, rowEnd, colEnd, K);
+          hipLaunchKernelGGL(gemm_c32_small_kernel<16>, dim3((unsigned)((M + 31) / 32), total),
+                             dim3(256), 0, ctx->stream, G, rowC, colC, colA, rowB, rowEnd, colEnd,
+                             K);
       } else if (gkind == kGemmBf16x3 && N <= 64) {
         const int tmt = (M + GT_BM - 1) / GT_BM, tnt = (N + GT_BN - 1) / GT_BN;
         hipLaunchKernelGGL(gemm_c32_tsb_kernel, dim3(tmt * tnt, total), dim3(256), 0, ctx->stream,
