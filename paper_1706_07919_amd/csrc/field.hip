@@ -272,17 +272,20 @@ bem_status field_go(bem_ctx* ctx, const bem_surface* s, int n_k, const double* k
   C* Snode = (C*)ws;
   const int fch = (n_k + FCH - 1) / FCH;
   dim3 gnode((s->n + kFT - 1) / kFT, fch, n_rhs);
+  // the profiling bracket covers both passes: the field at the nodes (the
+  // expansion centres) and at the points
+  const int pi = prof_begin(ctx, "field");
   hipLaunchKernelGGL((field_kernel<R, FCH, 0>), gnode, dim3(kFT), 0, ctx->stream, s->n, s->x,
                      s->nrm, s->w, k, n_k, n_rhs, (const double2*)phi, (const double2*)psi, s->n,
                      s->x, (const int32_t*)nullptr, (const uint8_t*)nullptr, Snode, (C*)nullptr);
   BEM_CHECK_LAUNCH(ctx);
   dim3 gpts((m + kFT - 1) / kFT, fch, n_rhs);
-  const int pi = prof_begin(ctx, "field");
   hipLaunchKernelGGL((field_kernel<R, FCH, 1>), gpts, dim3(kFT), 0, ctx->stream, s->n, s->x,
                      s->nrm, s->w, k, n_k, n_rhs, (const double2*)phi, (const double2*)psi, m, xp,
                      i0, inside, Snode, (C*)U);
-  // kernel terms: one per (point, frequency, node, rhs)
-  prof_end(ctx, "field", pi, (double)m * n_k * s->n * n_rhs, (double)sizeof(C) * m * n_k * n_rhs);
+  // kernel terms: one per (point or node, frequency, node, rhs)
+  prof_end(ctx, "field", pi, ((double)m + s->n) * n_k * s->n * n_rhs,
+           (double)sizeof(C) * ((double)m + s->n) * n_k * n_rhs);
   BEM_CHECK_LAUNCH(ctx);
   return BEM_OK;
 }
