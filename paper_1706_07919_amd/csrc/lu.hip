@@ -1496,6 +1496,8 @@ __global__ __launch_bounds__(TS_T) void getrs_kernel(int n, int64_t ld, int64_t 
   __threadfence_block();
   __syncthreads();
   const int nb = (n + TS_B - 1) / TS_B;
+  // every off-diagonal range starts at an even column (0, or a multiple of 64)
+  const bool vec2 = sizeof(C) == 8 && ((ld | stride) & 1) == 0 && ((uintptr_t)LU & 15) == 0;
   for (int pass = 0; pass < 2; ++pass) {
     const bool fwd = pass == 0;
     for (int step = 0; step < nb; ++step) {
@@ -1511,18 +1513,44 @@ __global__ __launch_bounds__(TS_T) void getrs_kernel(int n, int64_t ld, int64_t 
       for (int rr = wid; rr < rows; rr += NW) {
         const C* Li = Lb + (int64_t)(i0 + rr) * ld;
         R sr = 0, si = 0, sr2 = 0, si2 = 0;
-        int j = jlo + lane;
-        for (; j + 64 < jhi; j += 128) {
-          const C l0 = Li[j], v0 = x[j], l1 = Li[j + 64], v1 = x[j + 64];
-          sr += l0.x * v0.x - l0.y * v0.y;
-          si += l0.x * v0.y + l0.y * v0.x;
-          sr2 += l1.x * v1.x - l1.y * v1.y;
-          si2 += l1.x * v1.y + l1.y * v1.x;
-        }
-        if (j < jhi) {
-          const C l0 = Li[j], v0 = x[j];
-          sr += l0.x * v0.x - l0.y * v0.y;
-          si += l0.x * v0.y + l0.y * v0.x;
+        if (vec2) {
+          // complex float rows with even ld and start: each lane takes pairs of
+          // elements as 16-byte words, two pairs per iteration
+          int j = jlo + 2 * lane;
+          for (; j + 129 < jhi; j += 256) {
+            const float4 la = *reinterpret_cast<const float4*>(Li + j);
+            const float4 lb = *reinterpret_cast<const float4*>(Li + j + 128);
+            const C a0 = x[j], a1 = x[j + 1], b0 = x[j + 128], b1 = x[j + 129];
+            sr += (la.x * a0.x - la.y * a0.y) + (la.z * a1.x - la.w * a1.y);
+            si += (la.x * a0.y + la.y * a0.x) + (la.z * a1.y + la.w * a1.x);
+            sr2 += (lb.x * b0.x - lb.y * b0.y) + (lb.z * b1.x - lb.w * b1.y);
+            si2 += (lb.x * b0.y + lb.y * b0.x) + (lb.z * b1.y + lb.w * b1.x);
+          }
+          for (; j + 1 < jhi; j += 128) {
+            const float4 la = *reinterpret_cast<const float4*>(Li + j);
+            const C a0 = x[j], a1 = x[j + 1];
+            sr += (la.x * a0.x - la.y * a0.y) + (la.z * a1.x - la.w * a1.y);
+            si += (la.x * a0.y + la.y * a0.x) + (la.z * a1.y + la.w * a1.x);
+          }
+          if (j < jhi) {
+            const C l0 = Li[j], v0 = x[j];
+            sr += l0.x * v0.x - l0.y * v0.y;
+            si += l0.x * v0.y + l0.y * v0.x;
+          }
+        } else {
+          int j = jlo + lane;
+          for (; j + 64 < jhi; j += 128) {
+            const C l0 = Li[j], v0 = x[j], l1 = Li[j + 64], v1 = x[j + 64];
+            sr += l0.x * v0.x - l0.y * v0.y;
+            si += l0.x * v0.y + l0.y * v0.x;
+            sr2 += l1.x * v1.x - l1.y * v1.y;
+            si2 += l1.x * v1.y + l1.y * v1.x;
+          }
+          if (j < jhi) {
+            const C l0 = Li[j], v0 = x[j];
+            sr += l0.x * v0.x - l0.y * v0.y;
+            si += l0.x * v0.y + l0.y * v0.x;
+          }
         }
         sr += sr2;
         si += si2;

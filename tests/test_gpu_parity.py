@@ -450,6 +450,33 @@ def test_invalid_inputs_rejected(ctx):
         native.bem_assemble(ctx, ds.struct, 1, k, 1, y, native.BEM_C64, A, s.n - 1, b, None)
 
 
+def test_empty_point_sets_are_no_ops(ctx):
+    """Zero observation points: the field and both syntheses return at once
+    and leave their outputs untouched (the index list of the sparse form is
+    still checked)."""
+    bodies = mixed_bodies(1)
+    ds = DeviceSurface.from_bodies(bodies)
+    k = dev(np.array([0.5, 1.0]))
+    phi = torch.zeros((2, 1, ds.n), dtype=torch.complex128, device="cuda")
+    xp = dev(np.zeros((1, 3)))
+    i0 = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+    ins = torch.full((1,), 5, dtype=torch.uint8, device="cuda")
+    U = torch.full((1, 1, 2), 3.0, dtype=torch.complex64, device="cuda")
+    native.bem_field_eval(ctx, ds.struct, 2, k, 1, phi, phi, 0, xp, i0, 0, ins,
+                          native.BEM_C64, U)
+    c = dev(np.ones((1, 2), dtype=np.complex128))
+    p = torch.full((1, 1, 64), 2.0, dtype=torch.float32, device="cuda")
+    native.pulse_synthesize(ctx, 0, 2, U[0], 1, c, 64, 0, xp, 0.1, p)
+    native.pulse_synthesize_sparse(ctx, 0, np.array([3, 9], np.int32), U[0], 1, c, 64, 0, xp,
+                                   0.1, p)
+    with pytest.raises(native.BemError):
+        native.pulse_synthesize_sparse(ctx, 0, np.array([9, 3], np.int32), U[0], 1, c, 64, 0,
+                                       xp, 0.1, p)
+    torch.cuda.synchronize()
+    assert i0.item() == 7 and ins.item() == 5
+    assert np.all(U.cpu().numpy() == 3.0) and np.all(p.cpu().numpy() == 2.0)
+
+
 # ------------------------------------------------------------------ S7/S8
 def _field_setup(ctx, bodies, k, xp):
     s = Surface(bodies)
