@@ -321,7 +321,9 @@ bem_status pulse_synthesize(bem_ctx* ctx, int32_t m, int32_t n_k, const void* U,
  *   p_q(x, t_n) = sum_j alpha_{m_j} Re[ c_q,j X_j(x) e^{-2 pi i m_j n / T} ]
  * with X_j = U_j(x) (+ e^{i m_j dk z} when add_incident != 0).
  *   m_index[n_sel] [host] int32: 1-based frequency indices, strictly
- *   increasing, at most T/2 (copied to the device before return);
+ *   increasing, at most T/2 (copied to device memory of the context; the call
+ *   waits for the context stream's earlier work so the host list may be
+ *   reused when it returns);
  *   U[m][n_sel] [dev] c64; c[n_pulse][n_sel] [dev] c128; xp, dk, T, p as for
  *   pulse_synthesize.  EINVAL for an index list that breaks these rules. */
 bem_status pulse_synthesize_sparse(bem_ctx* ctx, int32_t m, int32_t n_sel,
