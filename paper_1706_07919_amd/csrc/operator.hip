@@ -153,7 +153,7 @@ struct Phase {
 // (column rhs of y).  WRITE_A: write the matrix row and the diagonal
 // (first pass); later passes only form b for further right-hand sides.
 template <bool OUT128, bool WRITE_A>
-__global__ __launch_bounds__(kThreads) void assemble_kc_kernel(
+__global__ __launch_bounds__(kThreads, 3) void assemble_kc_kernel(
     int n, const double* __restrict__ x, const double* __restrict__ nrm,
     const double* __restrict__ w, const uint8_t* __restrict__ bc, const double* __restrict__ kv,
     int nk, int n_rhs, int rhs, const double2* __restrict__ y, void* __restrict__ A, int64_t ld,
