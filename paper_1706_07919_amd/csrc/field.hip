@@ -101,7 +101,7 @@ constexpr int kFT = 256, kNJ = 64;
 // MODE 0: write S(x_p) for points = nodes (raw, [rhs][n_k][n]).
 // MODE 1: write P(x_p) = phi_a + (S(x_p) - S(x_a)) / (4 pi) into U[rhs][m][n_k].
 template <typename R, int FCH, int MODE>
-__global__ __launch_bounds__(kFT) void field_kernel(
+__global__ __launch_bounds__(kFT, sizeof(R) == 4 ? 3 : 1) void field_kernel(
     int n, const double* __restrict__ x, const double* __restrict__ nrm,
     const double* __restrict__ w, const double* __restrict__ kv, int n_k, int n_rhs,
     const double2* __restrict__ phi, const double2* __restrict__ psi, int m,
