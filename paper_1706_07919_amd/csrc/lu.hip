@@ -1030,15 +1030,10 @@ __global__ __launch_bounds__(256) void gemm_c32_small_kernel(LuGroups G, int row
   const int64_t ld = grp.ld;
   GLOBAL float2* base = gmat<float2>(grp, b);
   const int t = threadIdx.x;
-  for (int e = t; e < NK * NK; e += 256) {
-    const int kk = e / NK, j = e % NK;
-    Bs[kk][j] = (kk < K && j < N) ? base[(int64_t)(rowB + kk) * ld + colC + j] : make_float2(0.f, 0.f);
-  }
-  __syncthreads();
   const int l = t % LPR;                // this lane's columns: 2l, 2l + 1
   const int row = blockIdx.x * RPB + t / LPR;
   // rows past the end load the last row and store nothing; every lane stays
-  // in the shuffles
+  // in the shuffles and the barrier
   const bool live = row < M;
   const int rr = min(row, M - 1);
   const GLOBAL float2* Ar = base + (int64_t)(rowC + rr) * ld + colA;
@@ -1060,6 +1055,12 @@ __global__ __launch_bounds__(256) void gemm_c32_small_kernel(LuGroups G, int row
     c0 = Cr[min(k0, N - 1)];
     c1 = Cr[min(k1, N - 1)];
   }
+  // B after this thread's row loads, so the two loads overlap
+  for (int e = t; e < NK * NK; e += 256) {
+    const int kk = e / NK, j = e % NK;
+    Bs[kk][j] = (kk < K && j < N) ? base[(int64_t)(rowB + kk) * ld + colC + j] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
   const int g0 = (t % 64) - l;          // first lane of this row within the wave
 #pragma unroll
   for (int kk = 0; kk < NK; ++kk) {
