@@ -106,6 +106,25 @@ bem_status bem_mesh_icosphere(int32_t level, double radius, double aspect,
                               const double center[3], int32_t rescale_area,
                               double* x, double* nrm, double* w, int32_t* faces);
 
+/* The axisymmetric acoustic bowl of Sec. IV C (Eq. dish): the closed meridian
+ * curve xi = a sin(theta), eta = a (0.2 cos(theta) - 0.6 sin^2(theta)),
+ * 0 <= theta <= pi, rotated about the eta axis -- a thin curved shell whose
+ * faces meet at a sharp rim.  Nodes: the pole theta = 0, rings
+ * theta_i = pi i / n_theta (0 < i < n_theta) of n_phi nodes at
+ * phi_j = 2 pi j / n_phi, the pole theta = pi; local frame
+ * (xi cos phi, xi sin phi, eta), then the eta axis turned by `tilt` about x
+ * (y' = y cos t - z sin t, z' = y sin t + z cos t) and shifted by `center`.
+ * Normals are analytic (outward normal of the meridian curve); weights are one
+ * third of the adjacent flat-triangle areas.  Outputs [host], caller-allocated
+ * with bem_mesh_bowl_counts() entries (x[V][3], nrm[V][3], w[V], faces[F][3]
+ * or NULL); fixed evaluation order, reproducible bit for bit.  EINVAL for
+ * n_theta < 2, n_phi < 3 or radius <= 0. */
+bem_status bem_mesh_bowl_counts(int32_t n_theta, int32_t n_phi, int32_t* n_vertices,
+                                int32_t* n_faces);
+bem_status bem_mesh_bowl(int32_t n_theta, int32_t n_phi, double radius, double tilt,
+                         const double center[3], double* x, double* nrm, double* w,
+                         int32_t* faces);
+
 /* ---------------------------------------------------------------- incident
  * Known surface data of the scattered field for the incident plane wave
  * e^{ik d.x} (Sec. IV A): y = -dP_inc/dn = -ik (d.n) e^{ik d.x} on hard nodes,

@@ -144,3 +144,96 @@ class Surface:
     @property
     def n(self) -> int:
         return self.x.shape[0]
+
+
+# ---------------------------------------------------------------- acoustic bowl
+def bowl_counts(n_theta: int, n_phi: int):
+    """(nodes, faces) of the bowl mesh: two poles and n_theta - 1 rings."""
+    return 2 + (n_theta - 1) * n_phi, 2 * n_phi * (n_theta - 1)
+
+
+def bowl(n_theta: int, n_phi: int, radius: float = 1.0, tilt: float = 0.0,
+         center=(0.0, 0.0, 0.0)):
+    """The axisymmetric bowl of Sec. IV C (Eq. dish): the closed meridian curve
+    xi = a sin(theta), eta = a (0.2 cos(theta) - 0.6 sin^2(theta)),
+    0 <= theta <= pi, rotated about the eta axis; a thin curved shell whose
+    two faces meet at a sharp rim (xi = a, eta = -0.6 a).
+
+    Nodes: the pole theta = 0, rings theta_i = pi i / n_theta (i = 1 ..
+    n_theta - 1) of n_phi nodes at phi_j = 2 pi j / n_phi, the pole theta = pi.
+    Local frame (xi cos phi, xi sin phi, eta); the eta axis is then turned by
+    `tilt` about x (y' = y cos t - z sin t, z' = y sin t + z cos t) and shifted
+    by `center`.  Normals are analytic: in the meridian plane the outward
+    normal of the curve is (-eta', xi') / |(xi', eta')|.  Weights: one third of
+    the adjacent flat-triangle areas (no rescaling).
+
+    Returns (x [V,3], nrm [V,3], w [V], faces [F,3] int32)."""
+    assert n_theta >= 2 and n_phi >= 3
+    V, F = bowl_counts(n_theta, n_phi)
+    ct, st = math.cos(tilt), math.sin(tilt)
+    cx, cy, cz = center
+    loc = []      # local (x, y, z) and normal
+    # top pole
+    loc.append(((0.0, 0.0, radius * (0.2 * math.cos(0.0))), (0.0, 0.0, 1.0)))
+    for i in range(1, n_theta):
+        th = (math.pi * i) / n_theta
+        s, c = math.sin(th), math.cos(th)
+        xi = radius * s
+        eta = radius * (0.2 * c - 0.6 * (s * s))
+        dxi = c
+        deta = -0.2 * s - 1.2 * (s * c)
+        m = math.sqrt(dxi * dxi + deta * deta)
+        nxi, neta = -deta / m, dxi / m
+        for j in range(n_phi):
+            ph = (2.0 * math.pi * j) / n_phi
+            cp, sp = math.cos(ph), math.sin(ph)
+            loc.append(((xi * cp, xi * sp, eta), (nxi * cp, nxi * sp, neta)))
+    # bottom pole
+    loc.append(((0.0, 0.0, radius * (0.2 * math.cos(math.pi))), (0.0, 0.0, -1.0)))
+    x = np.empty((V, 3))
+    nrm = np.empty((V, 3))
+    for k, ((px, py, pz), (qx, qy, qz)) in enumerate(loc):
+        x[k, 0] = cx + px
+        x[k, 1] = cy + (py * ct - pz * st)
+        x[k, 2] = cz + (py * st + pz * ct)
+        nrm[k, 0] = qx
+        nrm[k, 1] = qy * ct - qz * st
+        nrm[k, 2] = qy * st + qz * ct
+    faces = []
+    for j in range(n_phi):
+        faces.append((0, 1 + j, 1 + (j + 1) % n_phi))
+    for i in range(1, n_theta - 1):
+        r0 = 1 + (i - 1) * n_phi
+        r1 = r0 + n_phi
+        for j in range(n_phi):
+            j1 = (j + 1) % n_phi
+            faces.append((r0 + j, r1 + j, r1 + j1))
+            faces.append((r0 + j, r1 + j1, r0 + j1))
+    rl = 1 + (n_theta - 2) * n_phi
+    for j in range(n_phi):
+        faces.append((V - 1, rl + (j + 1) % n_phi, rl + j))
+    w = [0.0] * V
+    for (a, b, c) in faces:
+        pa, pb, pc = x[a], x[b], x[c]
+        e1 = (float(pb[0] - pa[0]), float(pb[1] - pa[1]), float(pb[2] - pa[2]))
+        e2 = (float(pc[0] - pa[0]), float(pc[1] - pa[1]), float(pc[2] - pa[2]))
+        c0 = e1[1] * e2[2] - e1[2] * e2[1]
+        c1 = e1[2] * e2[0] - e1[0] * e2[2]
+        c2 = e1[0] * e2[1] - e1[1] * e2[0]
+        third = (0.5 * math.sqrt((c0 * c0 + c1 * c1) + c2 * c2)) / 3.0
+        w[a] = w[a] + third
+        w[b] = w[b] + third
+        w[c] = w[c] + third
+    return x, nrm, np.array(w, dtype=np.float64), np.array(faces, dtype=np.int32)
+
+
+class ArraySurface:
+    """A surface given by its arrays (nodes, normals, weights, BC flags)."""
+
+    def __init__(self, x, nrm, w, bc):
+        self.x, self.nrm, self.w = x, nrm, w
+        self.bc = np.asarray(bc, dtype=np.uint8)
+
+    @property
+    def n(self) -> int:
+        return self.x.shape[0]

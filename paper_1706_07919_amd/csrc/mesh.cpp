@@ -132,3 +132,85 @@ extern "C" bem_status bem_mesh_icosphere(int32_t level, double radius, double as
     for (size_t t = 0; t < f.size(); ++t) faces[t] = f[t];
   return BEM_OK;
 }
+
+// The axisymmetric bowl of Sec. IV C (Eq. dish): the closed meridian curve
+// xi = a sin(theta), eta = a (0.2 cos(theta) - 0.6 sin^2(theta)) rotated about
+// the eta axis, meshed by poles and rings of constant theta.
+extern "C" bem_status bem_mesh_bowl_counts(int32_t n_theta, int32_t n_phi, int32_t* n_vertices,
+                                           int32_t* n_faces) {
+  if (n_theta < 2 || n_phi < 3 || n_theta > 4096 || n_phi > 8192 || !n_vertices || !n_faces)
+    return BEM_EINVAL;
+  *n_vertices = 2 + (n_theta - 1) * n_phi;
+  *n_faces = 2 * n_phi * (n_theta - 1);
+  return BEM_OK;
+}
+
+extern "C" bem_status bem_mesh_bowl(int32_t n_theta, int32_t n_phi, double radius, double tilt,
+                                    const double center[3], double* x, double* nrm, double* w,
+                                    int32_t* faces) {
+  int32_t V = 0, F = 0;
+  if (bem_mesh_bowl_counts(n_theta, n_phi, &V, &F) != BEM_OK || !(radius > 0.0) ||
+      !std::isfinite(radius) || !std::isfinite(tilt) || !center || !x || !nrm || !w)
+    return BEM_EINVAL;
+  const double ct = std::cos(tilt), st = std::sin(tilt);
+  const double cx = center[0], cy = center[1], cz = center[2];
+  auto place = [&](int k, double px, double py, double pz, double qx, double qy, double qz) {
+    x[3 * k + 0] = cx + px;
+    x[3 * k + 1] = cy + (py * ct - pz * st);
+    x[3 * k + 2] = cz + (py * st + pz * ct);
+    nrm[3 * k + 0] = qx;
+    nrm[3 * k + 1] = qy * ct - qz * st;
+    nrm[3 * k + 2] = qy * st + qz * ct;
+  };
+  place(0, 0.0, 0.0, radius * (0.2 * std::cos(0.0)), 0.0, 0.0, 1.0);
+  int k = 1;
+  for (int i = 1; i < n_theta; ++i) {
+    const double th = (M_PI * i) / n_theta;
+    const double s = std::sin(th), c = std::cos(th);
+    const double xi = radius * s;
+    const double eta = radius * (0.2 * c - 0.6 * (s * s));
+    // outward normal of the meridian curve: (-eta', xi') / |(xi', eta')|
+    const double dxi = c;
+    const double deta = -0.2 * s - 1.2 * (s * c);
+    const double m = std::sqrt(dxi * dxi + deta * deta);
+    const double nxi = -deta / m, neta = dxi / m;
+    for (int j = 0; j < n_phi; ++j) {
+      const double ph = (2.0 * M_PI * j) / n_phi;
+      const double cp = std::cos(ph), sp = std::sin(ph);
+      place(k++, xi * cp, xi * sp, eta, nxi * cp, nxi * sp, neta);
+    }
+  }
+  place(V - 1, 0.0, 0.0, radius * (0.2 * std::cos(M_PI)), 0.0, 0.0, -1.0);
+  std::vector<int32_t> f;
+  f.reserve(3 * (size_t)F);
+  auto tri = [&](int a, int b, int c) { f.push_back(a); f.push_back(b); f.push_back(c); };
+  for (int j = 0; j < n_phi; ++j) tri(0, 1 + j, 1 + (j + 1) % n_phi);
+  for (int i = 1; i < n_theta - 1; ++i) {
+    const int r0 = 1 + (i - 1) * n_phi, r1 = r0 + n_phi;
+    for (int j = 0; j < n_phi; ++j) {
+      const int j1 = (j + 1) % n_phi;
+      tri(r0 + j, r1 + j, r1 + j1);
+      tri(r0 + j, r1 + j1, r0 + j1);
+    }
+  }
+  const int rl = 1 + (n_theta - 2) * n_phi;
+  for (int j = 0; j < n_phi; ++j) tri(V - 1, rl + (j + 1) % n_phi, rl + j);
+  for (int v = 0; v < V; ++v) w[v] = 0.0;
+  for (size_t t = 0; t < f.size(); t += 3) {
+    const double* pa = x + 3 * f[t];
+    const double* pb = x + 3 * f[t + 1];
+    const double* pc = x + 3 * f[t + 2];
+    const double e1x = pb[0] - pa[0], e1y = pb[1] - pa[1], e1z = pb[2] - pa[2];
+    const double e2x = pc[0] - pa[0], e2y = pc[1] - pa[1], e2z = pc[2] - pa[2];
+    const double c0 = e1y * e2z - e1z * e2y;
+    const double c1 = e1z * e2x - e1x * e2z;
+    const double c2 = e1x * e2y - e1y * e2x;
+    const double third = (0.5 * std::sqrt((c0 * c0 + c1 * c1) + c2 * c2)) / 3.0;
+    w[f[t]] = w[f[t]] + third;
+    w[f[t + 1]] = w[f[t + 1]] + third;
+    w[f[t + 2]] = w[f[t + 2]] + third;
+  }
+  if (faces)
+    for (size_t t = 0; t < f.size(); ++t) faces[t] = f[t];
+  return BEM_OK;
+}

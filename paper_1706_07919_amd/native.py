@@ -25,7 +25,7 @@ PULSE_KINDS = {"paper": 0, "gauss": 1, "ricker": 2, "nwave": 3, "chirp": 4, "gsi
 EXPORTED = [
     "bem_ctx_create", "bem_ctx_destroy", "bem_last_error", "bem_ctx_set_workspace_limit",
     "bem_ctx_set_profiling", "bem_ctx_set_profiling_filter", "bem_ctx_kernel_stats",
-    "bem_mesh_counts", "bem_mesh_icosphere", "bem_incident", "bem_assemble", "bem_residual",
+    "bem_mesh_counts", "bem_mesh_icosphere", "bem_mesh_bowl_counts", "bem_mesh_bowl", "bem_incident", "bem_assemble", "bem_residual",
     "bem_solve_opts_default", "bem_solve_batched", "bem_getrf_batched", "bem_getrs_batched",
     "bem_autotune_lu",
     "bem_split_unknowns", "bem_field_eval", "pulse_synthesize", "pulse_synthesize_sparse",
@@ -85,6 +85,8 @@ def load(path: str = LIB_PATH):
                                   C.POINTER(i64)], C.c_int),
         "bem_mesh_counts": ([i32, C.POINTER(i32), C.POINTER(i32)], C.c_int),
         "bem_mesh_icosphere": ([i32, dbl, dbl, vp, i32, vp, vp, vp, vp], C.c_int),
+        "bem_mesh_bowl_counts": ([i32, i32, C.POINTER(i32), C.POINTER(i32)], C.c_int),
+        "bem_mesh_bowl": ([i32, i32, dbl, dbl, vp, vp, vp, vp, vp], C.c_int),
         "bem_incident": ([vp, C.POINTER(bem_surface), i32, vp, vp, vp], C.c_int),
         "bem_assemble": ([vp, C.POINTER(bem_surface), i32, vp, i32, vp, C.c_int, vp, i32, vp, vp], C.c_int),
         "bem_residual": ([vp, C.POINTER(bem_surface), i32, vp, i32, vp, vp, vp, vp], C.c_int),
@@ -192,6 +194,18 @@ def bem_mesh_counts(level: int):
     nv, nf = C.c_int32(), C.c_int32()
     _check(load().bem_mesh_counts(level, C.byref(nv), C.byref(nf)))
     return nv.value, nf.value
+
+
+def bem_mesh_bowl(n_theta, n_phi, radius=1.0, tilt=0.0, center=(0.0, 0.0, 0.0)):
+    nv, nf = C.c_int32(), C.c_int32()
+    _check(load().bem_mesh_bowl_counts(int(n_theta), int(n_phi), C.byref(nv), C.byref(nf)))
+    x = np.empty((nv.value, 3)); nrm = np.empty((nv.value, 3)); w = np.empty(nv.value)
+    faces = np.empty((nf.value, 3), dtype=np.int32)
+    c = np.ascontiguousarray(center, dtype=np.float64)
+    _check(load().bem_mesh_bowl(int(n_theta), int(n_phi), float(radius), float(tilt),
+                                c.ctypes.data, x.ctypes.data, nrm.ctypes.data, w.ctypes.data,
+                                faces.ctypes.data))
+    return x, nrm, w, faces
 
 
 def bem_mesh_icosphere(level, radius, aspect, center, rescale_area=True):

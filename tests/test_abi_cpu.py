@@ -121,3 +121,23 @@ def test_dominant_selection_invalid(lib):
         native.bem_pulse_dominant(np.ones(4, complex), 0)
     with pytest.raises(native.BemError):
         native.bem_pulse_dominant(np.array([1.0, np.nan]), 1)
+
+
+@pytest.mark.parametrize("nt,nph,radius,tilt,center", [
+    (2, 3, 1.0, 0.0, (0.0, 0.0, 0.0)),
+    (12, 16, 1.0, 0.15 * np.pi, (0.1, -0.2, 0.3)),
+    (48, 96, 1.3, 0.47, (1.0, 2.0, -3.0)),
+])
+def test_bowl_mesh_bit_exact_vs_oracle(lib, nt, nph, radius, tilt, center):
+    got = native.bem_mesh_bowl(nt, nph, radius, tilt, center)
+    ref = omesh.bowl(nt, nph, radius, tilt, center)
+    for g, r in zip(got, ref):
+        assert np.array_equal(g, r)
+
+
+def test_bowl_mesh_invalid(lib):
+    for args in [(1, 8), (8, 2)]:
+        with pytest.raises(native.BemError):
+            native.bem_mesh_bowl(*args)
+    with pytest.raises(native.BemError):
+        native.bem_mesh_bowl(8, 8, radius=-1.0)

@@ -6,6 +6,7 @@ import os
 import numpy as np
 import pytest
 
+from oracle import mesh
 from oracle.mesh import Surface, icosphere, spheroid_area
 from workloads import Body, HARD, SOFT
 
@@ -77,3 +78,33 @@ def test_multibody_concatenation():
     assert s.n == 42 + 162
     assert np.all(s.bc[:42] == HARD) and np.all(s.bc[42:] == SOFT)
     assert np.all(s.body[:42] == 0) and np.all(s.body[42:] == 1)
+
+
+# ---------------------------------------------------------------- acoustic bowl
+def test_bowl_mesh_against_closed_forms():
+    """The bowl of Sec. IV C (Eq. dish).  Its volume follows in closed form from
+    the thickness of the shell, 0.4 a sqrt(1 - (xi/a)^2) at radius xi:
+    V = 2 pi int_0^a xi 0.4 sqrt(1 - xi^2/a^2) dxi = 0.8 pi a^3 / 3; the
+    divergence theorem gives it from the mesh as (1/3) sum w_j x_j . n_j, which
+    also pins the orientation of the normals.  The lumped area converges at
+    O(h^2) to the surface of revolution's area (a library quadrature), and the
+    flux of a constant field through the closed surface, sum w_j n_j, to 0."""
+    import math
+    from scipy.integrate import quad
+    area = 2 * math.pi * quad(lambda t: math.sin(t) * math.hypot(
+        math.cos(t), -0.2 * math.sin(t) - 1.2 * math.sin(t) * math.cos(t)), 0, math.pi,
+        limit=200)[0]
+    vol = 0.8 * math.pi / 3
+    errs = []
+    for nt, nph in [(8, 16), (16, 32), (32, 64)]:
+        x, n, w, f = mesh.bowl(nt, nph, tilt=0.3, center=(0.5, -1.0, 2.0))
+        assert (len(x), len(f)) == mesh.bowl_counts(nt, nph)
+        assert np.allclose(np.linalg.norm(n, axis=1), 1.0, atol=1e-15)
+        c = np.array([0.5, -1.0, 2.0])
+        v = np.sum(w * np.sum((x - c) * n, axis=1)) / 3.0
+        flux = np.linalg.norm(np.sum(w[:, None] * n, axis=0))
+        errs.append(area - w.sum())
+        if nt >= 16:
+            assert abs(v - vol) < 0.005 * vol
+            assert flux < 0.02
+    assert errs[0] > 0 and 3.0 < errs[0] / errs[1] < 5.0 and 3.0 < errs[1] / errs[2] < 5.0
