@@ -97,7 +97,7 @@ def main():
         return
 
     from paper_1706_07919_amd import DeviceSurface, native
-    from workloads import config2, plane_grid
+    from workloads import two_spheres_workload, plane_grid
 
     if args.copy_calib:
         src = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0")
@@ -106,7 +106,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    w = config2(args.n_k)
+    w = two_spheres_workload(args.n_k)
     n_k = len(w.k)
     dev = torch.device("cuda:0")
     ctx = native.Context(0)
@@ -272,9 +272,9 @@ def run_spacetime(args):
     import torch
 
     from paper_1706_07919_amd import DeviceSurface, native
-    from workloads import config5
+    from workloads import spacetime_workload
 
-    w = config5(n_grid=args.st_grid)
+    w = spacetime_workload(n_grid=args.st_grid)
     ctx = native.Context(0)
     dev = torch.device("cuda:0")
     ds = DeviceSurface.from_bodies(w.bodies)
@@ -502,9 +502,9 @@ def run_uneven(args):
     import torch
 
     from paper_1706_07919_amd import DeviceSurface, native
-    from workloads import config3
+    from workloads import uneven_bodies_workload
 
-    w = config3(n_k=args.uneven_k)
+    w = uneven_bodies_workload(n_k=args.uneven_k)
     nk = len(w.k)
     ctx = native.Context(0)
     dev = torch.device("cuda:0")
@@ -557,10 +557,10 @@ def run_surrogate(args):
 
     from paper_1706_07919_amd import DeviceSurface, native
     from paper_1706_07919_amd import surrogate as sg
-    from workloads import config4, config4_train_k
+    from workloads import surrogate_workload, surrogate_train_k
 
-    w = config4()
-    k_train = config4_train_k(256)
+    w = surrogate_workload()
+    k_train = surrogate_train_k(256)
     k_pred = w.k
     ctx = native.Context(0)
     ds = DeviceSurface.from_bodies(w.bodies)

@@ -10,7 +10,7 @@ import pytest
 
 from oracle import mesh as omesh
 from oracle import pulse as opulse
-from workloads import Body, Pulse, config3, paper_sphere_pulse
+from workloads import Body, Pulse, uneven_bodies_workload, paper_sphere_pulse
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "bem.h")
@@ -51,8 +51,8 @@ def test_mesh_bit_exact_vs_oracle_sphere(lib, level):
     assert w.tobytes() == ow.tobytes()
 
 
-def test_mesh_bit_exact_vs_oracle_config3_bodies(lib):
-    for body in config3().bodies:
+def test_mesh_bit_exact_vs_oracle_uneven_bodies(lib):
+    for body in uneven_bodies_workload().bodies:
         if body.level > 4:
             continue
         for rescale in (True, False):

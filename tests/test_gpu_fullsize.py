@@ -8,7 +8,7 @@ import pytest
 
 from oracle import bie, field as ofield
 from oracle.mesh import Surface
-from workloads import config2, plane_grid
+from workloads import two_spheres_workload, plane_grid
 
 pytestmark = pytest.mark.gpu
 
@@ -21,7 +21,7 @@ from paper_1706_07919_amd import DeviceSurface  # noqa: E402
 def setup():
     assert torch.cuda.is_available()
     ctx = native.Context(0)
-    w = config2(512)
+    w = two_spheres_workload(512)
     ds = DeviceSurface.from_bodies(w.bodies)
     s = Surface(w.bodies)
     yield ctx, w, ds, s

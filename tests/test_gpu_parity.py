@@ -6,7 +6,7 @@ import pytest
 
 from oracle import bie, field as ofield, pulse as opulse
 from oracle.mesh import Surface
-from workloads import Body, HARD, SOFT, Pulse, config1, ring_points, seeded_complex
+from workloads import Body, HARD, SOFT, Pulse, sphere_l2_workload, ring_points, seeded_complex
 
 pytestmark = pytest.mark.gpu
 
@@ -297,8 +297,8 @@ def _solve(ctx, bodies, k, mode, n_rhs=1, rng=None):
 
 @pytest.mark.parametrize("mode", [native.BEM_FP64_DIRECT, native.BEM_FP32_IR_4M, native.BEM_FP32_IR_3M,
                                   native.BEM_FP32_IR_B3])
-def test_solve_config1_vs_oracle(ctx, mode):
-    w = config1()
+def test_solve_sphere_l2_vs_oracle(ctx, mode):
+    w = sphere_l2_workload()
     s = Surface(w.bodies)
     ds, kd, y, x, info = _solve(ctx, w.bodies, w.k, mode)
     x = x.cpu().numpy()[:, 0]
@@ -451,7 +451,7 @@ def test_solve_graph_replays_match_eager(ctx, mode):
 
 def test_solve_ir_fallback_forced(ctx):
     # max_iter = 1 cannot reach the step tolerance: every item falls back to FP64
-    w = config1()
+    w = sphere_l2_workload()
     ds = DeviceSurface.from_bodies(w.bodies)
     k = w.k[:4]
     kd = dev(k)
@@ -469,7 +469,7 @@ def test_solve_ir_fallback_forced(ctx):
 
 
 def test_invalid_inputs_rejected(ctx):
-    w = config1()
+    w = sphere_l2_workload()
     s = Surface(w.bodies)
     bad_n = s.nrm.copy()
     bad_n[5] *= 1.01

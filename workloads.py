@@ -87,7 +87,7 @@ def plane_grid(n: int, half: float = 10.0) -> np.ndarray:
     return np.stack([np.zeros(n * n), yy.ravel(), zz.ravel()], axis=1)
 
 
-def config1() -> Workload:
+def sphere_l2_workload() -> Workload:
     """Single sound-hard sphere, level-2 icosphere (162 nodes), 32 k in (0,6]."""
     return Workload(
         name="sphere_L2_hard_32k",
@@ -97,7 +97,7 @@ def config1() -> Workload:
         T=64, dk=6.0 / 32, z_shift=0.0)
 
 
-def config2(n_k: int = 512) -> Workload:
+def two_spheres_workload(n_k: int = 512) -> Workload:
     """Two sound-hard spheres (2 x 2562 nodes, N = 5124), k in (0,12]."""
     return Workload(
         name="two_spheres_L4_hard_512k",
@@ -107,7 +107,7 @@ def config2(n_k: int = 512) -> Workload:
         T=2 * n_k, dk=12.0 / n_k, z_shift=-12.0)
 
 
-def config3(seed: int = 0, n_k: int = 1024) -> Workload:
+def uneven_bodies_workload(seed: int = 0, n_k: int = 1024) -> Workload:
     """Eight scatterers of uneven size: radius U(0.3,1.5), sphere or prolate
     spheroid (aspect U(1,3)), level in {3,4,5}, one hard/soft flag each.
     Each body is an independent scattering problem."""
@@ -125,18 +125,18 @@ def config3(seed: int = 0, n_k: int = 1024) -> Workload:
                     T=2 * n_k, dk=12.0 / n_k, z_shift=0.0)
 
 
-def config4_train_k(n: int = 256) -> np.ndarray:
+def surrogate_train_k(n: int = 256) -> np.ndarray:
     """Training wavenumbers of the surrogate: cell centres of (0,12]."""
     return 12.0 * (np.arange(1, n + 1, dtype=np.float64) - 0.5) / n
 
 
-def config4() -> Workload:
+def surrogate_workload() -> Workload:
     return Workload(name="surrogate_two_spheres", bodies=two_spheres(4, 0, HARD),
                     k=uniform_k(12.0, 4096), points=np.zeros((0, 3)), pulses=[],
                     T=8192, dk=12.0 / 4096, z_shift=0.0)
 
 
-def config5_pulses(seed: int = 0) -> List[Pulse]:
+def spacetime_pulses(seed: int = 0) -> List[Pulse]:
     """Four incident pulses with seeded widths: Gaussian, Ricker, N-wave, chirp."""
     out = []
     for q, kind in enumerate(("gauss", "ricker", "nwave", "chirp")):
@@ -150,10 +150,10 @@ def config5_pulses(seed: int = 0) -> List[Pulse]:
     return out
 
 
-def config5(n_grid: int = 1024, n_k: int = 2048) -> Workload:
+def spacetime_workload(n_grid: int = 1024, n_k: int = 2048) -> Workload:
     return Workload(name="spacetime_two_spheres_1M", bodies=two_spheres(4, 0, HARD),
                     k=uniform_k(12.0, n_k), points=plane_grid(n_grid),
-                    pulses=config5_pulses(0), T=2 * n_k, dk=12.0 / n_k,
+                    pulses=spacetime_pulses(0), T=2 * n_k, dk=12.0 / n_k,
                     z_shift=-12.0)
 
 
