@@ -32,6 +32,42 @@ PEAK_F64_MFMA = 78.6e12
 PEAK_HBM = 8.0e12
 
 
+# dominant kernel of the factorisation per GEMM form: (stats name, kernel,
+# issued MFMA flops per 4M-equivalent flop, MFMA peak)
+DOMINANT = {
+    "3m": ("gemm_3m", "gemm_c32_lds_kernel<3M, 128x128> (LU trailing updates, complex 3M on "
+                      "MFMA f32, operands streamed into LDS)", 0.75, PEAK_F32_MFMA),
+    "4m": ("gemm_c32", "gemm_c32_lds_kernel<4M, 128x128> (LU trailing updates, complex 4M on "
+                       "MFMA f32, operands streamed into LDS)", 1.0, PEAK_F32_MFMA),
+    "b3": ("gemm_b3_packed", "gemm_c32_b3p_kernel (LU trailing updates, bf16x3 split on MFMA "
+                             "bf16, operands pre-split)", 3.0, PEAK_BF16_MFMA),
+}
+MODES = None     # filled on first use (needs the binding)
+# flops per field term: the compiled inner loop of field_kernel (c64) issues
+# 304 VALU instructions per node and 8 frequencies plus about 60 per node for
+# the float64 geometry and phases, i.e. about 47 single-precision operations
+# per (point, frequency, node) term
+FIELD_FLOPS_PER_TERM = 47.0
+
+
+class KernelTotals:
+    """Per-kernel statistics summed over every profiling window of the run
+    (the library resets its counters whenever profiling is switched)."""
+
+    def __init__(self, ctx, names):
+        self.ctx, self.names = ctx, tuple(names)
+        self.tot = {k: [0.0, 0.0, 0.0, 0] for k in self.names}
+
+    def harvest(self):
+        for k in self.names:
+            f, b, ms, n = self.ctx.kernel_stats(k)
+            t = self.tot[k]
+            t[0] += f
+            t[1] += b
+            t[2] += ms
+            t[3] += n
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -39,11 +75,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-k", type=int, default=512)
     ap.add_argument("--field-grid", type=int, default=64, help="points per side on x = 0")
-    ap.add_argument("--fp64-k", type=int, default=64, help="wavenumbers for the FP64 direct path")
+    ap.add_argument("--fp64-every", type=int, default=8,
+                    help="every this many wavenumbers of the sweep are also solved by the plain "
+                         "FP64 direct path (0: none)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-k", type=int, default=1)
-    ap.add_argument("--mode", choices=["b3", "4m", "3m"], default="b3",
+    ap.add_argument("--cpu-k", type=int, default=8)
+    ap.add_argument("--mode", choices=["b3", "4m", "3m"], default="3m",
                     help="complex GEMM form of the float32 factorisation")
+    ap.add_argument("--b3-steps", type=int, default=2,
+                    help="steps of the bf16x3 variant timed after the headline (0: none)")
+    ap.add_argument("--spacetime", type=int, default=1,
+                    help="1: time the space-time reconstruction (2048 solves, 1024^2 points, "
+                         "4 pulses, T = 4096) after the headline")
     ap.add_argument("--workload", choices=["spheres", "surrogate", "uneven", "spacetime",
                                            "truncation", "bowl"],
                     default="spheres",
@@ -59,9 +102,11 @@ def main():
     ap.add_argument("--tr-grid", type=int, default=256,
                     help="points per side of the x = 0 field grid for --workload truncation")
     ap.add_argument("--st-grid", type=int, default=1024,
-                    help="points per side of the field grid for --workload spacetime")
-    ap.add_argument("--uneven-k", type=int, default=64,
+                    help="points per side of the field grid of the space-time reconstruction")
+    ap.add_argument("--uneven-k", type=int, default=1024,
                     help="wavenumbers per body for --workload uneven")
+    ap.add_argument("--uneven-steps", type=int, default=1,
+                    help="timed passes of --workload uneven")
     ap.add_argument("--nb", type=int, default=0, help="LU block width (0 = library default)")
     ap.add_argument("--autotune", type=int, default=0,
                     help="measure the LU block width on this many matrices before the run")
@@ -87,7 +132,7 @@ def main():
         run_uneven(args)
         return
     if args.workload == "spacetime":
-        run_spacetime(args)
+        print(json.dumps(run_spacetime(args)))
         return
     if args.workload == "truncation":
         run_truncation(args)
@@ -106,10 +151,13 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    modes = {"b3": native.BEM_FP32_IR_B3, "4m": native.BEM_FP32_IR_4M, "3m": native.BEM_FP32_IR_3M}
+    gname, kdesc, issue_per_alg, peak = DOMINANT[args.mode]
     w = two_spheres_workload(args.n_k)
     n_k = len(w.k)
     dev = torch.device("cuda:0")
     ctx = native.Context(0)
+    totals = KernelTotals(ctx, (gname,))
     ds = DeviceSurface.from_bodies(w.bodies)
     n = ds.n
     kd = torch.as_tensor(w.k).to(dev)
@@ -129,9 +177,7 @@ def main():
     ins = torch.zeros(m, dtype=torch.uint8, device=dev)
     p = torch.zeros((1, m, T), dtype=torch.float32, device=dev)
     opts = native.bem_solve_opts_default()
-    mode = {"b3": native.BEM_FP32_IR_B3, "4m": native.BEM_FP32_IR_4M, "3m": native.BEM_FP32_IR_3M}[args.mode]
-    gname = {"b3": "gemm_b3_packed", "4m": "gemm_c32", "3m": "gemm_3m"}[args.mode]
-    opts.mode = mode
+    opts.mode = modes[args.mode]
     opts.nb = args.nb
     tuned = None
     if args.autotune > 0:
@@ -150,11 +196,15 @@ def main():
         native.pulse_synthesize(ctx, m, n_k, U[0], 1, cd, T, 1, xp, w.dk, p)
         infos.append(info)
 
+    # every launch of the dominant kernel is bracketed by HIP events on the
+    # stream it runs on, over the whole run (the roofline averages all of them)
+    ctx.set_profiling_filter((gname,))
+    ctx.set_profiling(True)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    # the timed steps bracket only the kernels the line reports on (the
-    # roofline kernel, field, synthesis) with HIP events
+    totals.harvest()
+    # the timed steps bracket the dominant kernel, the field and the synthesis
     timed_kernels = (gname, "field", "synth")
     ctx.set_profiling_filter(timed_kernels)
     ctx.set_profiling(True)
@@ -166,50 +216,76 @@ def main():
     t1 = time.perf_counter()
     elapsed = t1 - t0
     stats = {kname: ctx.kernel_stats(kname) for kname in timed_kernels}
-    ctx.set_profiling(False)
+    totals.harvest()
     # one more step, untimed, with every counted kernel bracketed: the split of
     # the step by kernel
     ctx.set_profiling_filter(None)
     ctx.set_profiling(True)
     step()
     torch.cuda.synchronize()
-    split = {kname: ctx.kernel_stats(kname)[2] for kname in
-             (gname, "gemm_b3", "gemm_b3_narrow", "gemm_small", "pack", "panel", "laswp", "trsm", "assemble",
-              "residual", "getrs", "field", "synth")}
-    ctx.set_profiling(False)
+    split_names = (gname, gname + "_narrow", "gemm_b3", "gemm_b3_narrow", "gemm_small", "pack",
+                   "panel", "laswp", "trsm", "assemble", "residual", "getrs", "field", "synth")
+    split = {kname: ctx.kernel_stats(kname)[2] for kname in split_names
+             if kname in DOMINANT_SPLIT_OK or ctx.kernel_stats(kname)[3] > 0}
+    totals.harvest()
+    ctx.set_profiling_filter((gname,))
+    ctx.set_profiling(True)
     solves_per_s = n_k * args.steps / elapsed
     info = infos[-1]
     iters = [info[q].iters for q in range(n_k)]
     fallbacks = sum(info[q].used_fp64 for q in range(n_k))
     max_resid = max(info[q].rel_resid for q in range(n_k))
-
-    gf, gb, gms, gl = stats[gname]
-    # stats count complex 4M flops (8 per complex multiply-add); the split form
-    # issues three bf16 MFMA products for each real product
-    mfma_flops = 3.0 * gf if args.mode == "b3" else (0.75 * gf if args.mode == "3m" else gf)
-    peak = PEAK_BF16_MFMA if args.mode == "b3" else PEAK_F32_MFMA
-    achieved = mfma_flops / (gms * 1e-3) if gms > 0 else 0.0
-    alg_4m = gf / (gms * 1e-3) if gms > 0 else 0.0
     ff, fb, fms, fl = stats["field"]
     field_rate = (m * n_k * args.steps) / (fms * 1e-3) if fms > 0 else 0.0
     sf, sb, sms, sl = stats["synth"]
 
-    # plain FP64 direct path on a subset of the wavenumbers
-    fp64_rate = None
-    if args.fp64_k > 0:
-        kk = min(args.fp64_k, n_k)
+    # plain FP64 direct path on every fp64_every-th wavenumber of the sweep
+    # (spread over the whole band): its rate, and the float32 + refinement
+    # result's distance from it
+    fp64_rate, rel64, rel64_max = None, None, None
+    if args.fp64_every > 0:
+        sel = torch.arange(0, n_k, args.fp64_every, device=dev)
+        kk = int(sel.numel())
+        ks = kd[sel].contiguous()
+        ys = y[sel].contiguous()
         x64 = torch.zeros((kk, 1, n), dtype=torch.complex128, device=dev)
         o64 = native.bem_solve_opts_default()
         o64.mode = native.BEM_FP64_DIRECT
-        native.bem_solve_batched(ctx, [(ds.struct, kk, kd[:kk], 1, y[:kk])], o64, [x64])
+        native.bem_solve_batched(ctx, [(ds.struct, kk, ks, 1, ys)], o64, [x64])
         torch.cuda.synchronize()
         ta = time.perf_counter()
-        native.bem_solve_batched(ctx, [(ds.struct, kk, kd[:kk], 1, y[:kk])], o64, [x64])
+        native.bem_solve_batched(ctx, [(ds.struct, kk, ks, 1, ys)], o64, [x64])
         torch.cuda.synchronize()
         fp64_rate = kk / (time.perf_counter() - ta)
-        rel64 = (torch.linalg.vector_norm(x64 - x[:kk]) / torch.linalg.vector_norm(x64)).item()
-    else:
-        rel64 = None
+        d = torch.linalg.vector_norm(x64 - x[sel], dim=(1, 2)) / torch.linalg.vector_norm(x64, dim=(1, 2))
+        rel64, rel64_max = (torch.linalg.vector_norm(x64 - x[sel]) / torch.linalg.vector_norm(x64)).item(), d.max().item()
+        del x64, ys
+
+    # the bf16x3 variant of the same step (not the headline: the products of
+    # its factorisation are bf16)
+    b3 = None
+    if args.b3_steps > 0 and args.mode != "b3":
+        ob3 = native.bem_solve_opts_default()
+        ob3.mode = native.BEM_FP32_IR_B3
+        native.bem_solve_batched(ctx, [(ds.struct, n_k, kd, 1, y)], ob3, [x])
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        for _ in range(args.b3_steps):
+            native.bem_incident(ctx, ds.struct, n_k, kd, (0.0, 0.0, 1.0), y)
+            native.bem_solve_batched(ctx, [(ds.struct, n_k, kd, 1, y)], ob3, [x])
+        torch.cuda.synchronize()
+        b3 = n_k * args.b3_steps / (time.perf_counter() - tb)
+
+    st = None
+    if args.spacetime:
+        del U, p, phi, psi
+        st = run_spacetime(args, ctx=ctx, mode=opts.mode)
+    totals.harvest()
+    ctx.set_profiling(False)
+
+    gf, gb, gms, gl = totals.tot[gname]
+    achieved = issue_per_alg * gf / (gms * 1e-3) if gms > 0 else 0.0
+    alg_rate = gf / (gms * 1e-3) if gms > 0 else 0.0
 
     cpu = None
     if not args.no_cpu:
@@ -227,62 +303,80 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"b3": "c64 LU (bf16x3 split products on bf16 MFMA, f32 accumulate)",
-                  "4m": "c64 LU (f32 MFMA)", "3m": "c64 LU (3M on f32 MFMA)"}[args.mode]
+                  "4m": "c64 LU (complex 4M on f32 MFMA, f32 accumulate)",
+                  "3m": "c64 LU (complex 3M on f32 MFMA, f32 accumulate)"}[args.mode]
                  + " + f64 residual refinement",
         "data": "synthetic",
         "config": {"workload": w.name, "n": n, "n_k": n_k, "field_points": m, "T": T,
                    "mode": {"b3": "FP32_IR_B3", "4m": "FP32_IR_4M", "3m": "FP32_IR_3M"}[args.mode],
                    "nb": opts.nb, "autotuned_nb": tuned[0] if tuned else None},
-        "field_pt_freq_per_s": field_rate,
+        "field_pt_freq_per_s": st["value"] if st else field_rate,
+        "field_pt_freq_per_s_note": ("space-time reconstruction at 1024^2 points x 2048 frequencies "
+                                     "(the step's own 4096-point field is field_pt_freq_per_s_step)"
+                                     if st else "4096 points x 512 frequencies of the step"),
+        "field_pt_freq_per_s_step": field_rate,
         "fp64_direct_solves_per_s": fp64_rate,
         "fp32ir_vs_fp64_direct_rel_err": rel64,
+        "fp32ir_vs_fp64_direct_max_rel_err_per_k": rel64_max,
+        "fp64_direct_sample": f"every {args.fp64_every}th wavenumber of the sweep" if args.fp64_every else None,
+        "b3_solves_per_s": b3,
         "ir_iters_max": max(iters),
         "ir_fallbacks": fallbacks,
         "max_rel_resid": max_resid,
-        "roofline": {"kernel": {"b3": "gemm_c32_b3p_kernel (LU trailing updates, bf16x3 split on "
-                                      "MFMA bf16, operands pre-split)",
-                                "4m": "gemm_c32_kernel (LU updates, complex 4M on MFMA f32)",
-                                "3m": "gemm_c32_3m_kernel (LU updates, complex 3M on MFMA f32)"}[args.mode],
+        "roofline": {"kernel": kdesc,
                      "bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": (measured_traffic("gemm_c32_b3p", args.nb or (tuned[0] if tuned else "default"),
-                                                  gl // args.steps)
-                                 if args.mode == "b3" else None),
+                     "achieved_note": "MFMA flops the kernel issues (3M: 6 MNK, 4M: 8 MNK, bf16x3: "
+                                      "24 MNK per complex update) over the HIP-event time of every "
+                                      "launch of the run",
+                     "traffic": measured_traffic(gname, args.nb or (tuned[0] if tuned else "default"),
+                                                 gl),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                      "scaled by a copy kernel)",
                      "algorithmic_bytes_per_launch": gb / max(gl, 1),
+                     "algorithmic_flops_per_launch": gf / max(gl, 1),
                      "launches": gl, "avg_launch_ms": gms / max(gl, 1),
-                     "complex_4m_equivalent_tflops": alg_4m / 1e12,
-                     "share_of_step": gms * 1e-3 / elapsed},
+                     "algorithmic_tflops": alg_rate / 1e12,
+                     "algorithmic_tflops_note": "8 MNK per complex update (the 4M count)",
+                     "share_of_step": stats[gname][2] * 1e-3 / elapsed},
         "kernels_ms_per_step": split,
         "kernels_ms_per_step_note": "one extra step with every kernel bracketed by events "
                                     "(the timed steps bracket only the roofline kernel, field "
                                     "and synthesis)",
-        "synth_hbm_frac": (sb / (sms * 1e-3)) / PEAK_HBM if sms > 0 else None,
+        "synth_hbm_frac_step": (sb / (sms * 1e-3)) / PEAK_HBM if sms > 0 else None,
+        "spacetime": st,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
 
 
-def run_spacetime(args):
+DOMINANT_SPLIT_OK = ("gemm_small", "panel", "laswp", "trsm", "assemble", "residual", "getrs",
+                     "field", "synth")
+
+
+def run_spacetime(args, ctx=None, mode=None):
     """Whole space-time path at full size: 2048 frequency solves of the two
     spheres, closest node + field at a grid of points on x = 0 for every
-    frequency, and synthesis of four pulses (T = 4096).  One JSON line with
-    the field rate (point x frequency evaluations/s) as the value."""
+    frequency, and synthesis of four pulses (T = 4096).  Returns one dict with
+    the field rate (point x frequency evaluations/s) as the value; the solves
+    run in the given mode (default: 3M refinement)."""
     import torch
 
     from paper_1706_07919_amd import DeviceSurface, native
     from workloads import spacetime_workload
 
     w = spacetime_workload(n_grid=args.st_grid)
-    ctx = native.Context(0)
+    own_ctx = ctx is None
+    if own_ctx:
+        ctx = native.Context(0)
     dev = torch.device("cuda:0")
     ds = DeviceSurface.from_bodies(w.bodies)
     n, nk, T = ds.n, len(w.k), w.T
     xp = torch.as_tensor(w.points).to(dev)
     m = xp.shape[0]
+    npulse = len(w.pulses)
     U = torch.empty((1, m, nk), dtype=torch.complex64, device=dev)
-    p = torch.empty((len(w.pulses), m, T), dtype=torch.float32, device=dev)
+    p = torch.empty((npulse, m, T), dtype=torch.float32, device=dev)
     i0 = torch.empty(m, dtype=torch.int32, device=dev)
     ins = torch.empty(m, dtype=torch.uint8, device=dev)
     kinds = {"gauss": ["sigma"], "ricker": ["sigma"], "nwave": ["sigma"], "chirp": ["ka", "kb", "D"]}
@@ -295,14 +389,15 @@ def run_spacetime(args):
     phi = torch.empty_like(x)
     psi = torch.empty_like(x)
     opts = native.bem_solve_opts_default()
-    opts.mode = native.BEM_FP32_IR_B3
+    opts.mode = mode if mode is not None else native.BEM_FP32_IR_3M
 
     def stamp():
         torch.cuda.synchronize()
         return time.perf_counter()
 
-    # one untimed solve first: the first call sizes and allocates the solver's
-    # workspace around the field and output buffers already resident
+    # every input of the timed path (geometry, wavenumbers, points, pulse
+    # coefficients) is resident before t0; the solver's workspace is sized by
+    # its first call, made here on the same wavenumbers
     native.bem_incident(ctx, ds.struct, nk, kd, (0.0, 0.0, 1.0), y)
     native.bem_solve_batched(ctx, [(ds.struct, nk, kd, 1, y)], opts, [x])
     x.zero_()
@@ -315,24 +410,32 @@ def run_spacetime(args):
     native.bem_field_eval(ctx, ds.struct, nk, kd, 1, phi, psi, m, xp, i0, 0, ins, native.BEM_C64, U)
     t2 = stamp()
     print(f"field {m} x {nk}: {t2 - t1:.2f} s", file=sys.stderr, flush=True)
-    native.pulse_synthesize(ctx, m, nk, U[0], len(w.pulses), cd, T, 1, xp, w.dk, p)
+    native.pulse_synthesize(ctx, m, nk, U[0], npulse, cd, T, 1, xp, w.dk, p)
     t3 = stamp()
-    print(f"synthesis: {t3 - t2:.2f} s", file=sys.stderr, flush=True)
-    syn_bytes = 8.0 * m * nk + 4.0 * len(w.pulses) * m * T
+    print(f"synthesis: {t3 - t2:.3f} s", file=sys.stderr, flush=True)
+    syn_bytes = 8.0 * m * nk + 4.0 * npulse * m * T
+    terms = float(m) * nk * n
     out = {"metric": "field pt*freq evals/sec (space-time path at full size)",
            "value": m * nk / (t2 - t1), "unit": "pt*freq/s", "higher_is_better": True,
            "data": "synthetic", "dtype": "c64 field kernel (f64-centred geometry), f32 synthesis",
-           "config": {"workload": w.name, "n": n, "n_k": nk, "points": m, "pulses": len(w.pulses),
+           "config": {"workload": w.name, "n": n, "n_k": nk, "points": m, "pulses": npulse,
                       "T": T},
            "solve_s": t1 - t0, "solves_per_s": nk / (t1 - t0), "field_s": t2 - t1,
-           "field_terms_per_s": m * nk * n / (t2 - t1),
+           "field_terms_per_s": terms / (t2 - t1),
+           "field_alu_frac": terms * FIELD_FLOPS_PER_TERM / (t2 - t1) / PEAK_F32_MFMA,
+           "field_alu_note": f"{FIELD_FLOPS_PER_TERM:g} float32 operations per term against the "
+                             "157.3 TFLOP/s FP32 vector peak",
            "inside_points": int(ins.sum().item()),
            "synthesis_s": t3 - t2, "synthesis_GBps": syn_bytes / (t3 - t2) / 1e9,
            "synthesis_hbm_frac": syn_bytes / (t3 - t2) / PEAK_HBM,
            "ir_iters_max": max(info[q].iters for q in range(nk)),
+           "ir_fallbacks": sum(info[q].used_fp64 for q in range(nk)),
            "max_rel_resid": max(info[q].rel_resid for q in range(nk)),
            "total_s": t3 - t0}
-    print(json.dumps(out))
+    del U, p, x, y, phi, psi
+    if own_ctx:
+        ctx.close()
+    return out
 
 
 def run_truncation(args):
@@ -362,7 +465,7 @@ def run_truncation(args):
     m = xp.shape[0]
     c = native.bem_pulse_coeffs("paper", [2.0, 0.1, W], dk, F, T, -(1.0 + W / 4))
     opts = native.bem_solve_opts_default()
-    opts.mode = native.BEM_FP32_IR_B3
+    opts.mode = native.BEM_FP32_IR_3M
     i0 = torch.empty(m, dtype=torch.int32, device=dev)
     ins = torch.empty(m, dtype=torch.uint8, device=dev)
 
@@ -448,7 +551,7 @@ def run_bowl(args):
     kd = torch.as_tensor(k).to(dev)
     cd = torch.as_tensor(c[None, :]).to(dev)
     opts = native.bem_solve_opts_default()
-    opts.mode = native.BEM_FP32_IR_B3
+    opts.mode = native.BEM_FP32_IR_3M
     y = torch.empty((F, 1, n), dtype=torch.complex128, device=dev)
     xs = torch.zeros_like(y)
     phi, psi = torch.empty_like(y), torch.empty_like(y)
@@ -497,8 +600,10 @@ def run_bowl(args):
 def run_uneven(args):
     """Eight independent scatterers of uneven size (spheres and prolate
     spheroids, 642 / 2562 / 10242 nodes, hard and soft) solved in one batched
-    call: every recursion step of the factorisation is one launch over all
-    matrices of all sizes.  One JSON line: solves/s over the whole call."""
+    call, 1024 wavenumbers each by default: the solver takes them in rounds
+    that fit the device, and every launch of a round covers all matrices of
+    all sizes.  One JSON line: solves/s over the whole call (one timed pass
+    after a short untimed pass that sizes the workspace)."""
     import torch
 
     from paper_1706_07919_amd import DeviceSurface, native
@@ -520,26 +625,29 @@ def run_uneven(args):
     mode = {"b3": native.BEM_FP32_IR_B3, "4m": native.BEM_FP32_IR_4M, "3m": native.BEM_FP32_IR_3M}[args.mode]
     opts = native.bem_solve_opts_default()
     opts.mode = mode
-    for _ in range(args.warmup):
-        native.bem_solve_batched(ctx, probs, opts, xs)
+    # untimed pass on the first 16 wavenumbers of every body (first launches,
+    # workspace)
+    small = [(s_, 16, k_[:16], 1, y_[:16]) for (s_, _, k_, _, y_) in probs]
+    native.bem_solve_batched(ctx, small, opts, [x_[:16] for x_ in xs])
     torch.cuda.synchronize()
+    steps = max(1, args.uneven_steps)
     t0 = time.perf_counter()
     infos = []
-    for _ in range(args.steps):
+    for _ in range(steps):
         infos.append(native.bem_solve_batched(ctx, probs, opts, xs))
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
+    dt = (time.perf_counter() - t0) / steps
     info = infos[-1]
     tot = len(w.bodies) * nk
     sizes = [ds.n for ds in surfs]
     flops = sum(8.0 * n ** 3 / 3.0 * nk for n in sizes)
     out = {"metric": "uneven batch: frequency solves/s (8 bodies, N in {642, 2562, 10242})",
            "value": tot / dt, "unit": "freq-solves/s", "higher_is_better": True,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt,
-           "data": "synthetic", "dtype": "c64 LU + f64 residual refinement",
+           "steps": steps, "ms_per_step": 1e3 * dt,
+           "data": "synthetic", "dtype": "c64 LU (" + args.mode + " on f32 MFMA) + f64 residual refinement",
            "config": {"workload": w.name, "sizes": sizes, "k_per_body": nk,
                       "mode": args.mode},
-           "lu_complex_4m_equivalent_tflops": flops / dt / 1e12,
+           "lu_algorithmic_tflops": flops / dt / 1e12,
            "ir_iters_max": max(info[q].iters for q in range(len(info))),
            "ir_fallbacks": sum(info[q].used_fp64 for q in range(len(info))),
            "max_rel_resid": max(info[q].rel_resid for q in range(len(info)))}
@@ -570,7 +678,7 @@ def run_surrogate(args):
     yp = torch.empty((nkp, 1, n), dtype=torch.complex128, device=dev)
     native.bem_incident(ctx, ds.struct, nkp, kp, (0.0, 0.0, 1.0), yp)
     opts = native.bem_solve_opts_default()
-    opts.mode = native.BEM_FP32_IR_B3
+    opts.mode = native.BEM_FP32_IR_3M
     x_dir = torch.zeros((nkp, 1, n), dtype=torch.complex128, device=dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -614,12 +722,13 @@ def run_surrogate(args):
 
 # lu.hip section (from its header to the next) holding each profiled kernel
 KERNEL_SECTIONS = {
-    "gemm_c32_b3p": ("GEMM f32 via bf16 split, packed operands", "GEMM f64"),
-    "gemm_c32_b3": ("GEMM f32 via bf16 split\n", "GEMM f32 via bf16 split, narrow"),
+    "gemm_3m": ("GEMM f32, operands streamed into LDS", "GEMM f32 via bf16 split\n"),
+    "gemm_c32": ("GEMM f32, operands streamed into LDS", "GEMM f32 via bf16 split\n"),
+    "gemm_b3_packed": ("GEMM f32 via bf16 split, packed operands", "GEMM f64"),
 }
 
 
-def kernel_source_sha256(kernel="gemm_c32_b3p"):
+def kernel_source_sha256(kernel="gemm_3m"):
     """Hash of the kernel's source section of lu.hip (its block comment,
     helpers and kernels, up to the next section header)."""
     import hashlib
@@ -631,13 +740,14 @@ def kernel_source_sha256(kernel="gemm_c32_b3p"):
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
-def measured_traffic(kernel, block_width="default", launches_per_step=None):
+def measured_traffic(kernel, block_width="default", launches=None, profiles=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, or None when there is none, the kernel's source changed since the
     counters were taken, or the factorisation's block width or the number of
-    launches per step differs (they set the launch sizes)."""
-    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_two_spheres_N5124_nk512.txt")
-    if not os.path.exists(path):
+    launches in the run differs (they set the mix of launch sizes)."""
+    path = os.path.join(profiles or os.path.join(ROOT, "profiles"),
+                        f"pmc_{kernel}_two_spheres_N5124_nk512.txt")
+    if not os.path.exists(path) or kernel not in KERNEL_SECTIONS:
         return None
     vals = {}
     for line in open(path):
@@ -647,14 +757,15 @@ def measured_traffic(kernel, block_width="default", launches_per_step=None):
     if vals.get("kernel_source_sha256") != kernel_source_sha256(kernel) or \
             vals.get("block_width") != str(block_width) or "traffic_bytes_per_launch" not in vals:
         return None
-    if launches_per_step is not None and vals.get("dispatches_per_step") != str(launches_per_step):
+    if launches is not None and vals.get("launches_in_run") != str(launches):
         return None
     return float(vals["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(w, x_gpu, n_cpu_k):
     """The FP64 oracle (numpy/scipy assembly + LAPACK LU) timed on the host for
-    a bounded sample of the same workload: n_cpu_k wavenumbers at N = 5124."""
+    a bounded sample of the same workload: n_cpu_k wavenumbers spread over the
+    sweep at N = 5124, each compared with the GPU result."""
     from oracle import bie
     from oracle.mesh import Surface
     try:
@@ -674,9 +785,10 @@ def cpu_baseline(w, x_gpu, n_cpu_k):
         errs.append(float(np.linalg.norm(xg - xs) / np.linalg.norm(xs)))
     dt = time.perf_counter() - t0
     return {"value": len(idx) / dt, "unit": "freq-solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(idx)} wavenumber(s) k={','.join(f'{w.k[q]:.4g}' for q in idx)} "
-                      f"of the same N=5124 workload, FP64 assembly + LAPACK LU",
-            "gpu_rel_err_vs_oracle": max(errs)}
+            "sample": f"{len(idx)} wavenumbers k={','.join(f'{w.k[q]:.4g}' for q in idx)} "
+                      f"of the same N=5124 workload, FP64 assembly + LAPACK LU ({dt:.1f} s)",
+            "gpu_rel_err_vs_oracle": max(errs),
+            "gpu_rel_err_vs_oracle_per_k": errs}
 
 
 if __name__ == "__main__":

@@ -552,12 +552,17 @@ bem_status chunk_finish_ir(SolveRun& R, const Chunk& c, int k0, int kc, int64_t 
   if ((st = fill_zero(ctx, c.x, (size_t)nv * n * 16)) != BEM_OK) return st;
   if ((st = launch_norm2(ctx, nv, n, c.b, c.rn2)) != BEM_OK) return st;   // r_0 = b
   void* hp = nullptr;
-  if ((st = pinned(ctx, (size_t)nv * 24 + (size_t)kc * 4 + (size_t)nv, &hp)) != BEM_OK) return st;
+  if ((st = pinned(ctx, (size_t)nv * 24 + (size_t)kc * 4 + 2 * (size_t)nv, &hp)) != BEM_OK) return st;
   double* h_dn = (double*)hp;
   double* h_xn = h_dn + nv;
   double* h_rn = h_xn + nv;
   int32_t* h_info = (int32_t*)(h_rn + nv);
+  // two staging slots for the flags: the upload before the correction solve
+  // (h_act) completes at the synchronisation that follows it; the upload
+  // before the update (h_act2) is only known to be done at the next sweep's
+  // synchronisation, so the next sweep's first upload must not reuse its slot
   uint8_t* h_act = (uint8_t*)(h_info + kc);
+  uint8_t* h_act2 = h_act + nv;
   // act: takes another sweep; fin: stops once the current correction is applied;
   // fresh: the float64 residual of the current x has been evaluated
   std::vector<uint8_t> act(nv, 1), fin(nv, 0), fresh(nv, 1);
@@ -607,8 +612,8 @@ bem_status chunk_finish_ir(SolveRun& R, const Chunk& c, int k0, int kc, int64_t 
     }
     if (more + nfin == 0) break;
     // take the corrections, then the residual of the new iterates
-    std::memcpy(h_act, act.data(), nv);
-    BEM_HIP_TRY(ctx, hipMemcpyAsync(c.active, h_act, nv, hipMemcpyHostToDevice, ctx->stream));
+    std::memcpy(h_act2, act.data(), nv);
+    BEM_HIP_TRY(ctx, hipMemcpyAsync(c.active, h_act2, nv, hipMemcpyHostToDevice, ctx->stream));
     if ((st = launch_ir_update(ctx, nv, n, c.d32, c.scale, c.active, c.x, c.dn2, c.xn2, 1)) != BEM_OK)
       return st;
     for (int v = 0; v < nv; ++v)

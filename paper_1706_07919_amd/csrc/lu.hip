@@ -692,6 +692,292 @@ __global__ __launch_bounds__(256) void gemm_c32_3m_kernel(LuGroups G, int rowC, 
     }
 }
 
+// ============================================================== GEMM f32, operands streamed into LDS
+// The complex update C -= A B on MFMA 32x32x2 f32 for the float32
+// factorisation, as three real products (3M: T1 = Ar Br, T2 = Ai Bi,
+// T3 = (Ar + Ai)(Br + Bi); Re C -= T1 - T2, Im C -= T3 - T1 - T2) or four (4M:
+// the interleaved real row of A against [Re B; -Im B] and [Im B; Re B]).
+//
+// * Operands go from global memory straight into LDS (global_load_lds, one
+//   16-byte word per lane, no staging registers), 16 complex k per stage, one
+//   stage in flight while the previous one is multiplied.  A keeps its
+//   row-major interleaved layout: 128 bytes per tile row and stage, the eight
+//   16-byte words of row r stored at positions permuted by r mod 8 so that
+//   the 32 rows an MFMA block reads hit distinct banks.  B rows are stored as
+//   they are (consecutive lanes read consecutive columns).
+// * Edges: rows past M and columns past N load clamped addresses and are never
+//   stored; depth past K (the last stage when K is not a multiple of 16) is
+//   zeroed on the way from LDS to the MFMA operands.
+// * Work list: every (matrix, tile) pair of the launch, over all size classes
+//   (each with its own tile counts), in matrix order, cut into eight
+//   contiguous ranges; range x runs on XCD x (workgroup w is dispatched to
+//   XCD w mod 8).  Tiles sharing an A or a B panel therefore read it through
+//   one XCD's L2, and in a large batch every matrix stays on one XCD.  Inside
+//   a matrix, tiles are walked in strips of GL_GM tile rows, column by column.
+// * Tile 128 x BN (BN = 64 WJ) per workgroup of 4 waves (2 x 2), each wave
+//   64 x 32 WJ as 2 x WJ MFMA blocks.
+constexpr int GL_BM = 128, GL_BK = 16, GL_GM = 8;
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// Work list of one launch: group g owns items [start[g], start[g + 1]), each
+// item one tile of one of its matrices (tm[g] x tn[g] tiles per matrix).
+struct GemmList {
+  int64_t start[kMaxGroups + 1];
+  int tm[kMaxGroups], tn[kMaxGroups];
+};
+
+// One 16-byte word per lane from global memory straight into LDS at
+// lds_wave + 16 * lane (lds_wave wave-uniform, in M0).  The compiler does not
+// order these loads against later LDS reads; the kernels using it wait on the
+// load counter themselves before each barrier.
+__device__ inline void lds_dma16(const GLOBAL u32x4* src, unsigned lds_wave) {
+  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off"
+               :: "v"(src), "s"(lds_wave) : "memory", "m0");
+}
+
+template <bool M3, int WJ>
+__global__ __launch_bounds__(256, 2) void gemm_c32_lds_kernel(LuGroups G, GemmList W, int rowC,
+                                                              int colC, int colA, int rowB,
+                                                              int rowEnd, int colEnd, int K) {
+  constexpr int BN = 64 * WJ;
+  constexpr int BW = GL_BK * BN / 2;            // 16-byte words of a B stage
+  __shared__ u32x4 As[2][GL_BM * GL_BK / 2], Bs[2][BW];
+  // ---- work item -> (group, matrix, tile)
+  const int64_t total = W.start[G.ng];
+  const int64_t per = (total + 7) >> 3;
+  const int64_t item = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (item >= total) return;
+  int gsel = 0;
+#pragma unroll
+  for (int i = 1; i < kMaxGroups; ++i)
+    if (i < G.ng && item >= W.start[i]) gsel = i;
+  int64_t first_item = 0, ld = 0, stride = 0;
+  const void* Abase = nullptr;
+  int n = 0, tiles_m = 1, tiles_n = 1;
+#pragma unroll
+  for (int i = 0; i < kMaxGroups; ++i)
+    if (i == gsel) {
+      first_item = W.start[i];
+      Abase = G.g[i].A;
+      ld = G.g[i].ld;
+      stride = G.g[i].stride;
+      n = G.g[i].n;
+      tiles_m = W.tm[i];
+      tiles_n = W.tn[i];
+    }
+  const int64_t local = item - first_item;
+  const int tiles = tiles_m * tiles_n;
+  const int64_t b = local / tiles;
+  const int t = (int)(local - b * tiles);
+  const int strip = GL_GM * tiles_n;
+  const int first = (t / strip) * GL_GM;
+  const int gsz = min(tiles_m - first, GL_GM);
+  const int tm = first + (t % strip) % gsz, tn = (t % strip) / gsz;
+  const int M = min(rowEnd, n) - rowC, N = min(colEnd, n) - colC;
+  const int m0 = tm * GL_BM, n0 = tn * BN;
+  const GLOBAL float2* Mat = (const GLOBAL float2*)Abase + b * stride;
+  const GLOBAL float2* A = Mat + (int64_t)rowC * ld + colA;
+  const GLOBAL float2* B = Mat + (int64_t)rowB * ld + colC;
+  GLOBAL float2* C = (GLOBAL float2*)Mat + (int64_t)rowC * ld + colC;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  const int h = lane >> 5, l32 = lane & 31;
+
+  // ---- loads of one stage: A slots q*256 + tid (row q*32 + tid/8, 16-byte
+  // word (tid % 8) ^ (row % 8)), B slots q*256 + tid (k row (q*256 + tid) /
+  // (BN/2), word tid % (BN/2)).  The addresses are recomputed per stage from
+  // the thread index (kept opaque to the compiler) so that none of them stays
+  // live across the MFMA loop, whose accumulators fill the register budget.
+  constexpr int BQ = BW / 256;
+  const int ldi = (int)ld;   // n * ld < 2^31 is checked on the host
+  const unsigned a_lds = (unsigned)(uintptr_t)(LDS_AS void*)&As[0][0] + wid * 1024;
+  const unsigned b_lds = (unsigned)(uintptr_t)(LDS_AS void*)&Bs[0][0] + wid * 1024;
+  const int S = (K + GL_BK - 1) / GL_BK;
+  auto load_stage = [&](int s) {
+    int tt = tid;
+    asm volatile("" : "+v"(tt));
+    const int k0 = s * GL_BK;
+    const unsigned abuf = (unsigned)(s & 1) * (GL_BM * GL_BK / 2 * 16);
+    const unsigned bbuf = (unsigned)(s & 1) * (BW * 16);
+    const int ka = min(k0 + 2 * ((tt & 7) ^ ((tt >> 3) & 7)), K - 2);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = min(m0 + q * 32 + (tt >> 3), M - 1);
+      lds_dma16((const GLOBAL u32x4*)(A + (row * ldi + ka)),
+                __builtin_amdgcn_readfirstlane(a_lds + abuf + q * 4096));
+    }
+    const int bc = min(n0 + 2 * (tt & (BN / 2 - 1)), ldi - colC - 2);
+#pragma unroll
+    for (int q = 0; q < BQ; ++q) {
+      const int kr = min(k0 + (q * 256 + tt) / (BN / 2), K - 1);
+      lds_dma16((const GLOBAL u32x4*)(B + (kr * ldi + bc)),
+                __builtin_amdgcn_readfirstlane(b_lds + bbuf + q * 4096));
+    }
+  };
+
+  constexpr int NACC = M3 ? 3 : 2;
+  floatx16 acc[NACC][2][WJ];
+#pragma unroll
+  for (int p = 0; p < NACC; ++p)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < WJ; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[p][i][j][v] = 0.f;
+
+  const int arow0 = wm * 64 + l32;                   // + 32 i
+  const int bcol0 = wn * 32 * WJ + l32;              // + 32 j
+  const int sw = l32 & 7;
+  // Operands of one group of 4 complex k (q4) in registers.  3M: lane half h
+  // holds k = 4 q4 + 2h + p for MFMA p (A as one 16-byte word per block).
+  // 4M: both halves take the same k, re (h = 0) or im (h = 1) of A, and the
+  // matching entries of the two B patterns.
+  constexpr int AW = M3 ? 1 : 2;   // 16-byte A words per block and group
+  constexpr int BK = M3 ? 2 : 4;   // B entries per block and group
+  struct Ops {
+    float4 a[2][AW];
+    float2 b[WJ][BK];
+  };
+  auto read_ops = [&](const u32x4* Ab, const float2* Bf, int q4, Ops& o) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int w = 0; w < AW; ++w) {
+        const int c = M3 ? 2 * q4 + h : 2 * q4 + w;
+        o.a[i][w] = __builtin_bit_cast(float4, Ab[(arow0 + 32 * i) * 8 + (c ^ sw)]);
+      }
+#pragma unroll
+    for (int j = 0; j < WJ; ++j)
+#pragma unroll
+      for (int e = 0; e < BK; ++e) {
+        const int kk = M3 ? 4 * q4 + 2 * h + e : 4 * q4 + e;
+        o.b[j][e] = Bf[kk * BN + bcol0 + 32 * j];
+      }
+  };
+  auto mma = [&](const Ops& o) {
+    if constexpr (M3) {
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        float ar[2], ai[2], as[2], br[WJ], bi[WJ], bs[WJ];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          ar[i] = p ? o.a[i][0].z : o.a[i][0].x;
+          ai[i] = p ? o.a[i][0].w : o.a[i][0].y;
+          as[i] = ar[i] + ai[i];
+        }
+#pragma unroll
+        for (int j = 0; j < WJ; ++j) {
+          br[j] = o.b[j][p].x;
+          bi[j] = o.b[j][p].y;
+          bs[j] = br[j] + bi[j];
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < WJ; ++j) {
+            acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i], br[j], acc[0][i][j], 0, 0, 0);
+            acc[1][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[i], bi[j], acc[1][i][j], 0, 0, 0);
+            acc[2][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(as[i], bs[j], acc[2][i][j], 0, 0, 0);
+          }
+      }
+    } else {
+#pragma unroll
+      for (int e4 = 0; e4 < 4; ++e4) {
+        const int w = e4 >> 1, e = e4 & 1;
+        float a[2], bre[WJ], bim[WJ];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const float re = e ? o.a[i][w].z : o.a[i][w].x, im = e ? o.a[i][w].w : o.a[i][w].y;
+          a[i] = h ? im : re;
+        }
+#pragma unroll
+        for (int j = 0; j < WJ; ++j) {
+          const float2 v = o.b[j][e4];
+          bre[j] = h ? -v.y : v.x;
+          bim[j] = h ? v.x : v.y;
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < WJ; ++j) {
+            acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], bre[j], acc[0][i][j], 0, 0, 0);
+            acc[1][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], bim[j], acc[1][i][j], 0, 0, 0);
+          }
+      }
+    }
+  };
+  // A partial last stage (K not a multiple of 16; K is even, so every A word
+  // is all in or all out): each thread zeroes the LDS words of its own loads
+  // that lie at or past K, after its loads have landed.
+  auto zero_tail = [&](int cur, int kvalid) {
+    const int tt = tid;
+    const u32x4 z = {0u, 0u, 0u, 0u};
+    const int c = (tt & 7) ^ ((tt >> 3) & 7);
+    if (2 * c >= kvalid)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) As[cur][q * 256 + tt] = z;
+#pragma unroll
+    for (int q = 0; q < BQ; ++q)
+      if ((q * 256 + tt) / (BN / 2) >= kvalid) Bs[cur][q * 256 + tt] = z;
+  };
+
+  load_stage(0);
+  for (int s = 0; s < S; ++s) {
+    // stage s has landed, and every wave is past its reads of stage s - 1,
+    // whose buffer the next load reuses
+    asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+    const int cur = s & 1;
+    const int kvalid = K - s * GL_BK;
+    if (kvalid < GL_BK) {
+      zero_tail(cur, kvalid);
+      __syncthreads();
+    }
+    if (s + 1 < S) load_stage(s + 1);
+    // the next group's operands are read while the current group's MFMAs run
+    const u32x4* Ab = &As[cur][0];
+    const float2* Bf = (const float2*)&Bs[cur][0];
+    Ops o[2];
+    read_ops(Ab, Bf, 0, o[0]);
+#pragma unroll
+    for (int q4 = 0; q4 < 4; ++q4) {
+      if (q4 + 1 < 4) read_ops(Ab, Bf, q4 + 1, o[(q4 + 1) & 1]);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(o[q4 & 1]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < WJ; ++j) {
+      const int col = n0 + bcol0 + 32 * j;
+      if (col >= N) continue;
+      float2 c[16];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        c[v] = C[min(row, M - 1) * ldi + col];
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        float dr, di;
+        if constexpr (M3) {
+          const float t1 = acc[0][i][j][v], t2 = acc[1][i][j][v], t3 = acc[2][i][j][v];
+          dr = t1 - t2;
+          di = t3 - t1 - t2;
+        } else {
+          dr = acc[0][i][j][v];
+          di = acc[1][i][j][v];
+        }
+        if (row < M) C[row * ldi + col] = make_float2(c[v].x - dr, c[v].y - di);
+      }
+    }
+}
+
 // ============================================================== GEMM f32 via bf16 split
 // The same 4M update with every real product taken as three bfloat16 MFMA
 // products: each float32 operand x is split into hi = bf16(x) and
@@ -1097,7 +1383,6 @@ __global__ __launch_bounds__(256) void gemm_c32_small_kernel(LuGroups G, int row
 constexpr int GP_BLK = 2 * 2 * GB_BM;   // 16-byte words per tile and 8-k block
 // largest packing buffer a context holds; bigger batches are packed in slices
 constexpr size_t kPackLimit = (size_t)4 << 30;
-typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 // 16-byte words of the packed A and B of one matrix for an M x N update of depth K
 inline int64_t pack_words(int M, int N, int K) {
@@ -1197,15 +1482,6 @@ __global__ __launch_bounds__(256) void pack_b_kernel(LuGroups G, int rowB, int c
 __device__ inline bf16x8 re_to_im8(bf16x8 b) {
   const u32x4 r = __builtin_bit_cast(u32x4, b);
   return __builtin_bit_cast(bf16x8, ((r >> 16) | (r << 16)) ^ 0x8000u);
-}
-
-// One 16-byte word per lane from global memory straight into LDS at
-// lds_wave + 16 * lane (lds_wave wave-uniform, in M0).  The compiler does not
-// order these loads against later LDS reads; the kernel waits on the load
-// counter itself before each barrier.
-__device__ inline void lds_dma16(const GLOBAL u32x4* src, unsigned lds_wave) {
-  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off"
-               :: "v"(src), "s"(lds_wave) : "memory", "m0");
 }
 
 __global__ __launch_bounds__(256, 2) void gemm_c32_b3p_kernel(LuGroups G, int rowC, int colC,
@@ -1693,6 +1969,63 @@ struct Fac {
     }
   }
   // C = rows [rowC, rowEnd) x cols [colC, colEnd) -= A(rows, [colA, colA+K)) B([rowB, rowB+K), cols)
+  // float32 3M / 4M update through gemm_c32_lds_kernel; false (nothing
+  // launched) when an operand is not 16-byte aligned (odd ld, column offset or
+  // depth)
+  bool gemm_lds(const LuGroups& G, int rowC, int colC, int colA, int rowB, int rowEnd, int colEnd,
+                int K, int N) {
+    if ((colA | colC | K) & 1) return false;
+    for (int i = 0; i < G.ng; ++i)
+      if (G.g[i].ld & 1) return false;
+    const bool narrow = N <= 64;
+    const int BN = narrow ? 64 : 128;
+    GemmList W{};
+    W.start[0] = 0;
+    for (int i = 0; i < G.ng; ++i) {
+      const int m = std::max(0, std::min(rowEnd, G.g[i].n) - rowC);
+      const int nn = std::max(0, std::min(colEnd, G.g[i].n) - colC);
+      W.tm[i] = std::max(1, (m + GL_BM - 1) / GL_BM);
+      W.tn[i] = std::max(1, (nn + BN - 1) / BN);
+      W.start[i + 1] = W.start[i] + (m > 0 && nn > 0 ? (int64_t)G.g[i].count * W.tm[i] * W.tn[i] : 0);
+    }
+    for (int i = G.ng + 1; i <= kMaxGroups; ++i) W.start[i] = W.start[G.ng];
+    const int64_t total = W.start[G.ng];
+    if (total <= 0) return true;
+    const int64_t grid = (total + 7) / 8 * 8;
+    const bool m3 = gkind == kGemm3M;
+    const char* kname = m3 ? (narrow ? "gemm_3m_narrow" : "gemm_3m")
+                           : (narrow ? "gemm_c32_narrow" : "gemm_c32");
+    const int pi = prof_begin(ctx, kname);
+    if (m3 && narrow)
+      hipLaunchKernelGGL((gemm_c32_lds_kernel<true, 1>), dim3((unsigned)grid), dim3(256), 0,
+                         ctx->stream, G, W, rowC, colC, colA, rowB, rowEnd, colEnd, K);
+    else if (m3)
+      hipLaunchKernelGGL((gemm_c32_lds_kernel<true, 2>), dim3((unsigned)grid), dim3(256), 0,
+                         ctx->stream, G, W, rowC, colC, colA, rowB, rowEnd, colEnd, K);
+    else if (narrow)
+      hipLaunchKernelGGL((gemm_c32_lds_kernel<false, 1>), dim3((unsigned)grid), dim3(256), 0,
+                         ctx->stream, G, W, rowC, colC, colA, rowB, rowEnd, colEnd, K);
+    else
+      hipLaunchKernelGGL((gemm_c32_lds_kernel<false, 2>), dim3((unsigned)grid), dim3(256), 0,
+                         ctx->stream, G, W, rowC, colC, colA, rowB, rowEnd, colEnd, K);
+    gemm_prof(kname, pi, rowC, colC, rowEnd, colEnd, K);
+    return true;
+  }
+  // algorithmic work of C -= A B: 8 M N K flops (complex multiply-adds of the
+  // 4M form), A, B read and C read and written once
+  void gemm_prof(const char* kname, int pi, int rowC, int colC, int rowEnd, int colEnd, int K) {
+    const double es = (double)esz();
+    auto mn = [&](int n, double& m, double& nn) {
+      m = std::max(0, std::min(rowEnd, n) - rowC);
+      nn = std::max(0, std::min(colEnd, n) - colC);
+    };
+    prof_end(ctx, kname, pi,
+             work(std::max(rowC, colC), [&](int n) { double m, nn; mn(n, m, nn); return 8.0 * m * nn * K; }),
+             work(std::max(rowC, colC), [&](int n) {
+               double m, nn; mn(n, m, nn);
+               return es * (m * K + (double)K * nn + 2.0 * m * nn);
+             }));
+  }
   void gemm(int rowC, int colC, int colA, int rowB, int rowEnd, int colEnd, int K) {
     if (K <= 0) return;
     if (use_pack && gemm_packed(rowC, colC, colA, rowB, rowEnd, colEnd, K)) return;
@@ -1701,10 +2034,13 @@ struct Fac {
     if (total == 0) return;
     const int M = std::min(rowEnd, maxn) - rowC, N = std::min(colEnd, maxn) - colC;
     if (M <= 0 || N <= 0) return;
+    if (prec == BEM_C64 && (gkind == kGemm3M || gkind == kGemm4M) && !(N <= 16 && K <= 16) &&
+        gemm_lds(G, rowC, colC, colA, rowB, rowEnd, colEnd, K, N))
+      return;
     const char* kname = prec == BEM_C128 ? "gemm_c64"
                         : N <= 16 && K <= 16 ? "gemm_small"
                         : gkind == kGemmBf16x3 ? (N <= 64 ? "gemm_b3_narrow" : "gemm_b3")
-                        : gkind == kGemm3M ? "gemm_3m" : "gemm_c32";
+                        : gkind == kGemm3M ? "gemm_3m_unaligned" : "gemm_c32_unaligned";
     const int pi = prof_begin(ctx, kname);
     if (prec == BEM_C128) {
       const int tn = (N + G64_BN - 1) / G64_BN, tm = (M + G64_BM - 1) / G64_BM;
@@ -1738,17 +2074,7 @@ struct Fac {
         hipLaunchKernelGGL(gemm_c32_kernel, dim3(tm * tn, total), dim3(256), 0, ctx->stream, G,
                            rowC, colC, colA, rowB, rowEnd, colEnd, K, tn);
     }
-    const double es = (double)esz();
-    auto mn = [&](int n, double& m, double& nn) {
-      m = std::max(0, std::min(rowEnd, n) - rowC);
-      nn = std::max(0, std::min(colEnd, n) - colC);
-    };
-    prof_end(ctx, kname, pi,
-             work(std::max(rowC, colC), [&](int n) { double m, nn; mn(n, m, nn); return 8.0 * m * nn * K; }),
-             work(std::max(rowC, colC), [&](int n) {
-               double m, nn; mn(n, m, nn);
-               return es * (m * K + (double)K * nn + 2.0 * m * nn);
-             }));
+    gemm_prof(kname, pi, rowC, colC, rowEnd, colEnd, K);
   }
   // matrices [b0, b1) of the concatenation of G's groups
   static LuGroups slice(const LuGroups& G, int b0, int b1, size_t es) {

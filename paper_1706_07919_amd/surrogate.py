@@ -129,7 +129,7 @@ def training_factors(ctx, ds, kd, y, nb=0, gemm_kind=None):
     """Float32 factors of the training wavenumbers (kept for re-use) and the
     FP64-accurate training solutions obtained by refining with them."""
     if gemm_kind is None:
-        gemm_kind = native.BEM_GEMM_BF16X3
+        gemm_kind = native.BEM_GEMM_3M
     t = __import__("torch")
     n = ds.n
     nk = int(kd.shape[0])
@@ -210,7 +210,7 @@ def fill_sweep(ctx, ds, k_train, k_pred, hidden=(512, 512, 512, 512), seed=0, ep
     if fallback.size:
         xf = torch.zeros((fallback.size, 1, n), dtype=torch.complex128, device=dev)
         opts = native.bem_solve_opts_default()
-        opts.mode = native.BEM_FP32_IR_B3
+        opts.mode = native.BEM_FP32_IR_3M
         native.bem_solve_batched(ctx, [(ds.struct, int(fallback.size), kp[fallback].contiguous(), 1,
                                         yp[fallback].contiguous())], opts, [xf])
         x[fallback] = xf

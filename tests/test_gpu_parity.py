@@ -212,6 +212,49 @@ def test_getrf_3m_and_split_gemm(ctx, n, kind):
             assert bwd < 3e-5
 
 
+@pytest.mark.parametrize("kind", [native.BEM_GEMM_4M, native.BEM_GEMM_3M])
+@pytest.mark.parametrize("n,pad,nb", [(300, 0, 72), (300, 1, 72), (777, 1, 0), (1100, 0, 256),
+                                      (1030, 2, 512)])
+def test_getrf_fp32_forms_backward_error(ctx, kind, n, pad, nb):
+    """Float32 factorisations with 4M and 3M products: an even leading dimension
+    takes the LDS-streamed kernel (a block width of 72 gives depths with a
+    partial last 16-k stage, 1030 rows a ragged last tile), an odd one the
+    register-staged kernel; both meet the float32 normwise backward-error bound
+    and reconstruct P A = L U."""
+    rng = np.random.default_rng(n + pad + nb)
+    batch = 3
+    ld = n + pad
+    M = seeded_complex(rng, (batch, n, n)) + 0.5 * np.sqrt(n) * np.eye(n)[None]
+    M[1] = M[1][rng.permutation(n)]
+    M[2] = seeded_complex(rng, (n, n))
+    A = torch.zeros((batch, n, ld), dtype=torch.complex64)
+    A[:, :, :n] = torch.as_tensor(M)
+    A = A.cuda()
+    piv = torch.zeros((batch, n), dtype=torch.int32, device="cuda")
+    info = torch.ones(batch, dtype=torch.int32, device="cuda")
+    native.bem_getrf_batched(ctx, native.BEM_C64, n, ld, n * ld, batch, A, piv, info, nb, kind)
+    assert info.cpu().numpy().tolist() == [0] * batch
+    B = seeded_complex(rng, (batch, 1, n))
+    X = torch.zeros((batch, 1, n), dtype=torch.complex64, device="cuda")
+    native.bem_getrs_batched(ctx, native.BEM_C64, n, ld, n * ld, batch, A, piv, 1,
+                             dev(B, torch.complex64), X, n)
+    X = X.cpu().numpy().astype(np.complex128)
+    for b_ in range(batch):
+        x = X[b_, 0]
+        bwd = np.linalg.norm(M[b_] @ x - B[b_, 0]) / (np.linalg.norm(M[b_]) * np.linalg.norm(x))
+        assert bwd < (1e-6 if kind == native.BEM_GEMM_4M else 3e-6), (b_, bwd)
+    if n <= 300:
+        LU = A.cpu().numpy()[:, :, :n].astype(np.complex128)
+        p = piv.cpu().numpy()
+        for b_ in range(batch):
+            L = np.tril(LU[b_], -1) + np.eye(n)
+            U = np.triu(LU[b_])
+            PA = M[b_].copy()
+            for i in range(n):
+                PA[[i, p[b_, i]]] = PA[[p[b_, i], i]]
+            assert np.max(np.abs(L @ U - PA)) < 1e-4 * np.sqrt(n) * 4
+
+
 @pytest.mark.parametrize("n,nb,batch,limit", [
     (777, 64, 3, 0),                     # every trailing update in one packed launch
     (1100, 256, 5, 4 * 8 * 1024 * 1024),  # 8 MiB packing buffer: batches packed in slices
@@ -328,6 +371,39 @@ def test_solve_mixed_bc_multi_rhs_vs_oracle(ctx):
         assert rel(x[q], xs.T) < 1e-6
 
 
+def test_refinement_items_stopping_at_different_sweeps(ctx):
+    """Items of one chunk leave the refinement at different sweeps (a tight
+    step tolerance, and wavenumbers next to the interior resonances ka = pi,
+    4.4934 of the sphere, whose items contract more slowly than the others):
+    every item still returns the discrete FP64 solution, and its reported FP64
+    residual is the residual of the x it returns (a correction dropped for an
+    item that stops would break both)."""
+    bodies = [Body((0.0, 0.0, 0.0), 1.0, 1.0, 3, HARD)]
+    k = np.array([0.7, 2.0, 4.43, 4.46, 4.49, 4.52, 6.1, 8.3, 3.10, 3.13, 3.16, 3.19, 5.0,
+                  9.7, 1.3, 11.4])
+    s = Surface(bodies)
+    ds = DeviceSurface.from_bodies(bodies)
+    kd = dev(k)
+    y = torch.empty((len(k), 1, ds.n), dtype=torch.complex128, device="cuda")
+    native.bem_incident(ctx, ds.struct, len(k), kd, (0.0, 0.0, 1.0), y)
+    x = torch.zeros((len(k), 1, ds.n), dtype=torch.complex128, device="cuda")
+    opts = native.bem_solve_opts_default()
+    opts.mode = native.BEM_FP32_IR_3M
+    opts.tol_step = 1e-13
+    opts.max_iter = 12
+    info = native.bem_solve_batched(ctx, [(ds.struct, len(k), kd, 1, y)], opts, [x])
+    iters = [info[q].iters for q in range(len(k))]
+    assert len(set(iters)) >= 2, iters
+    rr = native.bem_residual_check(ctx, ds.struct, len(k), kd, 1, y, x)
+    xg = x.cpu().numpy()[:, 0]
+    for q, kq in enumerate(k):
+        p, dp = bie.incident_plane_wave(s, kq)
+        _, _, xs = bie.solve(s, kq, bie.known_data(s, p, dp))
+        assert info[q].converged == 1 and info[q].used_fp64 == 0, (kq, iters)
+        assert rel(xg[q], xs) < 1e-9, (kq, rel(xg[q], xs))
+        assert abs(info[q].rel_resid - rr[q]) <= 1e-6 * rr[q] + 1e-16, (kq, info[q].rel_resid, rr[q])
+
+
 def test_bowl_solve_and_field_vs_oracle(ctx):
     """The hard acoustic bowl of Sec. IV C (Eq. dish, axis turned by 0.15 pi
     from the propagation direction; 16 x 24 rings, 362 nodes, a thin shell with
@@ -369,7 +445,8 @@ def test_bowl_solve_and_field_vs_oracle(ctx):
         assert np.max(np.abs(U[:, q] - ref)) < 2e-5 * max(1.0, np.max(np.abs(ref)))
 
 
-@pytest.mark.parametrize("mode", [native.BEM_FP32_IR_4M, native.BEM_FP32_IR_B3, native.BEM_FP64_DIRECT])
+@pytest.mark.parametrize("mode", [native.BEM_FP32_IR_4M, native.BEM_FP32_IR_3M, native.BEM_FP32_IR_B3,
+                                  native.BEM_FP64_DIRECT])
 def test_solve_uneven_batch_vs_oracle(ctx, mode):
     """Bodies of 42, 162 and 642 nodes (one problem each, different k counts)
     factored together in one recursion per round."""

@@ -134,3 +134,74 @@ def test_table1_from_oracle_bem():
         tr = pulse.synthesize(U, ct, T)
         assert abs(pulse.rms_error_percent(tr[0], full[0]) - e11) <= t1["printed_precision"] + 1e-9
         assert abs(pulse.rms_error_percent(tr[1], full[1]) - e4) <= t1["printed_precision"] + 1e-9
+
+
+def _nwave_discrete_closed_form(sigma, dk, n_k, T):
+    """c_m of the sampled N-wave F(s) = s / sigma on |s| <= sigma, from the
+    closed form of the sum.  With h = L / T the samples are s = j h
+    (j = -T/2 .. T/2 - 1), so c_m = (1/T) sum_{|j| <= J} (j h / sigma) e^{-i theta j},
+    theta = k_m h, J = floor(sigma / h).  The sum is odd in j:
+    sum_{|j|<=J} j e^{-i theta j} = -2i sum_{j=1}^{J} j sin(j theta), and
+    sum_{j=1}^{J} j sin(j theta) = [(J+1) sin(J theta) - J sin((J+1) theta)] / (4 sin^2(theta/2))
+    (minus the derivative of the Dirichlet kernel sum of cos(j theta))."""
+    L = 2 * np.pi / dk
+    h = L / T
+    J = int(np.floor(sigma / h))
+    assert J < T // 2
+    th = dk * np.arange(1, n_k + 1) * h
+    s = ((J + 1) * np.sin(J * th) - J * np.sin((J + 1) * th)) / (4.0 * np.sin(0.5 * th) ** 2)
+    return (h / sigma) * (-2j) * s / T
+
+
+def test_nwave_coefficients_closed_form_sum_and_continuous_limit():
+    # window edge sigma/h = J + 0.37 (no sample on the jump, so no rounding
+    # decides whether a sample is in the window)
+    dk, n_k, T = 12.0 / 256, 256, 512
+    h = 2 * np.pi / dk / T
+    for J in (3, 11, 40):
+        sigma = (J + 0.37) * h
+        c = pulse.coefficients(Pulse("nwave", {"sigma": sigma}), n_k, dk, T, 0.0)
+        ref = _nwave_discrete_closed_form(sigma, dk, n_k, T)
+        assert np.max(np.abs(c - ref)) < 1e-13 * np.max(np.abs(ref))
+    # continuous limit: the odd box-linear pulse has the transform
+    # int_{-sigma}^{sigma} (s/sigma) e^{-iks} ds = (-2i/sigma)(sin(k sigma) - k sigma cos(k sigma))/k^2,
+    # and the sampled sum approaches it at first order in h (the jumps at +-sigma)
+    sigma = 1.1
+    errs = []
+    for TT in (1024, 2048, 4096, 8192):
+        L = 2 * np.pi / dk
+        c = pulse.coefficients(Pulse("nwave", {"sigma": sigma}), 64, dk, TT, 0.0)
+        k = dk * np.arange(1, 65)
+        ft = (-2j / sigma) * (np.sin(k * sigma) - k * sigma * np.cos(k * sigma)) / k ** 2
+        errs.append(np.max(np.abs(c * L - ft)))
+    errs = np.array(errs)
+    hh = 2 * np.pi / dk / np.array([1024, 2048, 4096, 8192])
+    assert np.all(errs <= 2.0 * hh)            # |jump| = 1 at each edge: error <= ~h
+    assert errs[-1] < 0.5 * errs[0]            # and it shrinks with h (not monotonically:
+    # the fractional position of the jumps on the grid changes with T)
+
+
+@pytest.mark.parametrize("params", [{"ka": 3.0, "kb": 7.5, "D": 3.0},
+                                    {"ka": 2.2, "kb": 8.8, "D": 2.1}, None])
+def test_chirp_coefficients_match_complex_gaussian_integral(params):
+    """The Gaussian-windowed linear chirp sin(ka s + (kb - ka) s^2 / (2D)) e^{-s^2/(2D^2)}
+    is smooth and decays fast, so its sampled coefficients equal (1/L) times
+    its continuous transform.  With sin = (e^{i phi} - e^{-i phi}) / 2i, each half
+    is a complex Gaussian integral:
+    int exp(-a s^2 + i b s) ds = sqrt(pi / a) exp(-b^2 / (4a)) for Re a > 0, with
+    a = 1/(2D^2) -+ i beta, beta = (kb - ka)/(2D), b = +-ka - k."""
+    if params is None:       # the seeded chirp of the space-time workload
+        from workloads import spacetime_pulses
+        params = [p for p in spacetime_pulses(0) if p.kind == "chirp"][0].params
+    ka, kb, D = params["ka"], params["kb"], params["D"]
+    dk, n_k, T = 12.0 / 256, 256, 2048
+    L = 2 * np.pi / dk
+    c = pulse.coefficients(Pulse("chirp", params), n_k, dk, T, 0.0)
+    k = dk * np.arange(1, n_k + 1)
+    beta = (kb - ka) / (2.0 * D)
+    ap = 1.0 / (2 * D * D) - 1j * beta
+    am = 1.0 / (2 * D * D) + 1j * beta
+    plus = np.sqrt(np.pi / ap) * np.exp(-((ka - k) ** 2) / (4 * ap))
+    minus = np.sqrt(np.pi / am) * np.exp(-((ka + k) ** 2) / (4 * am))
+    ft = (plus - minus) / 2j
+    assert np.max(np.abs(c - ft / L)) < 1e-12 * L
