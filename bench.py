@@ -415,6 +415,11 @@ def run_spacetime(args, ctx=None, mode=None):
     print(f"synthesis: {t3 - t2:.3f} s", file=sys.stderr, flush=True)
     syn_bytes = 8.0 * m * nk + 4.0 * npulse * m * T
     terms = float(m) * nk * n
+    # after the timed region: the FP64 residual of every 128th solution, checked
+    # independently of the solver's own report
+    sel = torch.arange(0, nk, 128, device=dev)
+    rr_check = native.bem_residual_check(ctx, ds.struct, int(sel.numel()), kd[sel].contiguous(), 1,
+                                         y[sel].contiguous(), x[sel].contiguous())
     out = {"metric": "field pt*freq evals/sec (space-time path at full size)",
            "value": m * nk / (t2 - t1), "unit": "pt*freq/s", "higher_is_better": True,
            "data": "synthetic", "dtype": "c64 field kernel (f64-centred geometry), f32 synthesis",
@@ -431,6 +436,11 @@ def run_spacetime(args, ctx=None, mode=None):
            "ir_iters_max": max(info[q].iters for q in range(nk)),
            "ir_fallbacks": sum(info[q].used_fp64 for q in range(nk)),
            "max_rel_resid": max(info[q].rel_resid for q in range(nk)),
+           "min_rel_resid": min(info[q].rel_resid for q in range(nk)),
+           "converged": sum(info[q].converged for q in range(nk)),
+           "checked_rel_resid_max": float(rr_check.max()),
+           "checked_sample": "every 128th wavenumber, bem_residual_check",
+           "y_norm": torch.linalg.vector_norm(y).item(), "x_norm": torch.linalg.vector_norm(x).item(),
            "total_s": t3 - t0}
     del U, p, x, y, phi, psi
     if own_ctx:

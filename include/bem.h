@@ -63,9 +63,12 @@ bem_status bem_ctx_set_workspace_limit(bem_ctx* ctx, uint64_t bytes);
  * of a counted kernel is bracketed by HIP events on the stream it runs on and
  * credited with its algorithmic work; bem_ctx_kernel_stats returns the sums
  * (flops, bytes, milliseconds of device time, launch count) since profiling
- * was last switched (set_profiling resets them).  Kernel names: "gemm_c32",
- * "gemm_3m", "gemm_b3", "gemm_b3_narrow", "gemm_b3_packed", "gemm_small", "pack", "gemm_c64",
- * "panel", "laswp", "trsm", "assemble", "residual", "getrs", "field", "synth".
+ * was last switched (set_profiling resets them).  Kernel names: "gemm_c32" and
+ * "gemm_3m" (float32 4M / 3M updates of at least 65 columns), "gemm_c32_narrow" and
+ * "gemm_3m_narrow" (17 to 64 columns), "gemm_c32_unaligned" and "gemm_3m_unaligned"
+ * (operands not 16-byte aligned), "gemm_b3", "gemm_b3_narrow", "gemm_b3_packed",
+ * "gemm_small", "pack", "gemm_c64", "panel", "laswp", "trsm", "assemble", "residual",
+ * "getrs", "field", "synth".
  * For "assemble"/"residual" the flop slot counts node pairs and for "field"
  * kernel terms (point x frequency x node).  Unknown names report zeros.
  * Profiling turns the hipGraph replay of bem_solve_batched off.
@@ -236,6 +239,8 @@ typedef struct {
   double rel_step;        /* last ||dx||_2/||x||_2 */
 } bem_solve_info;
 
+/* Defaults: mode BEM_FP32_IR_3M, tol_step 1e-8, max_iter 10, fallback 1,
+ * use_graph 1, nb 0. */
 void bem_solve_opts_default(bem_solve_opts* opts);
 
 /* probs[n_probs] [host]; x_out[p] [dev] c128 [n_k][n_rhs][n] unknowns of

@@ -306,7 +306,7 @@ extern "C" bem_status bem_ctx_kernel_stats(bem_ctx* ctx, const char* kernel, dou
 
 extern "C" void bem_solve_opts_default(bem_solve_opts* o) {
   if (!o) return;
-  o->mode = BEM_FP32_IR_4M;
+  o->mode = BEM_FP32_IR_3M;
   o->tol_step = 1e-8;
   o->max_iter = 10;
   o->fallback = 1;

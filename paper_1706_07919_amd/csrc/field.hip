@@ -11,7 +11,11 @@
 // S(x_a) is computed once per node by the same kernel, so the per-point work
 // is one sweep over the nodes.  Float32 kernels take every phase k*r and k*s
 // in float64, reduce it to [-1/2, 1/2) revolutions, and evaluate the
-// trigonometric functions in float32 on the reduced argument.
+// trigonometric functions in float32 on the reduced argument.  Each point's
+// sweep is split over kParts lanes (lane q takes every kParts-th node), whose
+// partial sums are combined by a butterfly at the end: the float32 sums then
+// run over n / kParts terms each, which bounds their rounding error kParts
+// times tighter than one chain over all n nodes.
 #include "common.h"
 
 namespace bem {
@@ -96,7 +100,16 @@ __device__ inline void phase<double>(double theta, double& s, double& c) {
   sincos(theta, &s, &c);
 }
 
-constexpr int kFT = 256, kNJ = 64;
+constexpr int kFT = 256, kNJ = 128, kParts = 8, kPW = kFT / kParts;   // kPW points per workgroup
+
+// sum over the kParts consecutive lanes of one point (butterfly: every lane
+// ends with the total)
+template <typename R>
+__device__ inline R part_sum(R v) {
+#pragma unroll
+  for (int o = 1; o < kParts; o <<= 1) v += __shfl_xor(v, o, kParts);
+  return v;
+}
 
 // MODE 0: write S(x_p) for points = nodes (raw, [rhs][n_k][n]).
 // MODE 1: write P(x_p) = phi_a + (S(x_p) - S(x_a)) / (4 pi) into U[rhs][m][n_k].
@@ -114,7 +127,8 @@ __global__ __launch_bounds__(kFT, sizeof(R) == 4 ? 3 : 1) void field_kernel(
   __shared__ R sw[kNJ];
   __shared__ C sphi[FCH][kNJ];
   __shared__ C spsi[FCH][kNJ];
-  const int p = blockIdx.x * kFT + threadIdx.x;
+  const int p = blockIdx.x * kPW + threadIdx.x / kParts;
+  const int part = threadIdx.x % kParts;
   const int m0 = blockIdx.y * FCH;
   const int rhs = blockIdx.z;
   const int nf = min(FCH, n_k - m0);
@@ -168,7 +182,7 @@ __global__ __launch_bounds__(kFT, sizeof(R) == 4 ? 3 : 1) void field_kernel(
     }
     __syncthreads();
     if (!valid) continue;
-    for (int jj = 0; jj < cnt; ++jj) {
+    for (int jj = part; jj < cnt; jj += kParts) {
       if (j0 + jj == a) continue;
       const double dx = sx[jj][0] - px, dy = sx[jj][1] - py, dz = sx[jj][2] - pz;
       // r and the phase argument n_a.(x_j - x_a) stay in float64 (they enter
@@ -233,10 +247,21 @@ __global__ __launch_bounds__(kFT, sizeof(R) == 4 ? 3 : 1) void field_kernel(
       }
     }
   }
+#pragma unroll
+  for (int f = 0; f < FCH; ++f) {
+    A1[f].x = part_sum(A1[f].x);
+    A1[f].y = part_sum(A1[f].y);
+    A2[f].x = part_sum(A2[f].x);
+    A2[f].y = part_sum(A2[f].y);
+    A3[f].x = part_sum(A3[f].x);
+    A3[f].y = part_sum(A3[f].y);
+  }
   if (p >= m) return;
+  // lane q of the point writes frequency q of the chunk (and q + kParts, ...)
 #pragma unroll
   for (int f = 0; f < FCH; ++f) {
     if (f >= nf) break;
+    if (f % kParts != part) continue;
     const int64_t oa = ((int64_t)(m0 + f) * n_rhs + rhs) * n + a;
     const double2 pa = phi[oa], qa = psi[oa];
     const R par = (R)pa.x, pai = (R)pa.y, qar = (R)qa.x, qai = (R)qa.y;
@@ -271,7 +296,7 @@ bem_status field_go(bem_ctx* ctx, const bem_surface* s, int n_k, const double* k
   if (st != BEM_OK) return st;
   C* Snode = (C*)ws;
   const int fch = (n_k + FCH - 1) / FCH;
-  dim3 gnode((s->n + kFT - 1) / kFT, fch, n_rhs);
+  dim3 gnode((s->n + kPW - 1) / kPW, fch, n_rhs);
   // the profiling bracket covers both passes: the field at the nodes (the
   // expansion centres) and at the points
   const int pi = prof_begin(ctx, "field");
@@ -279,7 +304,7 @@ bem_status field_go(bem_ctx* ctx, const bem_surface* s, int n_k, const double* k
                      s->nrm, s->w, k, n_k, n_rhs, (const double2*)phi, (const double2*)psi, s->n,
                      s->x, (const int32_t*)nullptr, (const uint8_t*)nullptr, Snode, (C*)nullptr);
   BEM_CHECK_LAUNCH(ctx);
-  dim3 gpts((m + kFT - 1) / kFT, fch, n_rhs);
+  dim3 gpts((m + kPW - 1) / kPW, fch, n_rhs);
   hipLaunchKernelGGL((field_kernel<R, FCH, 1>), gpts, dim3(kFT), 0, ctx->stream, s->n, s->x,
                      s->nrm, s->w, k, n_k, n_rhs, (const double2*)phi, (const double2*)psi, m, xp,
                      i0, inside, Snode, (C*)U);

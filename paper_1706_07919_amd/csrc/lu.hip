@@ -2100,8 +2100,8 @@ struct Fac {
   // packing buffer bytes that would let every trailing update run in one slice
   size_t pack_need(int nb) const {
     size_t need = 0;
-    for (int c = 0; c < nmax; c += nb) {
-      const int e = std::min(c + nb, nmax);
+    for (int c = 0; c < nmax; c = block_end(c, nb)) {
+      const int e = block_end(c, nb);
       int total, maxn;
       active(e, &total, &maxn);
       if (total == 0) continue;
@@ -2201,9 +2201,11 @@ struct Fac {
   // Right-looking blocked top level: factor a block of nb columns (recursively),
   // apply its interchanges to every column left and right of it in one pass,
   // then the block row of U and the trailing update.
+  // end of the block of nb columns starting at column c
+  int block_end(int c, int nb) const { return std::min(nmax, c + nb); }
   void blocked(int nb) {
-    for (int c = 0; c < nmax; c += nb) {
-      const int e = std::min(c + nb, nmax);
+    for (int c = 0; c < nmax; c = block_end(c, nb)) {
+      const int e = block_end(c, nb);
       rec(c, e);
       laswp(c, e, 0, c, e, nmax);
       trsm(c, e - c, e, nmax);

@@ -172,6 +172,14 @@ def test_surrogate_fill_sweep_gain(ctx):
         err = (torch.linalg.vector_norm(r["x"] - x_dir, dim=(1, 2)) /
                torch.linalg.vector_norm(x_dir, dim=(1, 2))).max().item()
         assert err < 1e-6
+    # the filled results against the oracle's direct FP64 solve at three
+    # sampled wavenumbers of the dense grid
+    s = Surface(bodies)
+    for q in (9, 64, 127):
+        p, dp = bie.incident_plane_wave(s, k_pred[q])
+        _, _, xs = bie.solve(s, k_pred[q], bie.known_data(s, p, dp))
+        for r in (res, base):
+            assert rel(r["x"][q, 0].cpu().numpy(), xs) < 1e-6
     # the trained network's prediction is a far better start than zero
     assert np.median(res["rel_resid_prediction"]) < 0.05
     assert res["sweeps_mean"] < base["sweeps_mean"]
