@@ -49,7 +49,8 @@ typedef struct bem_ctx bem_ctx;
 /* Create a context on HIP device `device`, enqueuing on `hip_stream`
  * (a hipStream_t, NULL = the null stream).  The context owns the solver
  * workspace and the tuning cache; it is not thread-safe (one context per host
- * thread).  Returns BEM_EHIP if the device cannot be selected. */
+ * thread).  Returns BEM_EHIP if the device cannot be selected or the device
+ * address of the library's fixed field scratch cannot be taken. */
 bem_status bem_ctx_create(int device, void* hip_stream, bem_ctx** out);
 void bem_ctx_destroy(bem_ctx* ctx);
 /* Message of the last failed call on this context ("" if none). */
@@ -324,6 +325,24 @@ bem_status bem_field_eval(bem_ctx* ctx, const bem_surface* s, int32_t n_k, const
                           int32_t n_rhs, const void* phi, const void* psi, int32_t m,
                           const double* xp, int32_t* i0, int32_t i0_given, uint8_t* inside,
                           bem_prec prec, void* U);
+
+/* The same evaluation with no allocation: for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts that
+ * forbid hipMalloc).  It calls no hipMalloc / hipFree and creates no profiling
+ * events; the per-node sums S(x_a) that bem_field_eval keeps in the context's
+ * workspace go to a fixed 32 MiB device array of the library instead, so
+ *   n_rhs * n_k * n * (8 bytes for BEM_C64, 16 for BEM_C128) <= 32 MiB
+ * (e.g. n = 5124 nodes with up to 818 frequencies per call in c64), else
+ * BEM_EINVAL.  Arguments, results and ordering are those of bem_field_eval
+ * (same kernels, same results bit for bit).  Every context on a device shares
+ * that device's array, which keeps the last call's contents (nothing in it
+ * needs to start at zero): calls that overlap on one device (different
+ * streams or threads) race and give undefined results.  Returns BEM_EHIP if
+ * the context has no address for the array. */
+bem_status bem_field_eval_noalloc(bem_ctx* ctx, const bem_surface* s, int32_t n_k,
+                                  const double* k, int32_t n_rhs, const void* phi,
+                                  const void* psi, int32_t m, const double* xp, int32_t* i0,
+                                  int32_t i0_given, uint8_t* inside, bem_prec prec, void* U);
 
 /* ---------------------------------------------------------------- synthesis
  * Space-time field by inverse DFT over frequency (Sec. III last paragraph,

@@ -243,6 +243,10 @@ extern "C" bem_status bem_ctx_create(int device, void* hip_stream, bem_ctx** out
   c->stream = (hipStream_t)hip_stream;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cus = prop.multiProcessorCount;
+  if (field_scratch_init(c) != BEM_OK) {
+    delete c;
+    return BEM_EHIP;
+  }
   *out = c;
   return BEM_OK;
 }
@@ -906,17 +910,22 @@ extern "C" bem_status bem_refine_batched(bem_ctx* ctx, const bem_surface* s, int
 }
 
 // ============================================================ field / synthesis
-extern "C" bem_status bem_field_eval(bem_ctx* ctx, const bem_surface* s, int32_t n_k,
-                                     const double* k, int32_t n_rhs, const void* phi,
-                                     const void* psi, int32_t m, const double* xp, int32_t* i0,
-                                     int32_t i0_given, uint8_t* inside, bem_prec prec, void* U) {
+namespace {
+bem_status field_eval_impl(bem_ctx* ctx, const char* name, const bem_surface* s, int32_t n_k,
+                           const double* k, int32_t n_rhs, const void* phi, const void* psi,
+                           int32_t m, const double* xp, int32_t* i0, int32_t i0_given,
+                           uint8_t* inside, bem_prec prec, void* U, bool fixed_scratch) {
   if (!ctx) return BEM_EINVAL;
   bem_status st;
   if (!surface_ok(ctx, s, &st)) return st;
   if (n_k <= 0 || !k || n_rhs <= 0 || !phi || !psi || m < 0 || (m > 0 && (!xp || !i0 || !inside || !U)) ||
       (prec != BEM_C64 && prec != BEM_C128))
-    return fail(ctx, BEM_EINVAL, "bem_field_eval: bad argument");
-  if (n_rhs > 65535 || (n_k + 7) / 8 > 65535) return fail(ctx, BEM_EINVAL, "bem_field_eval: n_k or n_rhs too large");
+    return fail(ctx, BEM_EINVAL, "%s: bad argument", name);
+  if (n_rhs > 65535 || (n_k + 7) / 8 > 65535) return fail(ctx, BEM_EINVAL, "%s: n_k or n_rhs too large", name);
+  if (fixed_scratch && (prec == BEM_C128 ? 16 : 8) * (size_t)n_rhs * n_k * s->n > ctx->field_scratch_bytes)
+    return fail(ctx, BEM_EINVAL,
+                "%s: n_rhs * n_k * n = %lld node sums do not fit the %zu-byte fixed scratch", name,
+                (long long)n_rhs * n_k * s->n, ctx->field_scratch_bytes);
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
   if (m == 0) return BEM_OK;
   if (!i0_given) {
@@ -925,7 +934,25 @@ extern "C" bem_status bem_field_eval(bem_ctx* ctx, const bem_surface* s, int32_t
     // closest nodes given: only the inside flags are recomputed from them
     if ((st = launch_inside(ctx, s, m, xp, i0, inside)) != BEM_OK) return st;
   }
-  return launch_field(ctx, s, n_k, k, n_rhs, phi, psi, m, xp, i0, inside, prec, U);
+  return launch_field(ctx, s, n_k, k, n_rhs, phi, psi, m, xp, i0, inside, prec, U, fixed_scratch);
+}
+}  // namespace
+
+extern "C" bem_status bem_field_eval(bem_ctx* ctx, const bem_surface* s, int32_t n_k,
+                                     const double* k, int32_t n_rhs, const void* phi,
+                                     const void* psi, int32_t m, const double* xp, int32_t* i0,
+                                     int32_t i0_given, uint8_t* inside, bem_prec prec, void* U) {
+  return field_eval_impl(ctx, "bem_field_eval", s, n_k, k, n_rhs, phi, psi, m, xp, i0, i0_given,
+                         inside, prec, U, false);
+}
+
+extern "C" bem_status bem_field_eval_noalloc(bem_ctx* ctx, const bem_surface* s, int32_t n_k,
+                                             const double* k, int32_t n_rhs, const void* phi,
+                                             const void* psi, int32_t m, const double* xp,
+                                             int32_t* i0, int32_t i0_given, uint8_t* inside,
+                                             bem_prec prec, void* U) {
+  return field_eval_impl(ctx, "bem_field_eval_noalloc", s, n_k, k, n_rhs, phi, psi, m, xp, i0,
+                         i0_given, inside, prec, U, true);
 }
 
 extern "C" bem_status pulse_synthesize(bem_ctx* ctx, int32_t m, int32_t n_k, const void* U,

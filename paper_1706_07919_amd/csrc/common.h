@@ -54,6 +54,10 @@ struct bem_ctx {
   // frequency indices of a sparse synthesis (grown on demand)
   int32_t* midx = nullptr;
   size_t midx_cap = 0;
+  // device address of the field evaluation's fixed scratch on this context's
+  // device (taken once, when the context is created) and its size
+  void* field_scratch = nullptr;
+  size_t field_scratch_bytes = 0;
 };
 
 namespace bem {
@@ -160,9 +164,14 @@ bem_status launch_closest(bem_ctx*, const bem_surface*, int m, const double* xp,
                           uint8_t* inside);
 bem_status launch_inside(bem_ctx*, const bem_surface*, int m, const double* xp,
                          const int32_t* i0, uint8_t* inside);
+// fixed_scratch: node sums in the fixed per-device scratch (no workspace, no
+// profiling events), EINVAL when they do not fit
 bem_status launch_field(bem_ctx*, const bem_surface*, int n_k, const double* k, int n_rhs,
                         const void* phi, const void* psi, int m, const double* xp,
-                        const int32_t* i0, const uint8_t* inside, bem_prec prec, void* U);
+                        const int32_t* i0, const uint8_t* inside, bem_prec prec, void* U,
+                        bool fixed_scratch = false);
+// take the device address of the field scratch for ctx (its device current)
+bem_status field_scratch_init(bem_ctx* ctx);
 // m_index (device, or NULL for the dense grid m = 1..n_k): frequency index of
 // each column of U and c
 bem_status launch_synth(bem_ctx*, int m, int n_k, const void* U, const int32_t* m_index,

@@ -21,6 +21,16 @@
 namespace bem {
 namespace {
 
+// ---------------------------------------------------------------- fixed scratch
+// The node sums S(x_a) of bem_field_eval_noalloc live in this file-scope
+// array (one copy per device, held until the process ends) instead of the
+// context's workspace.  Host code never passes the array's name as an address
+// (in host code it is only a stand-in for the device symbol): field_scratch_init
+// takes the device address once per context, with the context's device
+// current, and the kernels receive that pointer.
+constexpr size_t kFieldScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kFieldScratchBytes];
+
 constexpr double kInv2Pi = 0.15915494309189533576888376337251;
 constexpr double kFourPi = 12.566370614359172953850573533118;
 
@@ -285,21 +295,25 @@ __global__ __launch_bounds__(kFT, sizeof(R) == 4 ? 3 : 1) void field_kernel(
   }
 }
 
+// Snode_fixed: the fixed scratch (bem_field_eval_noalloc: no workspace, no
+// profiling events), or NULL for the context's workspace.
 template <typename R, int FCH>
 bem_status field_go(bem_ctx* ctx, const bem_surface* s, int n_k, const double* k, int n_rhs,
                     const void* phi, const void* psi, int m, const double* xp,
-                    const int32_t* i0, const uint8_t* inside, void* U) {
+                    const int32_t* i0, const uint8_t* inside, void* U, void* Snode_fixed) {
   using C = typename CX<R>::T;
-  void* ws = nullptr;
-  const size_t need = sizeof(C) * (size_t)n_rhs * n_k * s->n;
-  bem_status st = workspace(ctx, need, &ws);
-  if (st != BEM_OK) return st;
+  void* ws = Snode_fixed;
+  if (!ws) {
+    const size_t need = sizeof(C) * (size_t)n_rhs * n_k * s->n;
+    bem_status st = workspace(ctx, need, &ws);
+    if (st != BEM_OK) return st;
+  }
   C* Snode = (C*)ws;
   const int fch = (n_k + FCH - 1) / FCH;
   dim3 gnode((s->n + kPW - 1) / kPW, fch, n_rhs);
   // the profiling bracket covers both passes: the field at the nodes (the
   // expansion centres) and at the points
-  const int pi = prof_begin(ctx, "field");
+  const int pi = Snode_fixed ? -1 : prof_begin(ctx, "field");
   hipLaunchKernelGGL((field_kernel<R, FCH, 0>), gnode, dim3(kFT), 0, ctx->stream, s->n, s->x,
                      s->nrm, s->w, k, n_k, n_rhs, (const double2*)phi, (const double2*)psi, s->n,
                      s->x, (const int32_t*)nullptr, (const uint8_t*)nullptr, Snode, (C*)nullptr);
@@ -309,8 +323,9 @@ bem_status field_go(bem_ctx* ctx, const bem_surface* s, int n_k, const double* k
                      s->nrm, s->w, k, n_k, n_rhs, (const double2*)phi, (const double2*)psi, m, xp,
                      i0, inside, Snode, (C*)U);
   // kernel terms: one per (point or node, frequency, node, rhs)
-  prof_end(ctx, "field", pi, ((double)m + s->n) * n_k * s->n * n_rhs,
-           (double)sizeof(C) * ((double)m + s->n) * n_k * n_rhs);
+  if (!Snode_fixed)
+    prof_end(ctx, "field", pi, ((double)m + s->n) * n_k * s->n * n_rhs,
+             (double)sizeof(C) * ((double)m + s->n) * n_k * n_rhs);
   BEM_CHECK_LAUNCH(ctx);
   return BEM_OK;
 }
@@ -337,11 +352,38 @@ bem_status launch_inside(bem_ctx* ctx, const bem_surface* s, int m, const double
 
 bem_status launch_field(bem_ctx* ctx, const bem_surface* s, int n_k, const double* k, int n_rhs,
                         const void* phi, const void* psi, int m, const double* xp,
-                        const int32_t* i0, const uint8_t* inside, bem_prec prec, void* U) {
+                        const int32_t* i0, const uint8_t* inside, bem_prec prec, void* U,
+                        bool fixed_scratch) {
   if (m <= 0) return BEM_OK;
+  void* fixed = nullptr;
+  if (fixed_scratch) {
+    const size_t need = (prec == BEM_C128 ? 16 : 8) * (size_t)n_rhs * n_k * s->n;
+    if (!ctx->field_scratch)
+      return fail(ctx, BEM_EHIP, "bem_field_eval_noalloc: no device address for the fixed scratch");
+    if (need > ctx->field_scratch_bytes)
+      return fail(ctx, BEM_EINVAL,
+                  "bem_field_eval_noalloc: n_rhs * n_k * n = %lld node sums need %zu bytes, more "
+                  "than the %zu-byte fixed scratch",
+                  (long long)n_rhs * n_k * s->n, need, ctx->field_scratch_bytes);
+    fixed = ctx->field_scratch;
+  }
   if (prec == BEM_C128)
-    return field_go<double, 8>(ctx, s, n_k, k, n_rhs, phi, psi, m, xp, i0, inside, U);
-  return field_go<float, 8>(ctx, s, n_k, k, n_rhs, phi, psi, m, xp, i0, inside, U);
+    return field_go<double, 8>(ctx, s, n_k, k, n_rhs, phi, psi, m, xp, i0, inside, U, fixed);
+  return field_go<float, 8>(ctx, s, n_k, k, n_rhs, phi, psi, m, xp, i0, inside, U, fixed);
+}
+
+bem_status field_scratch_init(bem_ctx* ctx) {
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    ctx->field_scratch = nullptr;
+    ctx->field_scratch_bytes = 0;
+    return fail(ctx, BEM_EHIP, "hipGetSymbolAddress of the field scratch failed: %s",
+                hipGetErrorString(e));
+  }
+  ctx->field_scratch = ptr;
+  ctx->field_scratch_bytes = kFieldScratchBytes;
+  return BEM_OK;
 }
 
 }  // namespace bem

@@ -28,7 +28,8 @@ EXPORTED = [
     "bem_mesh_counts", "bem_mesh_icosphere", "bem_mesh_bowl_counts", "bem_mesh_bowl", "bem_incident", "bem_assemble", "bem_residual",
     "bem_solve_opts_default", "bem_solve_batched", "bem_getrf_batched", "bem_getrs_batched",
     "bem_autotune_lu",
-    "bem_split_unknowns", "bem_field_eval", "pulse_synthesize", "pulse_synthesize_sparse",
+    "bem_split_unknowns", "bem_field_eval", "bem_field_eval_noalloc", "pulse_synthesize",
+    "pulse_synthesize_sparse",
     "bem_pulse_coeffs", "bem_pulse_dominant",
     "bem_residual_check", "bem_refine_batched", "bem_mlp_features", "bem_mlp_dense_fwd", "bem_mlp_dense_bwd",
     "bem_mlp_mse_grad", "bem_mlp_adam", "bem_mlp_pack", "bem_mlp_unpack",
@@ -100,6 +101,8 @@ def load(path: str = LIB_PATH):
         "bem_split_unknowns": ([vp, C.POINTER(bem_surface), i32, i32, vp, vp, vp, vp], C.c_int),
         "bem_field_eval": ([vp, C.POINTER(bem_surface), i32, vp, i32, vp, vp, i32, vp, vp, i32, vp,
                             C.c_int, vp], C.c_int),
+        "bem_field_eval_noalloc": ([vp, C.POINTER(bem_surface), i32, vp, i32, vp, vp, i32, vp, vp,
+                                    i32, vp, C.c_int, vp], C.c_int),
         "pulse_synthesize": ([vp, i32, i32, vp, i32, vp, i32, i32, vp, dbl, vp], C.c_int),
         "pulse_synthesize_sparse": ([vp, i32, i32, vp, vp, i32, vp, i32, i32, vp, dbl, vp],
                                     C.c_int),
@@ -308,6 +311,13 @@ def bem_field_eval(ctx, surf, n_k, k, n_rhs, phi, psi, m, xp, i0, i0_given, insi
     _check(load().bem_field_eval(ctx.handle, C.byref(surf), n_k, _ptr(k), n_rhs, _ptr(phi),
                                  _ptr(psi), m, _ptr(xp), _ptr(i0), int(i0_given), _ptr(inside),
                                  prec, _ptr(U)), ctx)
+
+
+def bem_field_eval_noalloc(ctx, surf, n_k, k, n_rhs, phi, psi, m, xp, i0, i0_given, inside,
+                           prec, U):
+    _check(load().bem_field_eval_noalloc(ctx.handle, C.byref(surf), n_k, _ptr(k), n_rhs,
+                                         _ptr(phi), _ptr(psi), m, _ptr(xp), _ptr(i0),
+                                         int(i0_given), _ptr(inside), prec, _ptr(U)), ctx)
 
 
 def pulse_synthesize(ctx, m, n_k, U, n_pulse, c, T, add_incident, xp, dk, p):
