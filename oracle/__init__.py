@@ -11,6 +11,9 @@ Modules (each function cites the passage of the paper it follows):
             functions of Appendix A and the S_inf integrals of Appendix B), dense
             LAPACK solve
   field   - closest surface node, non-singular field representation (Eq. BRIEFdmn)
+  quadratic - six-node quadratic elements on geodesic spheres with Gauss
+            quadrature (Sec. III, Sec. IV A: 500 elements / 1002 nodes):
+            assembly, direct solve and field
   pulse   - incident pulses (Eq. pulse and others), DFT coefficients, time
             synthesis by inverse FFT (Eq. inverseFourier, Sec. IV)
   series  - closed-form spherical-harmonic series for a soft/hard sphere (pins)
