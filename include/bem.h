@@ -396,6 +396,74 @@ bem_status bem_pulse_coeffs(int32_t kind, const double* params, int32_t n_params
  *   0 < n_keep <= n_k, else EINVAL. */
 bem_status bem_pulse_dominant(const double* c, int32_t n_k, int32_t n_keep, int32_t* m_index);
 
+/* ---------------------------------------------------------------- quadratic elements
+ * Surface of six-node quadratic elements (Sec. III: quadratic interpolants
+ * within each element, integrals free of singularities evaluated by Gauss
+ * quadrature; Sec. IV A: the sphere as 500 quadratic elements and 1002
+ * nodes): nodes x[n][3] with unit normals nrm[n][3] (out of the body; used at
+ * the collocation nodes) and BC flags bc[n]; elements elem[n_elem][6] =
+ * (v0, v1, v2, m01, m12, m20), the corners counter-clockwise seen from
+ * outside, then the nodes on the edges (v0 v1), (v1 v2), (v2 v0).  All [dev].
+ * A node may belong to at most 12 elements (EINVAL otherwise). */
+typedef struct {
+  int32_t n;
+  const double* x;
+  const double* nrm;
+  const uint8_t* bc;
+  int32_t n_elem;
+  const int32_t* elem;
+} bem_quad_surface;
+
+/* Frequency-nu geodesic sphere of six-node elements [host]: every icosahedron
+ * face cut into nu^2 triangles on its barycentric grid, points projected onto
+ * the sphere and mapped to center + (radius u0, radius u1, radius aspect u2);
+ * the edge midpoints are the projected chord midpoints; analytic normals.
+ * 40 nu^2 + 2 nodes (the vertices first) and 20 nu^2 elements (nu = 5: 1002
+ * and 500, the paper's sizes).  Fixed evaluation order (no fused
+ * multiply-add): reproducible bit for bit.  x[n][3], nrm[n][3],
+ * elems[n_elem][6] caller-allocated; EINVAL for nu outside 1..64, radius <= 0
+ * or aspect < 1. */
+bem_status bem_mesh_quadratic_counts(int32_t nu, int32_t* n_nodes, int32_t* n_elems);
+bem_status bem_mesh_quadratic(int32_t nu, double radius, double aspect, const double center[3],
+                              double* x, double* nrm, int32_t* elems);
+
+/* System of the quadratic-element equation, collocated at the nodes:
+ *   4 pi phi_i + int [psi - phi_i g' - psi_i f'] G dS = int [phi - phi_i g - psi_i f] H dS
+ * with phi, psi and the geometry interpolated by each element's six shape
+ * functions, f, g of Appendix A about x_i, H = dG/dn with the element normal,
+ * every element integrated by the 7-point degree-5 triangle rule (Radon's):
+ *   (M_psi)_ij =  sum N_a(q) wJ_q G_q,  (M_phi)_ij = -sum N_a(q) wJ_q H_q  (node a of e = j)
+ *   (M_phi)_ii += 4 pi - sum_q (g' G - g H) wJ_q,  (M_psi)_ii += -sum_q (f' G - f H) wJ_q
+ * in float64.  Arguments and outputs (A row-major, b = -B y, diag64) as for
+ * bem_assemble. */
+bem_status bem_assemble_quadratic(bem_ctx* ctx, const bem_quad_surface* s, int32_t n_k,
+                                  const double* k, int32_t n_rhs, const void* y, bem_prec prec,
+                                  void* A, int32_t ld, void* b, void* diag64);
+
+/* Direct solve of the quadratic-element system per wavenumber (Sec. IV A).
+ * BEM_FP64_DIRECT: float64 LU.  The float32 modes: the float32 LU of the
+ * rounded matrix (4M / 3M / bf16x3 updates) refined against the stored float64
+ * operator until ||dx||_2/||x||_2 <= tol_step; items that do not converge in
+ * max_iter sweeps are re-solved in float64 when fallback != 0 (else ENOCONV).
+ * k[n_k], y[n_k][n_rhs][n] c128 [dev]; x_out[n_k][n_rhs][n] c128 [dev];
+ * info [host] [n_k*n_rhs] or NULL (rel_resid is that of the stored float64
+ * operator).  Synchronises the stream. */
+bem_status bem_solve_quadratic(bem_ctx* ctx, const bem_quad_surface* s, int32_t n_k,
+                               const double* k, int32_t n_rhs, const void* y,
+                               const bem_solve_opts* opts, void* x_out, bem_solve_info* info);
+
+/* Field at observation points by Eq. BRIEFdmn with the element quadrature
+ * (x0 the closest node a; the Gauss quadrature of the paper's Sec. III):
+ *   4 pi P(x_p) = 4 pi phi_a + int [u (H^p - H^a) - u' (G^p - G^a)] dS,
+ *   u = phi - phi_a g - psi_a f,  u' = psi - phi_a g' - psi_a f'
+ * in float64; closest node and inside flags as for bem_field_eval.
+ * phi, psi [dev] c128 [n_k][n_rhs][n]; xp[m][3], i0[m] (output), inside[m]
+ * (output) [dev]; U [dev] c128 [n_rhs][m][n_k]. */
+bem_status bem_field_eval_quadratic(bem_ctx* ctx, const bem_quad_surface* s, int32_t n_k,
+                                    const double* k, int32_t n_rhs, const void* phi,
+                                    const void* psi, int32_t m, const double* xp, int32_t* i0,
+                                    uint8_t* inside, void* U);
+
 /* ---------------------------------------------------------------- surrogate
  * A small network mapping a wavenumber to the surface unknowns of a fixed
  * geometry (not part of the paper; its predictions are only used after

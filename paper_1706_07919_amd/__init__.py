@@ -5,4 +5,4 @@ The computation lives in ``libbem.so`` (HIP kernels for gfx950, C ABI in
 keeps the device buffers of a surface together (``surface``).
 """
 from . import native  # noqa: F401
-from .surface import DeviceSurface, host_surface  # noqa: F401
+from .surface import DeviceQuadSurface, DeviceSurface, host_surface  # noqa: F401

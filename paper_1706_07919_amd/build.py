@@ -20,7 +20,8 @@ ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libbem.so")
 OBJ = os.path.join(HERE, "_build")
 
-HIP_SOURCES = ["operator.hip", "lu.hip", "ir.hip", "field.hip", "synth.hip", "mlp.hip", "api.cpp"]
+HIP_SOURCES = ["operator.hip", "lu.hip", "ir.hip", "field.hip", "synth.hip", "mlp.hip", "quad.hip",
+               "api.cpp"]
 HOST_SOURCES = ["mesh.cpp", "pulse.cpp"]
 
 

@@ -1004,3 +1004,268 @@ extern "C" bem_status pulse_synthesize_sparse(bem_ctx* ctx, int32_t m, int32_t n
   BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   return launch_synth(ctx, m, n_sel, U, ctx->midx, n_pulse, c, T, add_incident, xp, dk, p);
 }
+
+// ============================================================ quadratic elements
+namespace {
+
+bool quad_surface_ok(bem_ctx* ctx, const bem_quad_surface* s, bem_status* st) {
+  if (!s || s->n <= 0 || !s->x || !s->nrm || !s->bc || s->n_elem <= 0 || !s->elem) {
+    *st = fail(ctx, BEM_EINVAL, "quadratic surface: n, n_elem must be > 0 and x, nrm, bc, elem non-NULL");
+    return false;
+  }
+  if ((int64_t)s->n_elem * 7 * 8 >= ((int64_t)1 << 31)) {
+    *st = fail(ctx, BEM_EINVAL, "quadratic surface: too many elements");
+    return false;
+  }
+  return true;
+}
+
+// buffers of one chunk of kc wavenumbers of the quadratic solve
+struct QuadChunk {
+  double2* A64;    // [kc][n][ld] the float64 operator (kept for the residual)
+  void* LU;        // [kc][n][ld] c128 (FP64 direct) or c64 factors
+  int32_t* piv;    // [kc][n]
+  int32_t* perm;   // [kc][n]
+  int32_t* info;   // [kc]
+  double2* diag;   // [kc][n][2]
+  double2* b;      // [kc][nr][n]
+  double2* x;      // [kc][nr][n]
+  double2* r;      // [kc][nr][n]
+  float2* r32;     // [kc][nr][n]
+  float2* d32;     // [kc][nr][n]
+  double* scale;   // [kc*nr]
+  double* dn2;     // [kc*nr]
+  double* xn2;     // [kc*nr]
+  double* rn2;     // [kc*nr]
+  uint8_t* active; // [kc*nr]
+};
+
+QuadChunk quad_carve(void* base, int n, int64_t ld, int nr, int kc, bool c128_factors,
+                     size_t* used) {
+  char* p = (char*)base;
+  auto take = [&](size_t bytes) {
+    void* out = p;
+    p += (bytes + 255) / 256 * 256;
+    return out;
+  };
+  const size_t v = (size_t)kc * nr * n;
+  QuadChunk c;
+  c.A64 = (double2*)take((size_t)kc * n * ld * 16);
+  c.LU = take((size_t)kc * n * ld * (c128_factors ? 16 : 8));
+  c.piv = (int32_t*)take((size_t)kc * n * 4);
+  c.perm = (int32_t*)take((size_t)kc * n * 4);
+  c.info = (int32_t*)take((size_t)kc * 4);
+  c.diag = (double2*)take((size_t)kc * n * 32);
+  c.b = (double2*)take(v * 16);
+  c.x = (double2*)take(v * 16);
+  c.r = (double2*)take(v * 16);
+  c.r32 = (float2*)take(v * 8);
+  c.d32 = (float2*)take(v * 8);
+  c.scale = (double*)take((size_t)kc * nr * 8);
+  c.dn2 = (double*)take((size_t)kc * nr * 8);
+  c.xn2 = (double*)take((size_t)kc * nr * 8);
+  c.rn2 = (double*)take((size_t)kc * nr * 8);
+  c.active = (uint8_t*)take((size_t)kc * nr);
+  if (used) *used = (size_t)(p - (char*)base);
+  return c;
+}
+
+}  // namespace
+
+extern "C" bem_status bem_assemble_quadratic(bem_ctx* ctx, const bem_quad_surface* s, int32_t n_k,
+                                             const double* k, int32_t n_rhs, const void* y,
+                                             bem_prec prec, void* A, int32_t ld, void* b,
+                                             void* diag64) {
+  if (!ctx) return BEM_EINVAL;
+  bem_status st;
+  if (!quad_surface_ok(ctx, s, &st)) return st;
+  if (n_rhs <= 0 || !y || !b || (prec != BEM_C64 && prec != BEM_C128) || (A && ld < s->n))
+    return fail(ctx, BEM_EINVAL, "bem_assemble_quadratic: bad argument");
+  if (n_k > 65535) return fail(ctx, BEM_EINVAL, "bem_assemble_quadratic: n_k > 65535");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
+  if ((st = check_k(ctx, n_k, k)) != BEM_OK) return st;
+  void* ws = nullptr;
+  if ((st = workspace(ctx, quad_setup_bytes(s->n, s->n_elem), &ws)) != BEM_OK) return st;
+  double* qp = nullptr;
+  int32_t* inc = nullptr;
+  if ((st = quad_setup(ctx, s, ws, &qp, &inc)) != BEM_OK) return st;
+  return launch_quad_assemble(ctx, s, qp, inc, n_k, k, n_rhs, y, prec, A, A ? ld : 0,
+                              A ? (int64_t)s->n * ld : 0, b, diag64);
+}
+
+// Chunks of wavenumbers sized to the workspace: float64 assembly (the operator
+// is kept), factorisation (float64, or float32 of the rounded matrix), and for
+// the float32 modes refinement r = b - A64 x until ||dx|| / ||x|| <= tol_step.
+extern "C" bem_status bem_solve_quadratic(bem_ctx* ctx, const bem_quad_surface* s, int32_t n_k,
+                                          const double* k, int32_t n_rhs, const void* y,
+                                          const bem_solve_opts* opts, void* x_out,
+                                          bem_solve_info* info) {
+  if (!ctx) return BEM_EINVAL;
+  bem_status st;
+  if (!quad_surface_ok(ctx, s, &st)) return st;
+  bem_solve_opts o;
+  bem_solve_opts_default(&o);
+  if (opts) o = *opts;
+  if (n_rhs <= 0 || !y || !x_out || o.mode < BEM_FP64_DIRECT || o.mode > BEM_FP32_IR_B3 ||
+      o.max_iter < 0 || !(o.tol_step >= 0.0) || o.nb < 0)
+    return fail(ctx, BEM_EINVAL, "bem_solve_quadratic: bad argument");
+  if (s->n > 12288) return fail(ctx, BEM_EUNSUPPORTED, "bem_solve_quadratic: n = %d > 12288", s->n);
+  if (n_rhs > 65535) return fail(ctx, BEM_EINVAL, "bem_solve_quadratic: n_rhs > 65535");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
+  if ((st = check_k(ctx, n_k, k)) != BEM_OK) return st;
+  const int n = s->n, nr = n_rhs;
+  const int64_t ld = round_up(n, 16);
+  const bool fp64 = o.mode == BEM_FP64_DIRECT;
+  const int gk = o.mode == BEM_FP32_IR_3M ? BEM_GEMM_3M
+                 : o.mode == BEM_FP32_IR_B3 ? BEM_GEMM_BF16X3 : BEM_GEMM_4M;
+  const size_t setup = quad_setup_bytes(n, s->n_elem);
+  auto bytes = [&](int kc, bool c128f) {
+    size_t used = 0;
+    (void)quad_carve(nullptr, n, ld, nr, kc, c128f, &used);
+    return used + setup + 256;
+  };
+  size_t free_b = 0, total_b = 0;
+  BEM_HIP_TRY(ctx, hipMemGetInfo(&free_b, &total_b));
+  const size_t limit = ctx->ws_limit ? ctx->ws_limit : (size_t)(0.75 * (double)(free_b + ctx->ws_size));
+  int kc = n_k;
+  // the residual grid holds a chunk's kc * n_rhs vectors in its y dimension
+  while (kc > 1 && (bytes(kc, true) > limit || (int64_t)kc * n_rhs > 65535)) kc = (kc + 1) / 2;
+  void* ws = nullptr;
+  if ((st = workspace(ctx, bytes(kc, true), &ws)) != BEM_OK) return st;
+  double* qp = nullptr;
+  int32_t* inc = nullptr;
+  if ((st = quad_setup(ctx, s, ws, &qp, &inc)) != BEM_OK) return st;
+  void* cbase = (char*)ws + (setup + 255) / 256 * 256;
+  void* hp = nullptr;
+  if ((st = pinned(ctx, (size_t)kc * nr * 24 + (size_t)kc * nr + (size_t)kc * 4 + 8, &hp)) != BEM_OK)
+    return st;
+  double* h_dn = (double*)hp;
+  double* h_xn = h_dn + (size_t)kc * nr;
+  double* h_rn = h_xn + (size_t)kc * nr;
+  uint8_t* h_act = (uint8_t*)(h_rn + (size_t)kc * nr);
+  int32_t* h_info = (int32_t*)(h_act + ((size_t)kc * nr + 3) / 4 * 4);
+  LuPlan plan;
+  for (int k0 = 0; k0 < n_k; k0 += kc) {
+    const int cur = std::min(kc, n_k - k0);
+    const int nv = cur * nr;
+    const int64_t stride = (int64_t)n * ld;
+    const double2* yk = (const double2*)y + (size_t)k0 * nr * n;
+    double2* xo = (double2*)x_out + (size_t)k0 * nr * n;
+    bool chunk_fp64 = fp64;
+    std::vector<uint8_t> act(nv, 1);
+    std::vector<int> iters(nv, 0);
+    std::vector<double> step(nv, 0.0), bn(nv, 0.0);
+    for (int pass = 0; pass < 2; ++pass) {
+      QuadChunk c = quad_carve(cbase, n, ld, nr, cur, true, nullptr);
+      if ((st = launch_quad_assemble(ctx, s, qp, inc, cur, k + k0, nr, yk, BEM_C128, c.A64, ld,
+                                     stride, c.b, c.diag)) != BEM_OK)
+        return st;
+      if ((st = launch_norm2(ctx, nv, n, c.b, c.rn2)) != BEM_OK) return st;
+      std::vector<LuMatrixSet> sets(1, LuMatrixSet{c.LU, c.piv, c.info, ld, stride, n, cur});
+      if (chunk_fp64) {
+        BEM_HIP_TRY(ctx, hipMemcpyAsync(c.LU, c.A64, (size_t)cur * stride * 16,
+                                        hipMemcpyDeviceToDevice, ctx->stream));
+        plan.nb = o.nb > 0 ? o.nb : lu_plan_nb(ctx, BEM_C128, 0, n);
+        if ((st = lu_factor_groups(ctx, BEM_C128, sets, plan, 0)) != BEM_OK) return st;
+        if ((st = lu_perm(ctx, n, cur, c.piv, c.perm)) != BEM_OK) return st;
+        if ((st = lu_solve_perm(ctx, BEM_C128, n, ld, stride, cur, c.LU, c.perm, nr, c.b, c.x,
+                                (int64_t)nr * n)) != BEM_OK)
+          return st;
+      } else {
+        if ((st = launch_c128_to_c64(ctx, (int64_t)cur * stride, c.A64, c.LU)) != BEM_OK) return st;
+        plan.nb = o.nb > 0 ? o.nb : lu_plan_nb(ctx, BEM_C64, gk, n);
+        if ((st = lu_factor_groups(ctx, BEM_C64, sets, plan, gk)) != BEM_OK) return st;
+        if ((st = lu_perm(ctx, n, cur, c.piv, c.perm)) != BEM_OK) return st;
+        if ((st = fill_zero(ctx, c.x, (size_t)nv * n * 16)) != BEM_OK) return st;
+        BEM_HIP_TRY(ctx, hipMemcpyAsync(c.r, c.b, (size_t)nv * n * 16, hipMemcpyDeviceToDevice,
+                                        ctx->stream));
+        std::fill(act.begin(), act.end(), 1);
+        for (int it = 0; it < std::max(1, o.max_iter); ++it) {
+          std::memcpy(h_act, act.data(), nv);
+          BEM_HIP_TRY(ctx, hipMemcpyAsync(c.active, h_act, nv, hipMemcpyHostToDevice, ctx->stream));
+          if ((st = launch_ir_scale(ctx, nv, n, c.r, c.r32, c.scale)) != BEM_OK) return st;
+          if ((st = lu_solve_perm(ctx, BEM_C64, n, ld, stride, cur, c.LU, c.perm, nr, c.r32,
+                                  c.d32, (int64_t)nr * n)) != BEM_OK)
+            return st;
+          if ((st = launch_ir_update(ctx, nv, n, c.d32, c.scale, c.active, c.x, c.dn2, c.xn2, 1)) != BEM_OK)
+            return st;
+          if ((st = launch_quad_residual(ctx, n, c.A64, ld, stride, cur, nr, c.b, c.x, c.r)) != BEM_OK)
+            return st;
+          BEM_HIP_TRY(ctx, hipMemcpyAsync(h_dn, c.dn2, 8 * (size_t)nv, hipMemcpyDeviceToHost, ctx->stream));
+          BEM_HIP_TRY(ctx, hipMemcpyAsync(h_xn, c.xn2, 8 * (size_t)nv, hipMemcpyDeviceToHost, ctx->stream));
+          BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+          int live = 0;
+          for (int v = 0; v < nv; ++v) {
+            if (!act[v]) continue;
+            iters[v] = it + 1;
+            step[v] = h_xn[v] > 0 ? std::sqrt(h_dn[v] / h_xn[v]) : (h_dn[v] > 0 ? 1.0 : 0.0);
+            if (std::isfinite(step[v]) && !(step[v] > o.tol_step)) act[v] = 0;
+            else ++live;
+          }
+          if (live == 0) break;
+        }
+      }
+      // report: the float64 operator's residual of the returned x
+      if ((st = launch_quad_residual(ctx, n, c.A64, ld, stride, cur, nr, c.b, c.x, c.r)) != BEM_OK)
+        return st;
+      if ((st = launch_norm2(ctx, nv, n, c.r, c.dn2)) != BEM_OK) return st;
+      BEM_HIP_TRY(ctx, hipMemcpyAsync(h_dn, c.dn2, 8 * (size_t)nv, hipMemcpyDeviceToHost, ctx->stream));
+      BEM_HIP_TRY(ctx, hipMemcpyAsync(h_rn, c.rn2, 8 * (size_t)nv, hipMemcpyDeviceToHost, ctx->stream));
+      BEM_HIP_TRY(ctx, hipMemcpyAsync(h_info, c.info, 4 * (size_t)cur, hipMemcpyDeviceToHost, ctx->stream));
+      BEM_HIP_TRY(ctx, hipMemcpyAsync(xo, c.x, (size_t)nv * n * 16, hipMemcpyDeviceToDevice, ctx->stream));
+      BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      bool bad = false;
+      for (int v = 0; v < nv; ++v) {
+        const bool conv = chunk_fp64 ? h_info[v / nr] == 0 : (!act[v] && h_info[v / nr] == 0);
+        bad = bad || !conv;
+        if (info) {
+          bem_solve_info& I = info[(size_t)k0 * nr + v];
+          I.iters = chunk_fp64 ? 0 : iters[v];
+          I.used_fp64 = chunk_fp64 && !fp64 ? 1 : 0;
+          I.singular = h_info[v / nr] != 0;
+          I.converged = conv ? 1 : 0;
+          I.rel_resid = h_rn[v] > 0 ? std::sqrt(h_dn[v] / h_rn[v]) : 0.0;
+          I.rel_step = chunk_fp64 ? 0.0 : step[v];
+        }
+      }
+      if (chunk_fp64) {
+        for (int q = 0; q < cur; ++q)
+          if (h_info[q] != 0) return fail(ctx, BEM_ESINGULAR, "zero pivot in the FP64 factorisation");
+        break;
+      }
+      if (!bad) break;
+      if (!o.fallback)
+        return fail(ctx, BEM_ENOCONV, "bem_solve_quadratic: refinement did not converge");
+      chunk_fp64 = true;   // re-solve the whole chunk in float64
+    }
+  }
+  BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return BEM_OK;
+}
+
+extern "C" bem_status bem_field_eval_quadratic(bem_ctx* ctx, const bem_quad_surface* s,
+                                               int32_t n_k, const double* k, int32_t n_rhs,
+                                               const void* phi, const void* psi, int32_t m,
+                                               const double* xp, int32_t* i0, uint8_t* inside,
+                                               void* U) {
+  if (!ctx) return BEM_EINVAL;
+  bem_status st;
+  if (!quad_surface_ok(ctx, s, &st)) return st;
+  if (n_k <= 0 || !k || n_rhs <= 0 || !phi || !psi || m < 0 || (m > 0 && (!xp || !i0 || !inside || !U)))
+    return fail(ctx, BEM_EINVAL, "bem_field_eval_quadratic: bad argument");
+  if (n_k > 65535 || n_rhs > 65535) return fail(ctx, BEM_EINVAL, "bem_field_eval_quadratic: n_k or n_rhs too large");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
+  if (m == 0) return BEM_OK;
+  const size_t setup = (quad_setup_bytes(s->n, s->n_elem) + 255) / 256 * 256;
+  const size_t interp = ((size_t)n_k * n_rhs * s->n_elem * 7 * 16 + 255) / 256 * 256;
+  void* ws = nullptr;
+  if ((st = workspace(ctx, setup + 2 * interp, &ws)) != BEM_OK) return st;
+  double* qp = nullptr;
+  int32_t* inc = nullptr;
+  if ((st = quad_setup(ctx, s, ws, &qp, &inc)) != BEM_OK) return st;
+  bem_surface nodal{s->n, s->x, s->nrm, nullptr, s->bc};
+  if ((st = launch_closest(ctx, &nodal, m, xp, i0, inside)) != BEM_OK) return st;
+  char* base = (char*)ws + setup;
+  return launch_quad_field(ctx, s, qp, n_k, k, n_rhs, phi, psi, base, base + interp, m, xp, i0,
+                           inside, U);
+}

@@ -178,4 +178,21 @@ bem_status launch_synth(bem_ctx*, int m, int n_k, const void* U, const int32_t* 
                         int n_pulse, const double* c, int T, int add_incident, const double* xp,
                         double dk, float* p);
 
+// ------------------------------------------------------------------ quadratic elements
+// workspace of quad_setup (quadrature points and node incidences)
+size_t quad_setup_bytes(int n, int n_elem);
+bem_status quad_setup(bem_ctx*, const bem_quad_surface*, void* ws, double** qp, int32_t** inc);
+bem_status launch_quad_assemble(bem_ctx*, const bem_quad_surface*, const double* qp,
+                                const int32_t* inc, int n_k, const double* k, int n_rhs,
+                                const void* y, bem_prec prec, void* A, int64_t ld,
+                                int64_t a_stride, void* b, void* diag64);
+// r = b - A64 x over n_k matrices (stride elements apart) and n_rhs vectors each
+bem_status launch_quad_residual(bem_ctx*, int n, const void* A64, int64_t ld, int64_t stride,
+                                int n_k, int n_rhs, const void* b, const void* x, void* r);
+// phq, psq: [n_k * n_rhs][n_elem * 7] c128 scratch
+bem_status launch_quad_field(bem_ctx*, const bem_quad_surface*, const double* qp, int n_k,
+                             const double* k, int n_rhs, const void* phi, const void* psi,
+                             void* phq, void* psq, int m, const double* xp, const int32_t* i0,
+                             const uint8_t* inside, void* U);
+
 }  // namespace bem

@@ -214,3 +214,132 @@ extern "C" bem_status bem_mesh_bowl(int32_t n_theta, int32_t n_phi, double radiu
     for (size_t t = 0; t < f.size(); ++t) faces[t] = f[t];
   return BEM_OK;
 }
+
+// Six-node quadratic elements on a frequency-nu geodesic sphere (Sec. III:
+// quadratic interpolation within each element; Sec. IV A: 500 elements and
+// 1002 nodes, i.e. nu = 5).  Each icosahedron face is cut into nu^2 triangles
+// on its barycentric grid; a grid point with integer weights (c_A, c_B, c_C)
+// is shared between faces through its nonzero (vertex, weight) pairs and
+// placed at normalise(sum c_v V_v), summed in increasing vertex index.  The
+// elements' edge midpoints (chord midpoints projected onto the sphere) follow
+// the vertices, in the order met walking each element's edges (v0 v1),
+// (v1 v2), (v2 v0).  Element nodes: (v0, v1, v2, m01, m12, m20).
+namespace {
+
+void geodesic(int nu, std::vector<V3>& pts, std::vector<int32_t>& f) {
+  std::vector<V3> ico;
+  std::vector<int32_t> tri;
+  base_icosahedron(ico, tri);
+  pts.clear();
+  f.clear();
+  std::unordered_map<uint64_t, int32_t> index;
+  auto point = [&](int a, int b, int c, int i, int j) -> int32_t {
+    // nonzero (vertex, weight) pairs in increasing vertex order
+    int pv[3] = {a, b, c}, pw[3] = {nu - i - j, i, j};
+    int cnt = 0, kv[3], kw[3];
+    for (int s = 0; s < 3; ++s)
+      if (pw[s] > 0) {
+        kv[cnt] = pv[s];
+        kw[cnt] = pw[s];
+        ++cnt;
+      }
+    for (int s = 1; s < cnt; ++s)
+      for (int t = s; t > 0 && (kv[t] < kv[t - 1] || (kv[t] == kv[t - 1] && kw[t] < kw[t - 1])); --t) {
+        std::swap(kv[t], kv[t - 1]);
+        std::swap(kw[t], kw[t - 1]);
+      }
+    uint64_t key = 0;
+    for (int s = 0; s < 3; ++s) {
+      const uint64_t slot = s < cnt ? (uint64_t)kv[s] * 4096u + (uint64_t)kw[s] : 0xFFFFu;
+      key |= slot << (16 * s);
+    }
+    auto it = index.find(key);
+    if (it != index.end()) return it->second;
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int s = 0; s < cnt; ++s) {
+      const double w = (double)kw[s];
+      sx = sx + w * ico[kv[s]].x;
+      sy = sy + w * ico[kv[s]].y;
+      sz = sz + w * ico[kv[s]].z;
+    }
+    pts.push_back(unit({sx, sy, sz}));
+    const int32_t idx = (int32_t)pts.size() - 1;
+    index.emplace(key, idx);
+    return idx;
+  };
+  std::vector<int32_t> grid((size_t)(nu + 1) * (nu + 1));
+  for (int t = 0; t < 20; ++t) {
+    const int a = tri[3 * t], b = tri[3 * t + 1], c = tri[3 * t + 2];
+    for (int i = 0; i <= nu; ++i)
+      for (int j = 0; j <= nu - i; ++j) grid[(size_t)i * (nu + 1) + j] = point(a, b, c, i, j);
+    auto g = [&](int i, int j) { return grid[(size_t)i * (nu + 1) + j]; };
+    for (int i = 0; i < nu; ++i)
+      for (int j = 0; j < nu - i; ++j) {
+        const int32_t up[3] = {g(i, j), g(i + 1, j), g(i, j + 1)};
+        f.insert(f.end(), up, up + 3);
+        if (i + j < nu - 1) {
+          const int32_t dn[3] = {g(i + 1, j), g(i + 1, j + 1), g(i, j + 1)};
+          f.insert(f.end(), dn, dn + 3);
+        }
+      }
+  }
+}
+
+}  // namespace
+
+extern "C" bem_status bem_mesh_quadratic_counts(int32_t nu, int32_t* n_nodes, int32_t* n_elems) {
+  if (nu < 1 || nu > 64 || !n_nodes || !n_elems) return BEM_EINVAL;
+  *n_nodes = 40 * nu * nu + 2;
+  *n_elems = 20 * nu * nu;
+  return BEM_OK;
+}
+
+extern "C" bem_status bem_mesh_quadratic(int32_t nu, double radius, double aspect,
+                                         const double center[3], double* x, double* nrm,
+                                         int32_t* elems) {
+  int32_t N = 0, F = 0;
+  if (bem_mesh_quadratic_counts(nu, &N, &F) != BEM_OK || !(radius > 0.0) || !(aspect >= 1.0) ||
+      !std::isfinite(radius) || !std::isfinite(aspect) || !center || !x || !nrm || !elems)
+    return BEM_EINVAL;
+  std::vector<V3> u;
+  std::vector<int32_t> f;
+  geodesic(nu, u, f);
+  std::unordered_map<uint64_t, int32_t> mids;
+  for (size_t t = 0; t < f.size(); t += 3) {
+    const int32_t v[3] = {f[t], f[t + 1], f[t + 2]};
+    int32_t m[3];
+    for (int s = 0; s < 3; ++s) {
+      const int32_t p = v[s], q = v[(s + 1) % 3];
+      const uint64_t key = p < q ? ((uint64_t)p << 32) | (uint32_t)q : ((uint64_t)q << 32) | (uint32_t)p;
+      auto it = mids.find(key);
+      if (it != mids.end()) {
+        m[s] = it->second;
+      } else {
+        const V3 pa = u[p], pb = u[q];
+        u.push_back(unit({(pa.x + pb.x) * 0.5, (pa.y + pb.y) * 0.5, (pa.z + pb.z) * 0.5}));
+        m[s] = (int32_t)u.size() - 1;
+        mids.emplace(key, m[s]);
+      }
+    }
+    int32_t* e = elems + 2 * t;   // element t/3, six entries
+    e[0] = v[0];
+    e[1] = v[1];
+    e[2] = v[2];
+    e[3] = m[0];
+    e[4] = m[1];
+    e[5] = m[2];
+  }
+  if ((int32_t)u.size() != N) return BEM_EINVAL;
+  const double cx = center[0], cy = center[1], cz = center[2];
+  const double sx = radius, sz = radius * aspect;
+  for (int32_t i = 0; i < N; ++i) {
+    x[3 * i + 0] = cx + sx * u[i].x;
+    x[3 * i + 1] = cy + sx * u[i].y;
+    x[3 * i + 2] = cz + sz * u[i].z;
+    const V3 n = unit({u[i].x / sx, u[i].y / sx, u[i].z / sz});
+    nrm[3 * i + 0] = n.x;
+    nrm[3 * i + 1] = n.y;
+    nrm[3 * i + 2] = n.z;
+  }
+  return BEM_OK;
+}

@@ -33,6 +33,8 @@ EXPORTED = [
     "bem_pulse_coeffs", "bem_pulse_dominant",
     "bem_residual_check", "bem_refine_batched", "bem_mlp_features", "bem_mlp_dense_fwd", "bem_mlp_dense_bwd",
     "bem_mlp_mse_grad", "bem_mlp_adam", "bem_mlp_pack", "bem_mlp_unpack",
+    "bem_mesh_quadratic_counts", "bem_mesh_quadratic", "bem_assemble_quadratic",
+    "bem_solve_quadratic", "bem_field_eval_quadratic",
 ]
 
 
@@ -45,6 +47,11 @@ class BemError(RuntimeError):
 class bem_surface(C.Structure):
     _fields_ = [("n", C.c_int32), ("x", C.c_void_p), ("nrm", C.c_void_p), ("w", C.c_void_p),
                 ("bc", C.c_void_p)]
+
+
+class bem_quad_surface(C.Structure):
+    _fields_ = [("n", C.c_int32), ("x", C.c_void_p), ("nrm", C.c_void_p), ("bc", C.c_void_p),
+                ("n_elem", C.c_int32), ("elem", C.c_void_p)]
 
 
 class bem_problem(C.Structure):
@@ -118,6 +125,14 @@ def load(path: str = LIB_PATH):
         "bem_mlp_adam": ([vp, i64, vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float], C.c_int),
         "bem_mlp_pack": ([vp, i32, i32, vp, vp, i32, vp], C.c_int),
         "bem_mlp_unpack": ([vp, i32, i32, vp, vp, vp], C.c_int),
+        "bem_mesh_quadratic_counts": ([i32, C.POINTER(i32), C.POINTER(i32)], C.c_int),
+        "bem_mesh_quadratic": ([i32, dbl, dbl, vp, vp, vp, vp], C.c_int),
+        "bem_assemble_quadratic": ([vp, C.POINTER(bem_quad_surface), i32, vp, i32, vp, C.c_int, vp,
+                                    i32, vp, vp], C.c_int),
+        "bem_solve_quadratic": ([vp, C.POINTER(bem_quad_surface), i32, vp, i32, vp,
+                                 C.POINTER(bem_solve_opts), vp, C.POINTER(bem_solve_info)], C.c_int),
+        "bem_field_eval_quadratic": ([vp, C.POINTER(bem_quad_surface), i32, vp, i32, vp, vp, i32,
+                                      vp, vp, vp, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -240,6 +255,41 @@ def bem_pulse_dominant(c, n_keep):
 
 
 # ---------------------------------------------------------------- device entry points
+def bem_mesh_quadratic(nu, radius=1.0, aspect=1.0, center=(0.0, 0.0, 0.0)):
+    """Six-node elements on a frequency-nu geodesic sphere: (x, nrm, elems)."""
+    nn, ne = C.c_int32(), C.c_int32()
+    _check(load().bem_mesh_quadratic_counts(int(nu), C.byref(nn), C.byref(ne)))
+    x = np.empty((nn.value, 3)); nrm = np.empty((nn.value, 3))
+    elems = np.empty((ne.value, 6), dtype=np.int32)
+    c = np.ascontiguousarray(center, dtype=np.float64)
+    _check(load().bem_mesh_quadratic(int(nu), float(radius), float(aspect), c.ctypes.data,
+                                     x.ctypes.data, nrm.ctypes.data, elems.ctypes.data))
+    return x, nrm, elems
+
+
+def quad_surface_struct(n, x, nrm, bc, n_elem, elem):
+    return bem_quad_surface(int(n), _ptr(x), _ptr(nrm), _ptr(bc), int(n_elem), _ptr(elem))
+
+
+def bem_assemble_quadratic(ctx, qsurf, n_k, k, n_rhs, y, prec, A, ld, b, diag64=None):
+    _check(load().bem_assemble_quadratic(ctx.handle, C.byref(qsurf), n_k, _ptr(k), n_rhs,
+                                         _ptr(y), prec, _ptr(A), int(ld), _ptr(b), _ptr(diag64)),
+           ctx)
+
+
+def bem_solve_quadratic(ctx, qsurf, n_k, k, n_rhs, y, opts, x_out):
+    info = (bem_solve_info * (n_k * n_rhs))()
+    _check(load().bem_solve_quadratic(ctx.handle, C.byref(qsurf), n_k, _ptr(k), n_rhs, _ptr(y),
+                                      C.byref(opts), _ptr(x_out), info), ctx)
+    return info
+
+
+def bem_field_eval_quadratic(ctx, qsurf, n_k, k, n_rhs, phi, psi, m, xp, i0, inside, U):
+    _check(load().bem_field_eval_quadratic(ctx.handle, C.byref(qsurf), n_k, _ptr(k), n_rhs,
+                                           _ptr(phi), _ptr(psi), m, _ptr(xp), _ptr(i0),
+                                           _ptr(inside), _ptr(U)), ctx)
+
+
 def surface_struct(n, x, nrm, w, bc):
     return bem_surface(int(n), _ptr(x), _ptr(nrm), _ptr(w), _ptr(bc))
 

@@ -37,3 +37,27 @@ class DeviceSurface:
     @classmethod
     def from_bodies(cls, bodies, rescale_area=True, device="cuda"):
         return cls(*host_surface(bodies, rescale_area), device=device)
+
+
+class DeviceQuadSurface:
+    """Six-node elements of one body on the device (nodes, normals, BC flags,
+    element table) plus the C struct; the mesh comes from the library's host
+    builder (``bem_mesh_quadratic``)."""
+
+    def __init__(self, x, nrm, bc, elems, device="cuda"):
+        import torch
+        self.n = int(x.shape[0])
+        self.n_elem = int(elems.shape[0])
+        self.x = torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64).to(device)
+        self.nrm = torch.as_tensor(np.ascontiguousarray(nrm), dtype=torch.float64).to(device)
+        self.bc = torch.as_tensor(np.ascontiguousarray(bc), dtype=torch.uint8).to(device)
+        self.elem = torch.as_tensor(np.ascontiguousarray(elems), dtype=torch.int32).to(device)
+        self.struct = native.quad_surface_struct(self.n, self.x, self.nrm, self.bc, self.n_elem,
+                                                 self.elem)
+
+    @classmethod
+    def from_body(cls, body, nu, device="cuda"):
+        """``body``: center, radius, aspect, bc (its level is not used)."""
+        x, nrm, elems = native.bem_mesh_quadratic(nu, body.radius, body.aspect, body.center)
+        bc = np.full(x.shape[0], body.bc, dtype=np.uint8)
+        return cls(x, nrm, bc, elems, device=device)

@@ -141,3 +141,22 @@ def test_bowl_mesh_invalid(lib):
             native.bem_mesh_bowl(*args)
     with pytest.raises(native.BemError):
         native.bem_mesh_bowl(8, 8, radius=-1.0)
+
+
+@pytest.mark.parametrize("nu,radius,aspect,center", [(1, 1.0, 1.0, (0.0, 0.0, 0.0)),
+                                                     (2, 0.7, 1.8, (0.3, -1.0, 2.0)),
+                                                     (5, 1.0, 1.0, (0.0, 0.0, 0.0))])
+def test_quadratic_mesh_bit_exact_vs_oracle(nu, radius, aspect, center):
+    """The library's six-node geodesic mesh (host builder) equals the oracle's
+    bit for bit: node coordinates, normals and the element table; nu = 5 is the
+    paper's 500-element, 1002-node sphere."""
+    from oracle.quadratic import QuadSurface
+    from workloads import Body, HARD
+    x, nrm, elems = native.bem_mesh_quadratic(nu, radius, aspect, center)
+    qs = QuadSurface(Body(center, radius, aspect, 0, HARD), nu)
+    assert x.shape == qs.x.shape and elems.shape == qs.elems.shape
+    assert np.array_equal(elems, qs.elems)
+    assert np.array_equal(x.view(np.uint64), qs.x.view(np.uint64))
+    assert np.array_equal(nrm.view(np.uint64), qs.nrm.view(np.uint64))
+    with pytest.raises(native.BemError):
+        native.bem_mesh_quadratic(0)
