@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--cpu-k", type=int, default=8)
     ap.add_argument("--mode", choices=["b3", "4m", "3m"], default="3m",
                     help="complex GEMM form of the float32 factorisation")
+    ap.add_argument("--field-rhs", type=int, default=4,
+                    help="right-hand sides of the multi-rhs field measurement (0: off)")
     ap.add_argument("--b3-steps", type=int, default=2,
                     help="steps of the bf16x3 variant timed after the headline (0: none)")
     ap.add_argument("--spacetime", type=int, default=1,
@@ -267,14 +269,51 @@ def main():
     if args.b3_steps > 0 and args.mode != "b3":
         ob3 = native.bem_solve_opts_default()
         ob3.mode = native.BEM_FP32_IR_B3
-        native.bem_solve_batched(ctx, [(ds.struct, n_k, kd, 1, y)], ob3, [x])
+        xb3 = torch.zeros_like(x)   # x keeps the headline mode's solution
+        native.bem_solve_batched(ctx, [(ds.struct, n_k, kd, 1, y)], ob3, [xb3])
         torch.cuda.synchronize()
         tb = time.perf_counter()
         for _ in range(args.b3_steps):
             native.bem_incident(ctx, ds.struct, n_k, kd, (0.0, 0.0, 1.0), y)
-            native.bem_solve_batched(ctx, [(ds.struct, n_k, kd, 1, y)], ob3, [x])
+            native.bem_solve_batched(ctx, [(ds.struct, n_k, kd, 1, y)], ob3, [xb3])
         torch.cuda.synchronize()
         b3 = n_k * args.b3_steps / (time.perf_counter() - tb)
+        del xb3
+
+    # the field with several right-hand sides (the step's solution and phase-
+    # rotated copies): every generated kernel value is applied to all of them
+    mrhs = None
+    if args.field_rhs > 1:
+        R = args.field_rhs
+        rot = torch.exp(1j * 0.7 * torch.arange(R, device=dev, dtype=torch.float64)).view(1, R, 1)
+        phr = (phi * rot).contiguous()
+        psr = (psi * rot).contiguous()
+        Ur = torch.zeros((R, m, n_k), dtype=torch.complex64, device=dev)
+
+        def fr(nr, a, b, out):
+            native.bem_field_eval(ctx, ds.struct, n_k, kd, nr, a, b, m, xp, i0, 1, ins,
+                                  native.BEM_C64, out)
+        fr(R, phr, psr, Ur)
+        fr(1, phi, psi, U)
+        torch.cuda.synchronize()
+        reps = 3
+        ta = time.perf_counter()
+        for _ in range(reps):
+            fr(R, phr, psr, Ur)
+        torch.cuda.synchronize()
+        t_multi = (time.perf_counter() - ta) / reps
+        ta = time.perf_counter()
+        for _ in range(reps):
+            fr(1, phi, psi, U)
+        torch.cuda.synchronize()
+        t_one = (time.perf_counter() - ta) / reps
+        mrhs = {"n_rhs": R, "points": m, "n_k": n_k,
+                "pt_freq_rhs_per_s": m * n_k * R / t_multi,
+                "ms": 1e3 * t_multi, "ms_one_rhs": 1e3 * t_one,
+                "vs_separate_calls": R * t_one / t_multi,
+                "note": "both passes of bem_field_eval (nodes and points); vs_separate_calls = "
+                        "n_rhs single-rhs calls' time over one n_rhs call"}
+        del phr, psr, Ur
 
     st = None
     if args.spacetime:
@@ -315,6 +354,7 @@ def main():
                                      "(the step's own 4096-point field is field_pt_freq_per_s_step)"
                                      if st else "4096 points x 512 frequencies of the step"),
         "field_pt_freq_per_s_step": field_rate,
+        "field_multi_rhs": mrhs,
         "fp64_direct_solves_per_s": fp64_rate,
         "fp32ir_vs_fp64_direct_rel_err": rel64,
         "fp32ir_vs_fp64_direct_max_rel_err_per_k": rel64_max,

@@ -9,7 +9,11 @@
 //   A1 = sum w_j (phi_j H^x_j - psi_j G^x_j), A2 = sum w_j (g_aj H^x_j - g'_aj G^x_j),
 //   A3 = sum w_j (f_aj H^x_j - f'_aj G^x_j)   (j != a).
 // S(x_a) is computed once per node by the same kernel, so the per-point work
-// is one sweep over the nodes.  Float32 kernels take every phase k*r and k*s
+// is one sweep over the nodes.  A2 and A3 do not depend on the right-hand
+// side: a workgroup takes NR right-hand sides at once and applies every
+// generated kernel value (w G, w H for one node, point and frequency) to all
+// of them, so NR right-hand sides cost one kernel generation and NR complex
+// multiply-adds per term instead of NR generations.  Float32 kernels take every phase k*r and k*s
 // in float64, reduce it to [-1/2, 1/2) revolutions, and evaluate the
 // trigonometric functions in float32 on the reduced argument.  Each point's
 // sweep is split over kParts lanes (lane q takes every kParts-th node), whose
@@ -123,7 +127,8 @@ __device__ inline R part_sum(R v) {
 
 // MODE 0: write S(x_p) for points = nodes (raw, [rhs][n_k][n]).
 // MODE 1: write P(x_p) = phi_a + (S(x_p) - S(x_a)) / (4 pi) into U[rhs][m][n_k].
-template <typename R, int FCH, int MODE>
+// Right-hand sides blockIdx.z * NR + r, r < min(NR, n_rhs - blockIdx.z * NR).
+template <typename R, int FCH, int MODE, int NR>
 __global__ __launch_bounds__(kFT, sizeof(R) == 4 ? 3 : 1) void field_kernel(
     int n, const double* __restrict__ x, const double* __restrict__ nrm,
     const double* __restrict__ w, const double* __restrict__ kv, int n_k, int n_rhs,
@@ -135,12 +140,13 @@ __global__ __launch_bounds__(kFT, sizeof(R) == 4 ? 3 : 1) void field_kernel(
   __shared__ double sx[kNJ][3];
   __shared__ double sn[kNJ][3];
   __shared__ R sw[kNJ];
-  __shared__ C sphi[FCH][kNJ];
-  __shared__ C spsi[FCH][kNJ];
+  __shared__ C sphi[NR][FCH][kNJ];
+  __shared__ C spsi[NR][FCH][kNJ];
   const int p = blockIdx.x * kPW + threadIdx.x / kParts;
   const int part = threadIdx.x % kParts;
   const int m0 = blockIdx.y * FCH;
-  const int rhs = blockIdx.z;
+  const int r0 = blockIdx.z * NR;
+  const int nrh = min(NR, n_rhs - r0);
   const int nf = min(FCH, n_k - m0);
   const bool valid = p < m && (MODE == 0 || !inside[p]);
   const int a = p < m ? (MODE == 0 ? p : i0[p]) : 0;
@@ -163,10 +169,11 @@ __global__ __launch_bounds__(kFT, sizeof(R) == 4 ? 3 : 1) void field_kernel(
 #pragma unroll
   for (int f = 1; f < FCH; ++f)
     if (f < nf && !(fabs(kk[f] - (kk[0] + f * dkk)) <= 4e-16 * fabs(kk[f]))) uni = false;
-  C A1[FCH], A2[FCH], A3[FCH];
+  C A1[NR][FCH], A2[FCH], A3[FCH];
 #pragma unroll
   for (int f = 0; f < FCH; ++f) {
-    A1[f].x = A1[f].y = R(0);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) A1[r][f].x = A1[r][f].y = R(0);
     A2[f].x = A2[f].y = R(0);
     A3[f].x = A3[f].y = R(0);
   }
@@ -178,16 +185,16 @@ __global__ __launch_bounds__(kFT, sizeof(R) == 4 ? 3 : 1) void field_kernel(
       sn[e / 3][e % 3] = nrm[3 * j0 + e];
     }
     for (int e = threadIdx.x; e < cnt; e += kFT) sw[e] = (R)w[j0 + e];
-    for (int e = threadIdx.x; e < FCH * kNJ; e += kFT) {
-      const int f = e / kNJ, jj = e % kNJ;
-      if (f < nf && jj < cnt) {
-        const int64_t o = ((int64_t)(m0 + f) * n_rhs + rhs) * n + j0 + jj;
+    for (int e = threadIdx.x; e < NR * FCH * kNJ; e += kFT) {
+      const int r = e / (FCH * kNJ), f = (e / kNJ) % FCH, jj = e % kNJ;
+      if (r < nrh && f < nf && jj < cnt) {
+        const int64_t o = ((int64_t)(m0 + f) * n_rhs + r0 + r) * n + j0 + jj;
         const double2 u = phi[o], v = psi[o];
-        sphi[f][jj].x = (R)u.x; sphi[f][jj].y = (R)u.y;
-        spsi[f][jj].x = (R)v.x; spsi[f][jj].y = (R)v.y;
+        sphi[r][f][jj].x = (R)u.x; sphi[r][f][jj].y = (R)u.y;
+        spsi[r][f][jj].x = (R)v.x; spsi[r][f][jj].y = (R)v.y;
       } else {
-        sphi[f][jj].x = sphi[f][jj].y = R(0);
-        spsi[f][jj].x = spsi[f][jj].y = R(0);
+        sphi[r][f][jj].x = sphi[r][f][jj].y = R(0);
+        spsi[r][f][jj].x = spsi[r][f][jj].y = R(0);
       }
     }
     __syncthreads();
@@ -245,9 +252,13 @@ __global__ __launch_bounds__(kFT, sizeof(R) == 4 ? 3 : 1) void field_kernel(
         const R gr = wg * ec, gi = wg * es;
         const R hb = k * wh1;
         const R hr = ec * wh2 - es * hb, hi = ec * hb + es * wh2;
-        const C ph = sphi[f][jj], ps = spsi[f][jj];
-        A1[f].x += (ph.x * hr - ph.y * hi) - (ps.x * gr - ps.y * gi);
-        A1[f].y += (ph.x * hi + ph.y * hr) - (ps.x * gi + ps.y * gr);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          if (r >= nrh) break;   // uniform
+          const C ph = sphi[r][f][jj], ps = spsi[r][f][jj];
+          A1[r][f].x += (ph.x * hr - ph.y * hi) - (ps.x * gr - ps.y * gi);
+          A1[r][f].y += (ph.x * hi + ph.y * hr) - (ps.x * gi + ps.y * gr);
+        }
         const R g = cs, gp = -k * ss * nn;
         const R fv = ss * kinv[f], fp = cs * nn;
         A2[f].x += g * hr - gp * gr;
@@ -259,45 +270,68 @@ __global__ __launch_bounds__(kFT, sizeof(R) == 4 ? 3 : 1) void field_kernel(
   }
 #pragma unroll
   for (int f = 0; f < FCH; ++f) {
-    A1[f].x = part_sum(A1[f].x);
-    A1[f].y = part_sum(A1[f].y);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      A1[r][f].x = part_sum(A1[r][f].x);
+      A1[r][f].y = part_sum(A1[r][f].y);
+    }
     A2[f].x = part_sum(A2[f].x);
     A2[f].y = part_sum(A2[f].y);
     A3[f].x = part_sum(A3[f].x);
     A3[f].y = part_sum(A3[f].y);
   }
   if (p >= m) return;
-  // lane q of the point writes frequency q of the chunk (and q + kParts, ...)
+  // the point's NR * FCH outputs (r, f) are shared out over its kParts lanes
 #pragma unroll
-  for (int f = 0; f < FCH; ++f) {
-    if (f >= nf) break;
-    if (f % kParts != part) continue;
-    const int64_t oa = ((int64_t)(m0 + f) * n_rhs + rhs) * n + a;
-    const double2 pa = phi[oa], qa = psi[oa];
-    const R par = (R)pa.x, pai = (R)pa.y, qar = (R)qa.x, qai = (R)qa.y;
-    C S;
-    S.x = A1[f].x - (par * A2[f].x - pai * A2[f].y) - (qar * A3[f].x - qai * A3[f].y);
-    S.y = A1[f].y - (par * A2[f].y + pai * A2[f].x) - (qar * A3[f].y + qai * A3[f].x);
-    if (MODE == 0) {
-      Snode[((int64_t)rhs * n_k + m0 + f) * n + a] = S;
-    } else {
-      C out;
-      if (!valid) {
-        out.x = out.y = R(0);
+  for (int r = 0; r < NR; ++r) {
+#pragma unroll
+    for (int f = 0; f < FCH; ++f) {
+      if ((r * FCH + f) % kParts != part || r >= nrh || f >= nf) continue;
+      const int rhs = r0 + r;
+      const int64_t oa = ((int64_t)(m0 + f) * n_rhs + rhs) * n + a;
+      const double2 pa = phi[oa], qa = psi[oa];
+      const R par = (R)pa.x, pai = (R)pa.y, qar = (R)qa.x, qai = (R)qa.y;
+      C S;
+      S.x = A1[r][f].x - (par * A2[f].x - pai * A2[f].y) - (qar * A3[f].x - qai * A3[f].y);
+      S.y = A1[r][f].y - (par * A2[f].y + pai * A2[f].x) - (qar * A3[f].y + qai * A3[f].x);
+      if (MODE == 0) {
+        Snode[((int64_t)rhs * n_k + m0 + f) * n + a] = S;
       } else {
-        const C s0 = Snode[((int64_t)rhs * n_k + m0 + f) * n + a];
-        const R inv4pi = (R)(1.0 / kFourPi);
-        out.x = par + (S.x - s0.x) * inv4pi;
-        out.y = pai + (S.y - s0.y) * inv4pi;
+        C out;
+        if (!valid) {
+          out.x = out.y = R(0);
+        } else {
+          const C s0 = Snode[((int64_t)rhs * n_k + m0 + f) * n + a];
+          const R inv4pi = (R)(1.0 / kFourPi);
+          out.x = par + (S.x - s0.x) * inv4pi;
+          out.y = pai + (S.y - s0.y) * inv4pi;
+        }
+        U[((int64_t)rhs * m + p) * n_k + m0 + f] = out;
       }
-      U[((int64_t)rhs * m + p) * n_k + m0 + f] = out;
     }
   }
 }
 
 // Snode_fixed: the fixed scratch (bem_field_eval_noalloc: no workspace, no
 // profiling events), or NULL for the context's workspace.
-template <typename R, int FCH>
+template <typename R, int FCH, int NR>
+void field_pass(bem_ctx* ctx, const bem_surface* s, int n_k, const double* k, int n_rhs,
+                const void* phi, const void* psi, int m, const double* xp, const int32_t* i0,
+                const uint8_t* inside, void* Snode, void* U) {
+  using C = typename CX<R>::T;
+  const int fch = (n_k + FCH - 1) / FCH;
+  const int nz = (n_rhs + NR - 1) / NR;
+  dim3 gnode((s->n + kPW - 1) / kPW, fch, nz);
+  hipLaunchKernelGGL((field_kernel<R, FCH, 0, NR>), gnode, dim3(kFT), 0, ctx->stream, s->n, s->x,
+                     s->nrm, s->w, k, n_k, n_rhs, (const double2*)phi, (const double2*)psi, s->n,
+                     s->x, (const int32_t*)nullptr, (const uint8_t*)nullptr, (C*)Snode, (C*)nullptr);
+  dim3 gpts((m + kPW - 1) / kPW, fch, nz);
+  hipLaunchKernelGGL((field_kernel<R, FCH, 1, NR>), gpts, dim3(kFT), 0, ctx->stream, s->n, s->x,
+                     s->nrm, s->w, k, n_k, n_rhs, (const double2*)phi, (const double2*)psi, m, xp,
+                     i0, inside, (C*)Snode, (C*)U);
+}
+
+template <typename R>
 bem_status field_go(bem_ctx* ctx, const bem_surface* s, int n_k, const double* k, int n_rhs,
                     const void* phi, const void* psi, int m, const double* xp,
                     const int32_t* i0, const uint8_t* inside, void* U, void* Snode_fixed) {
@@ -308,20 +342,16 @@ bem_status field_go(bem_ctx* ctx, const bem_surface* s, int n_k, const double* k
     bem_status st = workspace(ctx, need, &ws);
     if (st != BEM_OK) return st;
   }
-  C* Snode = (C*)ws;
-  const int fch = (n_k + FCH - 1) / FCH;
-  dim3 gnode((s->n + kPW - 1) / kPW, fch, n_rhs);
   // the profiling bracket covers both passes: the field at the nodes (the
   // expansion centres) and at the points
   const int pi = Snode_fixed ? -1 : prof_begin(ctx, "field");
-  hipLaunchKernelGGL((field_kernel<R, FCH, 0>), gnode, dim3(kFT), 0, ctx->stream, s->n, s->x,
-                     s->nrm, s->w, k, n_k, n_rhs, (const double2*)phi, (const double2*)psi, s->n,
-                     s->x, (const int32_t*)nullptr, (const uint8_t*)nullptr, Snode, (C*)nullptr);
-  BEM_CHECK_LAUNCH(ctx);
-  dim3 gpts((m + kPW - 1) / kPW, fch, n_rhs);
-  hipLaunchKernelGGL((field_kernel<R, FCH, 1>), gpts, dim3(kFT), 0, ctx->stream, s->n, s->x,
-                     s->nrm, s->w, k, n_k, n_rhs, (const double2*)phi, (const double2*)psi, m, xp,
-                     i0, inside, Snode, (C*)U);
+  // one right-hand side: 8 frequencies per thread; more: 4 frequencies and up
+  // to 4 right-hand sides per workgroup (8 frequencies with 2 right-hand
+  // sides already exceed the 168-register budget of three workgroups per CU)
+  if (n_rhs == 1)
+    field_pass<R, 8, 1>(ctx, s, n_k, k, n_rhs, phi, psi, m, xp, i0, inside, ws, U);
+  else
+    field_pass<R, 4, 4>(ctx, s, n_k, k, n_rhs, phi, psi, m, xp, i0, inside, ws, U);
   // kernel terms: one per (point or node, frequency, node, rhs)
   if (!Snode_fixed)
     prof_end(ctx, "field", pi, ((double)m + s->n) * n_k * s->n * n_rhs,
@@ -368,8 +398,8 @@ bem_status launch_field(bem_ctx* ctx, const bem_surface* s, int n_k, const doubl
     fixed = ctx->field_scratch;
   }
   if (prec == BEM_C128)
-    return field_go<double, 8>(ctx, s, n_k, k, n_rhs, phi, psi, m, xp, i0, inside, U, fixed);
-  return field_go<float, 8>(ctx, s, n_k, k, n_rhs, phi, psi, m, xp, i0, inside, U, fixed);
+    return field_go<double>(ctx, s, n_k, k, n_rhs, phi, psi, m, xp, i0, inside, U, fixed);
+  return field_go<float>(ctx, s, n_k, k, n_rhs, phi, psi, m, xp, i0, inside, U, fixed);
 }
 
 bem_status field_scratch_init(bem_ctx* ctx) {
