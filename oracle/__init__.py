@@ -11,6 +11,8 @@ Modules (each function cites the passage of the paper it follows):
             functions of Appendix A and the S_inf integrals of Appendix B), dense
             LAPACK solve
   field   - closest surface node, non-singular field representation (Eq. BRIEFdmn)
+  chief   - interior-point conditions added to the surface rows, solved in the
+            least-squares sense (the remedy for fictitious resonances)
   quadratic - six-node quadratic elements on geodesic spheres with Gauss
             quadrature (Sec. III, Sec. IV A: 500 elements / 1002 nodes):
             assembly, direct solve and field

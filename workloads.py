@@ -181,3 +181,21 @@ def mlp_initial_weights(sizes, seed: int = 0):
 
 SURROGATE_OCTAVES = 8      # Fourier features sin/cos(2^l pi k / 12), l = 0..7
 SURROGATE_HIDDEN = (512, 512, 512, 512)
+
+
+def interior_points(bodies: List[Body], per_body: int = 8, seed: int = 0,
+                    frac=(0.2, 0.6)) -> np.ndarray:
+    """Random points strictly inside each body (seeded): a direction uniform on
+    the sphere and a radius fraction uniform in ``frac`` of the body's
+    semi-axes, [len(bodies) * per_body, 3].  Auxiliary collocation points for
+    the interior-point conditions that remove fictitious resonances."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in bodies:
+        v = rng.normal(size=(per_body, 3))
+        v /= np.linalg.norm(v, axis=1)[:, None]
+        t = rng.uniform(frac[0], frac[1], size=(per_body, 1))
+        u = v * t
+        out.append(np.asarray(b.center)[None, :] + u * np.array([b.radius, b.radius, b.radius * b.aspect]))
+    return np.concatenate(out).astype(np.float64)
+
