@@ -252,6 +252,31 @@ bem_status bem_solve_batched(bem_ctx* ctx, const bem_problem* probs, int32_t n_p
                              const bem_solve_opts* opts, void* const* x_out,
                              bem_solve_info* info);
 
+/* Remedy for fictitious resonances (Sec. IV A avoids the wavenumbers where
+ * the interior of a body resonates; there the surface equation is nearly
+ * singular and its solution carries a spurious interior mode).  Green's second
+ * identity on the exterior domain gives, for the radiating scattered field
+ * and a point x_c strictly inside a body (normals out of the body),
+ *   sum_j w_j (phi_j H_cj - psi_j G_cj) = 0,  d = x_j - x_c,
+ *   G = e^{ikr}/r,  H = e^{ikr}(ikr - 1)(d.n_j)/r^3,
+ * one more row C x = d per point (split by the boundary conditions as the
+ * surface rows).  The surface rows A x = b and the n_c interior rows are
+ * solved in the least-squares sense, float64 throughout: the normal equations
+ * (A^H A + C^H C) x = A^H b + C^H d are formed by complex GEMMs (rocBLAS) and
+ * factored by the library's LU.  Away from resonances the interior rows hold
+ * to the discretisation error and the result moves by that much.
+ * xc [dev] [n_c][3] float64: points strictly inside the bodies, off the nodal
+ * surfaces of the interior eigenfunctions (random points are); k [dev] n_k
+ * wavenumbers; y [dev] c128 [n_k][n_rhs][n] known data; x_out [dev] c128
+ * [n_k][n_rhs][n] unknowns; info [host] [n_k*n_rhs] or NULL (rel_resid: the
+ * stacked system's least-squares residual, ||[A;C] x - [b;d]|| / ||[b;d]||).
+ * Holds about (2 n + n_c) (n + n_rhs) 16 bytes per wavenumber of workspace;
+ * ESINGULAR if the normal equations have a zero pivot; synchronises the
+ * stream. */
+bem_status bem_solve_chief(bem_ctx* ctx, const bem_surface* s, int32_t n_k, const double* k,
+                           int32_t n_rhs, const void* y, int32_t n_c, const double* xc,
+                           void* x_out, bem_solve_info* info);
+
 /* Building blocks of the direct solve (Sec. IV A), exposed for testing and for
  * callers that keep the factors to re-use them for other right-hand sides
  * (Sec. V notes that the factorised system of a frequency can be kept and

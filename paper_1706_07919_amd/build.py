@@ -21,7 +21,7 @@ OUT = os.path.join(HERE, "libbem.so")
 OBJ = os.path.join(HERE, "_build")
 
 HIP_SOURCES = ["operator.hip", "lu.hip", "ir.hip", "field.hip", "synth.hip", "mlp.hip", "quad.hip",
-               "api.cpp"]
+               "chief.hip", "api.cpp"]
 HOST_SOURCES = ["mesh.cpp", "pulse.cpp"]
 
 
@@ -61,7 +61,8 @@ def build(verbose: bool = False, arch: str = "gfx950") -> str:
                 print(r.stdout, r.stderr, file=sys.stderr)
     objs = [os.path.join(OBJ, s + ".o") for s in HIP_SOURCES + HOST_SOURCES]
     tmp = OUT + ".tmp"
-    _run([hipcc, "-shared", "-fPIC", f"--offload-arch={arch}", *objs, "-o", tmp])
+    _run([hipcc, "-shared", "-fPIC", f"--offload-arch={arch}", *objs, "-L/opt/rocm/lib",
+          "-lrocblas", "-Wl,-rpath,/opt/rocm/lib", "-o", tmp])
     os.replace(tmp, OUT)
     return OUT
 

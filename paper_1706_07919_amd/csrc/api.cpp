@@ -261,6 +261,7 @@ extern "C" void bem_ctx_destroy(bem_ctx* ctx) {
   if (ctx->pack) (void)hipFree(ctx->pack);
   if (ctx->midx) (void)hipFree(ctx->midx);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  blas_destroy(ctx);
   resolve_stats(ctx);
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
   delete ctx;
@@ -1269,3 +1270,119 @@ extern "C" bem_status bem_field_eval_quadratic(bem_ctx* ctx, const bem_quad_surf
   return launch_quad_field(ctx, s, qp, n_k, k, n_rhs, phi, psi, base, base + interp, m, xp, i0,
                            inside, U);
 }
+
+// ============================================================ interior-point rows
+// Least-squares solve of the surface rows and the interior-point rows through
+// the float64 normal equations (see chief.hip), chunks of wavenumbers sized to
+// the workspace.
+extern "C" bem_status bem_solve_chief(bem_ctx* ctx, const bem_surface* s, int32_t n_k,
+                                      const double* k, int32_t n_rhs, const void* y, int32_t n_c,
+                                      const double* xc, void* x_out, bem_solve_info* info) {
+  if (!ctx) return BEM_EINVAL;
+  if (!s || s->n <= 0 || !s->x || !s->nrm || !s->w || !s->bc || n_rhs <= 0 || n_rhs > 65535 ||
+      !y || !x_out || n_c <= 0 || n_c > 65535 || !xc)
+    return fail(ctx, BEM_EINVAL, "bem_solve_chief: bad argument");
+  if (s->n > 12288) return fail(ctx, BEM_EUNSUPPORTED, "bem_solve_chief: n = %d > 12288", s->n);
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
+  bem_status st;
+  if ((st = check_k(ctx, n_k, k)) != BEM_OK) return st;
+  const int n = s->n, nr = n_rhs, naug = n + nr;
+  const int64_t ld = round_up(naug, 16);
+  const int64_t sa = (int64_t)n * ld, sc = (int64_t)n_c * ld, sm = (int64_t)naug * ld;
+  const int rows = n + n_c;
+  auto carve = [&](void* base, int kc, char** p_out, size_t* used) {
+    char* p = (char*)base;
+    auto take = [&](size_t bytes) {
+      char* o = p;
+      p += (bytes + 255) / 256 * 256;
+      return o;
+    };
+    const size_t v = (size_t)kc * nr;
+    p_out[0] = take((size_t)kc * sa * 16);   // [A | b]
+    p_out[1] = take((size_t)kc * sc * 16);   // [C | d]
+    p_out[2] = take((size_t)kc * sm * 16);   // normal equations, then their factors
+    p_out[3] = take((size_t)kc * n * 4);     // piv
+    p_out[4] = take((size_t)kc * n * 4);     // perm
+    p_out[5] = take((size_t)kc * 4);         // info
+    p_out[6] = take(v * n * 16);             // b
+    p_out[7] = take(v * n * 16);             // right-hand sides of the normal equations
+    p_out[8] = take(v * n * 16);             // x
+    p_out[9] = take(v * rows * 8);           // squared residual per row
+    p_out[10] = take(v * rows * 8);          // squared right-hand side per row
+    p_out[11] = take(v * n * 16);            // zeros
+    if (used) *used = (size_t)(p - (char*)base);
+  };
+  size_t free_b = 0, total_b = 0;
+  BEM_HIP_TRY(ctx, hipMemGetInfo(&free_b, &total_b));
+  const size_t limit = ctx->ws_limit ? ctx->ws_limit : (size_t)(0.75 * (double)(free_b + ctx->ws_size));
+  char* P[12];
+  auto bytes = [&](int kc) {
+    size_t used = 0;
+    carve(nullptr, kc, P, &used);
+    return used + 256;
+  };
+  int kc = n_k;
+  while (kc > 1 && (bytes(kc) > limit || (int64_t)kc * nr > 65535)) kc = (kc + 1) / 2;
+  void* ws = nullptr;
+  if ((st = workspace(ctx, bytes(kc), &ws)) != BEM_OK) return st;
+  std::vector<double> hrs, hr0;
+  std::vector<int32_t> hinfo;
+  for (int k0 = 0; k0 < n_k; k0 += kc) {
+    const int cur = std::min(kc, n_k - k0);
+    const int nv = cur * nr;
+    carve(ws, cur, P, nullptr);
+    const double2* yk = (const double2*)y + (size_t)k0 * nr * n;
+    if ((st = launch_assemble(ctx, s, cur, k + k0, nr, yk, BEM_C128, P[0], ld, sa, P[6], nullptr)) != BEM_OK)
+      return st;
+    if ((st = launch_aug_b(ctx, n, cur, nr, P[6], P[0], ld, sa)) != BEM_OK) return st;
+    if ((st = launch_interior_rows(ctx, s, cur, k + k0, nr, yk, n_c, xc, P[1], ld, sc)) != BEM_OK)
+      return st;
+    if ((st = gram_c128(ctx, naug, n, P[0], ld, sa, P[2], ld, sm, cur, false)) != BEM_OK) return st;
+    if ((st = gram_c128(ctx, naug, n_c, P[1], ld, sc, P[2], ld, sm, cur, true)) != BEM_OK) return st;
+    if ((st = launch_extract_rhs(ctx, n, cur, nr, P[2], ld, sm, P[7])) != BEM_OK) return st;
+    std::vector<LuMatrixSet> sets(1, LuMatrixSet{P[2], (int32_t*)P[3], (int32_t*)P[5], ld, sm, n, cur});
+    LuPlan plan;
+    plan.nb = lu_plan_nb(ctx, BEM_C128, 0, n);
+    if ((st = lu_factor_groups(ctx, BEM_C128, sets, plan, 0)) != BEM_OK) return st;
+    if ((st = lu_perm(ctx, n, cur, (const int32_t*)P[3], (int32_t*)P[4])) != BEM_OK) return st;
+    if ((st = lu_solve_perm(ctx, BEM_C128, n, ld, sm, cur, P[2], (const int32_t*)P[4], nr, P[7],
+                            P[8], (int64_t)nr * n)) != BEM_OK)
+      return st;
+    // the stacked system's residual and right-hand side per row
+    if ((st = fill_zero(ctx, P[11], (size_t)nv * n * 16)) != BEM_OK) return st;
+    if ((st = launch_aug_resid(ctx, n, cur, nr, P[0], ld, sa, n, P[8], (double*)P[9], rows, 0)) != BEM_OK ||
+        (st = launch_aug_resid(ctx, n, cur, nr, P[1], ld, sc, n_c, P[8], (double*)P[9], rows, n)) != BEM_OK ||
+        (st = launch_aug_resid(ctx, n, cur, nr, P[0], ld, sa, n, P[11], (double*)P[10], rows, 0)) != BEM_OK ||
+        (st = launch_aug_resid(ctx, n, cur, nr, P[1], ld, sc, n_c, P[11], (double*)P[10], rows, n)) != BEM_OK)
+      return st;
+    BEM_HIP_TRY(ctx, hipMemcpyAsync((double2*)x_out + (size_t)k0 * nr * n, P[8], (size_t)nv * n * 16,
+                                    hipMemcpyDeviceToDevice, ctx->stream));
+    hrs.resize((size_t)nv * rows);
+    hr0.resize((size_t)nv * rows);
+    hinfo.resize(cur);
+    BEM_HIP_TRY(ctx, hipMemcpyAsync(hrs.data(), P[9], 8 * hrs.size(), hipMemcpyDeviceToHost, ctx->stream));
+    BEM_HIP_TRY(ctx, hipMemcpyAsync(hr0.data(), P[10], 8 * hr0.size(), hipMemcpyDeviceToHost, ctx->stream));
+    BEM_HIP_TRY(ctx, hipMemcpyAsync(hinfo.data(), P[5], 4 * (size_t)cur, hipMemcpyDeviceToHost, ctx->stream));
+    BEM_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (int q = 0; q < cur; ++q)
+      if (hinfo[q] != 0)
+        return fail(ctx, BEM_ESINGULAR, "bem_solve_chief: zero pivot in the normal equations of k[%d]", k0 + q);
+    if (info)
+      for (int v = 0; v < nv; ++v) {
+        double a = 0.0, b0 = 0.0;
+        for (int r = 0; r < rows; ++r) {
+          a += hrs[(size_t)v * rows + r];
+          b0 += hr0[(size_t)v * rows + r];
+        }
+        bem_solve_info& I = info[(size_t)k0 * nr + v];
+        I.iters = 0;
+        I.used_fp64 = 0;
+        I.singular = 0;
+        I.converged = 1;
+        I.rel_resid = b0 > 0 ? std::sqrt(a / b0) : 0.0;
+        I.rel_step = 0.0;
+      }
+  }
+  return BEM_OK;
+}
+

@@ -58,6 +58,8 @@ struct bem_ctx {
   // device (taken once, when the context is created) and its size
   void* field_scratch = nullptr;
   size_t field_scratch_bytes = 0;
+  // rocBLAS handle of the interior-point least-squares solve (created on first use)
+  void* blas = nullptr;
 };
 
 namespace bem {
@@ -156,6 +158,21 @@ bem_status launch_ir_update(bem_ctx*, int nvec, int n, const void* d32, const do
 bem_status launch_norm2(bem_ctx*, int nvec, int n, const void* v, double* out);
 bem_status launch_c128_to_c64(bem_ctx*, int64_t count, const void* in, void* out);
 bem_status fill_zero(bem_ctx*, void* p, size_t bytes);
+
+// ------------------------------------------------------------------ interior-point rows
+bem_status launch_aug_b(bem_ctx*, int n, int n_k, int n_rhs, const void* b, void* A, int64_t ld,
+                        int64_t stride);
+bem_status launch_interior_rows(bem_ctx*, const bem_surface*, int n_k, const double* k, int n_rhs,
+                                const void* y, int n_c, const double* xc, void* C, int64_t ld,
+                                int64_t stride);
+bem_status gram_c128(bem_ctx*, int len, int m_cols, const void* R, int64_t ld, int64_t r_stride,
+                     void* M, int64_t ldm, int64_t m_stride, int batch, bool accumulate);
+bem_status launch_extract_rhs(bem_ctx*, int n, int n_k, int n_rhs, const void* M, int64_t ld,
+                              int64_t stride, void* r);
+bem_status launch_aug_resid(bem_ctx*, int n, int n_k, int n_rhs, const void* R, int64_t ld,
+                            int64_t stride, int rows, const void* x, double* rs, int rs_rows,
+                            int rs_off);
+void blas_destroy(bem_ctx*);
 bem_status launch_copy_active(bem_ctx*, int nvec, int n, const uint8_t* active, const void* src,
                               void* dst);
 

@@ -34,7 +34,7 @@ EXPORTED = [
     "bem_residual_check", "bem_refine_batched", "bem_mlp_features", "bem_mlp_dense_fwd", "bem_mlp_dense_bwd",
     "bem_mlp_mse_grad", "bem_mlp_adam", "bem_mlp_pack", "bem_mlp_unpack",
     "bem_mesh_quadratic_counts", "bem_mesh_quadratic", "bem_assemble_quadratic",
-    "bem_solve_quadratic", "bem_field_eval_quadratic",
+    "bem_solve_quadratic", "bem_field_eval_quadratic", "bem_solve_chief",
 ]
 
 
@@ -133,6 +133,8 @@ def load(path: str = LIB_PATH):
                                  C.POINTER(bem_solve_opts), vp, C.POINTER(bem_solve_info)], C.c_int),
         "bem_field_eval_quadratic": ([vp, C.POINTER(bem_quad_surface), i32, vp, i32, vp, vp, i32,
                                       vp, vp, vp, vp], C.c_int),
+        "bem_solve_chief": ([vp, C.POINTER(bem_surface), i32, vp, i32, vp, i32, vp, vp,
+                             C.POINTER(bem_solve_info)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -281,6 +283,14 @@ def bem_solve_quadratic(ctx, qsurf, n_k, k, n_rhs, y, opts, x_out):
     info = (bem_solve_info * (n_k * n_rhs))()
     _check(load().bem_solve_quadratic(ctx.handle, C.byref(qsurf), n_k, _ptr(k), n_rhs, _ptr(y),
                                       C.byref(opts), _ptr(x_out), info), ctx)
+    return info
+
+
+def bem_solve_chief(ctx, surf, n_k, k, n_rhs, y, n_c, xc, x_out):
+    """Least-squares solve with n_c interior-point rows; returns the info array."""
+    info = (bem_solve_info * (n_k * n_rhs))()
+    _check(load().bem_solve_chief(ctx.handle, C.byref(surf), n_k, _ptr(k), n_rhs, _ptr(y), n_c,
+                                  _ptr(xc), _ptr(x_out), info), ctx)
     return info
 
 
