@@ -90,7 +90,7 @@ def main():
                     help="1: time the space-time reconstruction (2048 solves, 1024^2 points, "
                          "4 pulses, T = 4096) after the headline")
     ap.add_argument("--workload", choices=["spheres", "surrogate", "uneven", "spacetime",
-                                           "truncation", "bowl"],
+                                           "truncation", "bowl", "chief"],
                     default="spheres",
                     help="spheres: the headline sweep; surrogate: the learned-fill gain "
                          "test (256 training / 4096 predicted wavenumbers, N = 5124); "
@@ -98,7 +98,8 @@ def main():
                          "spacetime: 2048 solves, field on a 1024^2 grid, 4 pulses; "
                          "truncation: the paper's soft sphere and pulse rebuilt from the "
                          "5/10/20 frequencies of largest amplitude vs all 63; "
-                         "bowl: the hard acoustic bowl's focusing of a 6-cycle pulse")
+                         "bowl: the hard acoustic bowl's focusing of a 6-cycle pulse; "
+                         "chief: interior-point rows against fictitious resonances")
     ap.add_argument("--tr-level", type=int, default=5,
                     help="icosphere level of the sphere for --workload truncation")
     ap.add_argument("--tr-grid", type=int, default=256,
@@ -110,6 +111,11 @@ def main():
     ap.add_argument("--uneven-steps", type=int, default=1,
                     help="timed passes of --workload uneven")
     ap.add_argument("--nb", type=int, default=0, help="LU block width (0 = library default)")
+    ap.add_argument("--gemm-narrow-max", type=int, default=0,
+                    help="set the plan of the size class by hand: 128 x 64 GEMM tiles up to this "
+                         "many columns (0: leave the plan alone)")
+    ap.add_argument("--gemm-persistent", type=int, default=0,
+                    help="with --gemm-narrow-max: 1 = persistent GEMM launches")
     ap.add_argument("--autotune", type=int, default=0,
                     help="measure the LU block width on this many matrices before the run")
     ap.add_argument("--sur-epochs", type=int, default=300)
@@ -141,6 +147,9 @@ def main():
         return
     if args.workload == "bowl":
         run_bowl(args)
+        return
+    if args.workload == "chief":
+        run_chief(args)
         return
 
     from paper_1706_07919_amd import DeviceSurface, native
@@ -181,11 +190,17 @@ def main():
     opts = native.bem_solve_opts_default()
     opts.mode = modes[args.mode]
     opts.nb = args.nb
-    tuned = None
+    tuned = tuned_plan = tune_log = None
+    if args.gemm_narrow_max > 0:
+        gk = {"b3": native.BEM_GEMM_BF16X3, "4m": native.BEM_GEMM_4M, "3m": native.BEM_GEMM_3M}[args.mode]
+        native.bem_lu_set_plan(ctx, native.BEM_C64, n, gk, args.nb or 512, args.gemm_narrow_max,
+                               args.gemm_persistent)
     if args.autotune > 0:
         gk = {"b3": native.BEM_GEMM_BF16X3, "4m": native.BEM_GEMM_4M, "3m": native.BEM_GEMM_3M}[args.mode]
         tuned = native.bem_autotune_lu(ctx, native.BEM_C64, n, args.autotune, gk)
-        print(f"autotuned block width {tuned[0]} ({tuned[1]:.1f} ms for {args.autotune} matrices)",
+        tune_log = native.bem_autotune_lu_results(ctx)
+        tuned_plan = native.bem_lu_tuned_plan(ctx, native.BEM_C64, n, gk)
+        print(f"autotuned plan {tuned_plan} ({tuned[1]:.1f} ms for {args.autotune} matrices)",
               file=sys.stderr, flush=True)
     infos = []
 
@@ -348,7 +363,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": n, "n_k": n_k, "field_points": m, "T": T,
                    "mode": {"b3": "FP32_IR_B3", "4m": "FP32_IR_4M", "3m": "FP32_IR_3M"}[args.mode],
-                   "nb": opts.nb, "autotuned_nb": tuned[0] if tuned else None},
+                   "nb": opts.nb, "autotuned_nb": tuned[0] if tuned else None,
+                   "gemm_plan_set": ({"narrow_max": args.gemm_narrow_max,
+                                      "persistent": args.gemm_persistent}
+                                     if args.gemm_narrow_max > 0 else None),
+                   "autotuned_plan": ({"nb": tuned_plan[0], "narrow_max": tuned_plan[1],
+                                       "persistent": tuned_plan[2]} if tuned else None)},
+        "autotune_log": ([{"nb": r[0], "narrow_max": r[1], "persistent": r[2], "ms": r[3]}
+                          for r in tune_log] if tuned else None),
         "field_pt_freq_per_s": st["value"] if st else field_rate,
         "field_pt_freq_per_s_note": ("space-time reconstruction at 1024^2 points x 2048 frequencies "
                                      "(the step's own 4096-point field is field_pt_freq_per_s_step)"
@@ -567,6 +589,72 @@ def run_truncation(args):
     print(json.dumps(out))
 
 
+def run_chief(args):
+    """The remedy for fictitious resonances on a hard unit sphere (level 4,
+    2562 nodes) under the plane wave: the six interior eigenvalues below 8
+    and six wavenumbers between them, 16 interior points.  Times the plain
+    solve (FP32 3M LU refined to FP64) and the least-squares solve with the
+    interior rows (FP64 normal equations) and reports how far the plain
+    solution moves when the interior rows are added: tens of per cent at the
+    eigenvalues (the spurious interior mode), the discretisation error between
+    them."""
+    import torch
+
+    from paper_1706_07919_amd import DeviceSurface, native
+    from workloads import Body, HARD, SPHERE_RESONANCES, interior_points
+
+    body = Body((0.0, 0.0, 0.0), 1.0, 1.0, 4, HARD)
+    ds = DeviceSurface.from_bodies([body])
+    n = ds.n
+    res = np.array(SPHERE_RESONANCES)
+    off = np.array([2.5, 3.8, 5.1, 6.0, 6.6, 7.4])
+    k = np.concatenate([res, off])
+    n_k = len(k)
+    xc = interior_points([body], 16, seed=3)
+    dev = torch.device("cuda:0")
+    ctx = native.Context(0)
+    kd = torch.as_tensor(k).to(dev)
+    xcd = torch.as_tensor(xc).to(dev)
+    y = torch.empty((n_k, 1, n), dtype=torch.complex128, device=dev)
+    native.bem_incident(ctx, ds.struct, n_k, kd, (0.0, 0.0, 1.0), y)
+    xp = torch.zeros_like(y)
+    xl = torch.zeros_like(y)
+    opts = native.bem_solve_opts_default()
+    opts.mode = native.BEM_FP32_IR_3M
+
+    def plain():
+        xp.zero_()
+        return native.bem_solve_batched(ctx, [(ds.struct, n_k, kd, 1, y)], opts, [xp])
+
+    def remedied():
+        return native.bem_solve_chief(ctx, ds.struct, n_k, kd, 1, y, len(xc), xcd, xl)
+
+    plain()
+    remedied()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info_p = plain()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    info_c = remedied()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    d = (torch.linalg.vector_norm(xp - xl, dim=(1, 2)) / torch.linalg.vector_norm(xl, dim=(1, 2))).cpu().numpy()
+    out = {"metric": "interior-point least-squares solves/sec at N=2562 (hard sphere at and between "
+                     "interior eigenvalues)",
+           "value": n_k / (t2 - t1), "unit": "freq-solves/s", "higher_is_better": True,
+           "data": "synthetic", "dtype": "c128 normal equations (rocBLAS zgemm) + f64-MFMA LU",
+           "config": {"workload": "hard unit sphere, level 4", "n": n, "n_k": n_k,
+                      "interior_points": len(xc), "k_resonant": res.tolist(), "k_between": off.tolist()},
+           "plain_solves_per_s": n_k / (t1 - t0),
+           "plain_vs_remedied_rel_diff_at_eigenvalues": d[:len(res)].tolist(),
+           "plain_vs_remedied_rel_diff_between": d[len(res):].tolist(),
+           "plain_ir_iters": [info_p[q].iters for q in range(n_k)],
+           "plain_fallbacks": sum(info_p[q].used_fp64 for q in range(n_k)),
+           "least_squares_rel_resid": [info_c[q].rel_resid for q in range(n_k)]}
+    print(json.dumps(out))
+
+
 def run_bowl(args):
     """The hard axisymmetric bowl of Sec. IV C (Eq. dish; axis turned by
     0.15 pi from the propagation direction +z; 48 x 96 rings, 4514 nodes)
@@ -673,8 +761,16 @@ def run_uneven(args):
         probs.append((ds.struct, nk, kd, 1, y))
         xs.append(torch.zeros((nk, 1, ds.n), dtype=torch.complex128, device=dev))
     mode = {"b3": native.BEM_FP32_IR_B3, "4m": native.BEM_FP32_IR_4M, "3m": native.BEM_FP32_IR_3M}[args.mode]
+    gk = {"b3": native.BEM_GEMM_BF16X3, "4m": native.BEM_GEMM_4M, "3m": native.BEM_GEMM_3M}[args.mode]
     opts = native.bem_solve_opts_default()
     opts.mode = mode
+    plans = None
+    if args.autotune > 0:
+        # the batch is planned by its largest size class
+        nmax = max(ds.n for ds in surfs)
+        native.bem_autotune_lu(ctx, native.BEM_C64, nmax, args.autotune, gk)
+        plans = {"n": nmax, "kept": native.bem_lu_tuned_plan(ctx, native.BEM_C64, nmax, gk),
+                 "log": native.bem_autotune_lu_results(ctx)}
     # untimed pass on the first 16 wavenumbers of every body (first launches,
     # workspace)
     small = [(s_, 16, k_[:16], 1, y_[:16]) for (s_, _, k_, _, y_) in probs]
@@ -697,6 +793,7 @@ def run_uneven(args):
            "data": "synthetic", "dtype": "c64 LU (" + args.mode + " on f32 MFMA) + f64 residual refinement",
            "config": {"workload": w.name, "sizes": sizes, "k_per_body": nk,
                       "mode": args.mode},
+           "autotune": plans,
            "lu_algorithmic_tflops": flops / dt / 1e12,
            "ir_iters_max": max(info[q].iters for q in range(len(info))),
            "ir_fallbacks": sum(info[q].used_fp64 for q in range(len(info))),

@@ -300,18 +300,39 @@ bem_status bem_getrs_batched(bem_ctx* ctx, bem_prec prec, int32_t n, int32_t ld,
                              int32_t batch, const void* LU, const int32_t* piv, int32_t n_rhs,
                              const void* B, void* X, int64_t bstride);
 
-/* Block width of the factorisation measured on this device: factors `batch`
+/* Plan of the factorisation measured on this device: factors `batch`
  * pseudo-random n x n matrices (diagonally dominant, deterministic) of the
- * given precision and GEMM form once per candidate width (a 0-terminated list
- * [host], or NULL for 256, 384, 512, 768, 1024), best of two runs each, and
- * keeps the fastest in the context for every later factorisation of that
- * precision, GEMM form and size class (n rounded up to 512) whose caller
- * passes nb = 0.  best_nb, best_ms [host] may be NULL.  Allocates
- * batch * n * ld elements for the duration of the call (BEM_ENOMEM if they do
- * not fit); synchronises the stream. */
+ * given precision and GEMM form once per candidate block width (a
+ * 0-terminated list [host], or NULL for 256, 384, 512, 768, 1024) and, for
+ * the float32 MFMA forms (BEM_GEMM_4M, BEM_GEMM_3M), per GEMM shape: 128 x 64
+ * tiles for updates of up to 64 or up to 128 columns (128 x 128 above), and
+ * one workgroup per tile or persistent workgroups drawing tiles from per-XCD
+ * counters; best of two runs each.  The fastest plan is kept in the context
+ * for every later factorisation of that precision, GEMM form and size class
+ * (n rounded up to 512) whose caller passes nb = 0 (the GEMM shape applies
+ * whatever nb the caller passes).  best_nb, best_ms [host] may be NULL.
+ * Allocates batch * n * ld elements for the duration of the call (BEM_ENOMEM
+ * if they do not fit); synchronises the stream. */
 bem_status bem_autotune_lu(bem_ctx* ctx, bem_prec prec, int32_t n, int32_t batch,
                            int32_t gemm_kind, const int32_t* candidates, int32_t* best_nb,
                            double* best_ms);
+
+/* Every plan tried by the context's last bem_autotune_lu call, in the order
+ * tried: block width, GEMM tile threshold (columns), persistent launches
+ * (0/1) and time (ms); the first max entries are written to the [host]
+ * arrays (each may be NULL).  Returns the number of plans tried. */
+int32_t bem_autotune_lu_results(bem_ctx* ctx, int32_t max, int32_t* nb, int32_t* narrow_max,
+                                int32_t* persistent, double* ms);
+/* Sets the plan of a size class by hand (as bem_autotune_lu would keep it):
+ * block width nb > 0, 128 x 64 GEMM tiles up to narrow_max columns (64 ..
+ * 1024), persistent GEMM launches 0/1.  Drops the context's captured
+ * factorisations. */
+bem_status bem_lu_set_plan(bem_ctx* ctx, bem_prec prec, int32_t n, int32_t gemm_kind, int32_t nb,
+                           int32_t narrow_max, int32_t persistent);
+/* The plan bem_autotune_lu (or bem_lu_set_plan) kept for (prec, gemm_kind,
+ * size class of n); EINVAL if none.  Outputs [host] may be NULL. */
+bem_status bem_lu_tuned_plan(bem_ctx* ctx, bem_prec prec, int32_t n, int32_t gemm_kind,
+                             int32_t* nb, int32_t* narrow_max, int32_t* persistent);
 
 /* Iterative refinement of given unknowns with stored float32 factors of
  * other (nearby) wavenumbers: x <- x + LU_f^{-1} (b - A(k) x), residual in

@@ -247,6 +247,14 @@ extern "C" bem_status bem_ctx_create(int device, void* hip_stream, bem_ctx** out
     delete c;
     return BEM_EHIP;
   }
+  // counters of the persistent GEMM launches, zero before the first launch
+  if (hipMalloc(&c->gemm_queue, 64) != hipSuccess || hipMemset(c->gemm_queue, 0, 64) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    (void)hipGetLastError();
+    if (c->gemm_queue) (void)hipFree(c->gemm_queue);
+    delete c;
+    return BEM_EHIP;
+  }
   *out = c;
   return BEM_OK;
 }
@@ -260,6 +268,7 @@ extern "C" void bem_ctx_destroy(bem_ctx* ctx) {
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->pack) (void)hipFree(ctx->pack);
   if (ctx->midx) (void)hipFree(ctx->midx);
+  if (ctx->gemm_queue) (void)hipFree(ctx->gemm_queue);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   blas_destroy(ctx);
   resolve_stats(ctx);
@@ -422,8 +431,7 @@ extern "C" bem_status bem_getrf_batched(bem_ctx* ctx, bem_prec prec, int32_t n, 
       gemm_kind > BEM_GEMM_BF16X3_UNPACKED)
     return fail(ctx, BEM_EINVAL, "bem_getrf_batched: bad argument");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
-  LuPlan plan;
-  plan.nb = nb > 0 ? nb : lu_plan_nb(ctx, prec, prec == BEM_C64 ? gemm_kind : 0, n);
+  const LuPlan plan = lu_plan_for(ctx, prec, prec == BEM_C64 ? gemm_kind : 0, n, nb);
   return lu_factor(ctx, prec, n, ld, stride, batch, A, piv, info, plan, gemm_kind);
 }
 
@@ -440,6 +448,44 @@ extern "C" bem_status bem_autotune_lu(bem_ctx* ctx, bem_prec prec, int32_t n, in
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
   return lu_autotune(ctx, prec, n, batch, prec == BEM_C64 ? gemm_kind : 0, candidates, best_nb,
                      best_ms);
+}
+
+extern "C" int32_t bem_autotune_lu_results(bem_ctx* ctx, int32_t max, int32_t* nb,
+                                           int32_t* narrow_max, int32_t* persistent, double* ms) {
+  if (!ctx) return 0;
+  const int cnt = (int)ctx->tune_log.size();
+  for (int i = 0; i < cnt && i < max; ++i) {
+    if (nb) nb[i] = ctx->tune_log[i].first.nb;
+    if (narrow_max) narrow_max[i] = ctx->tune_log[i].first.narrow_max;
+    if (persistent) persistent[i] = ctx->tune_log[i].first.persistent;
+    if (ms) ms[i] = ctx->tune_log[i].second;
+  }
+  return cnt;
+}
+
+extern "C" bem_status bem_lu_set_plan(bem_ctx* ctx, bem_prec prec, int32_t n, int32_t gemm_kind,
+                                      int32_t nb, int32_t narrow_max, int32_t persistent) {
+  if (!ctx) return BEM_EINVAL;
+  if (n <= 0 || nb <= 0 || (prec != BEM_C64 && prec != BEM_C128) || gemm_kind < BEM_GEMM_4M ||
+      gemm_kind > BEM_GEMM_BF16X3_UNPACKED || narrow_max < 64 || narrow_max > 1024 ||
+      (persistent != 0 && persistent != 1))
+    return fail(ctx, BEM_EINVAL, "bem_lu_set_plan: bad argument");
+  drop_graphs(ctx);
+  ctx->tuned[{(int)prec * 16 + gemm_kind, (n + 511) / 512 * 512}] =
+      bem_ctx::TunedPlan{nb, narrow_max, persistent};
+  return BEM_OK;
+}
+
+extern "C" bem_status bem_lu_tuned_plan(bem_ctx* ctx, bem_prec prec, int32_t n, int32_t gemm_kind,
+                                        int32_t* nb, int32_t* narrow_max, int32_t* persistent) {
+  if (!ctx) return BEM_EINVAL;
+  const auto it = ctx->tuned.find({(int)prec * 16 + gemm_kind, (n + 511) / 512 * 512});
+  if (it == ctx->tuned.end())
+    return fail(ctx, BEM_EINVAL, "bem_lu_tuned_plan: no measured plan for this size class");
+  if (nb) *nb = it->second.nb;
+  if (narrow_max) *narrow_max = it->second.narrow_max;
+  if (persistent) *persistent = it->second.persistent;
+  return BEM_OK;
 }
 
 extern "C" bem_status bem_getrs_batched(bem_ctx* ctx, bem_prec prec, int32_t n, int32_t ld,
@@ -727,7 +773,7 @@ extern "C" bem_status bem_solve_batched(bem_ctx* ctx, const bem_problem* probs, 
   {
     const int gk0 = o.mode == BEM_FP32_IR_3M ? BEM_GEMM_3M
                     : o.mode == BEM_FP32_IR_B3 ? BEM_GEMM_BF16X3 : BEM_GEMM_4M;
-    plan.nb = o.nb > 0 ? o.nb : lu_plan_nb(ctx, prec, fp64 ? 0 : gk0, nmax);
+    plan = lu_plan_for(ctx, prec, fp64 ? 0 : gk0, nmax, o.nb);
   }
   std::vector<SolveRun> runs;
   for (int p = 0; p < n_probs; ++p) {
@@ -1174,7 +1220,7 @@ extern "C" bem_status bem_solve_quadratic(bem_ctx* ctx, const bem_quad_surface* 
           return st;
       } else {
         if ((st = launch_c128_to_c64(ctx, (int64_t)cur * stride, c.A64, c.LU)) != BEM_OK) return st;
-        plan.nb = o.nb > 0 ? o.nb : lu_plan_nb(ctx, BEM_C64, gk, n);
+        plan = lu_plan_for(ctx, BEM_C64, gk, n, o.nb);
         if ((st = lu_factor_groups(ctx, BEM_C64, sets, plan, gk)) != BEM_OK) return st;
         if ((st = lu_perm(ctx, n, cur, c.piv, c.perm)) != BEM_OK) return st;
         if ((st = fill_zero(ctx, c.x, (size_t)nv * n * 16)) != BEM_OK) return st;

@@ -32,9 +32,15 @@ struct bem_ctx {
   // small pinned host staging buffer for norms / flags
   void* pinned = nullptr;
   size_t pinned_size = 0;
-  // measured block widths of the factorisation keyed by
-  // (precision * 16 + GEMM form, n rounded up to 512)
-  std::map<std::pair<int, int>, int> tuned_nb;
+  // measured plans of the factorisation keyed by (precision * 16 + GEMM form,
+  // n rounded up to 512): block width, the column count up to which the
+  // 128 x 64 GEMM tile is used, persistent GEMM launches
+  struct TunedPlan {
+    int nb, narrow_max, persistent;
+  };
+  std::map<std::pair<int, int>, TunedPlan> tuned;
+  // every candidate of the last bem_autotune_lu call and its time (ms)
+  std::vector<std::pair<TunedPlan, double>> tune_log;
   int num_cus = 256;
   bool profiling = false;
   std::string prof_filter;   // ",name,name," of the counted kernels, or empty = all
@@ -60,6 +66,9 @@ struct bem_ctx {
   size_t field_scratch_bytes = 0;
   // rocBLAS handle of the interior-point least-squares solve (created on first use)
   void* blas = nullptr;
+  // tile counters of the persistent GEMM launches (8 ranges x {next, done},
+  // zeroed at creation; every launch leaves them zero)
+  void* gemm_queue = nullptr;
 };
 
 namespace bem {
@@ -121,6 +130,11 @@ enum { kGemm4M = 0, kGemm3M = 1, kGemmBf16x3 = 2, kGemmBf16x3Unpacked = 3 };
 struct LuPlan {
   int nb = 0;          // top-level panel width (0 = recursive halving)
   int base = 8;        // width of the register-held base panel
+  // float32 MFMA updates: the 128 x 64 tile for updates of at most this many
+  // columns (128 x 128 above), and the launch form (0: a workgroup per tile,
+  // 1: persistent workgroups drawing tiles from a per-XCD counter)
+  int gemm_narrow_max = 64;
+  int gemm_persistent = 0;
 };
 bem_status lu_factor(bem_ctx*, bem_prec, int n, int64_t ld, int64_t stride, int batch, void* A,
                      int32_t* piv, int32_t* info, const LuPlan& plan, int gemm_kind);
@@ -147,6 +161,10 @@ int lu_default_nb(bem_prec prec, int n);
 // block width for a factorisation: the measured one of this context when
 // bem_autotune_lu has run for the size class, else the default
 int lu_plan_nb(bem_ctx* ctx, bem_prec prec, int gemm_kind, int n);
+// a factorisation's plan: block width nb (> 0) or the measured / default one,
+// and the measured GEMM tile threshold and launch form when the context has
+// them for this size class
+LuPlan lu_plan_for(bem_ctx* ctx, bem_prec prec, int gemm_kind, int n, int nb);
 bem_status lu_autotune(bem_ctx* ctx, bem_prec prec, int n, int batch, int gemm_kind,
                        const int32_t* candidates, int32_t* best_nb, double* best_ms);
 

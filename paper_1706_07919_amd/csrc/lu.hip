@@ -716,6 +716,11 @@ __global__ __launch_bounds__(256) void gemm_c32_3m_kernel(LuGroups G, int rowC, 
 //   a matrix, tiles are walked in strips of GL_GM tile rows, column by column.
 // * Tile 128 x BN (BN = 64 WJ) per workgroup of 4 waves (2 x 2), each wave
 //   64 x 32 WJ as 2 x WJ MFMA blocks.
+// * Launch forms: one workgroup per tile, or (queue != NULL) a persistent
+//   grid of the resident workgroups in which the workgroups of range x take
+//   its tiles in turn from range x's counter in `queue` (an atomic ticket per
+//   tile); the last workgroup of a range to find it empty resets the range's
+//   counters for the next launch.
 constexpr int GL_BM = 128, GL_BK = 16, GL_GM = 8;
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
@@ -735,18 +740,15 @@ __device__ inline void lds_dma16(const GLOBAL u32x4* src, unsigned lds_wave) {
                :: "v"(src), "s"(lds_wave) : "memory", "m0");
 }
 
+// One tile (work item `item` < the list's total) of the update.
 template <bool M3, int WJ>
-__global__ __launch_bounds__(256, 2) void gemm_c32_lds_kernel(LuGroups G, GemmList W, int rowC,
-                                                              int colC, int colA, int rowB,
-                                                              int rowEnd, int colEnd, int K) {
+__device__ __forceinline__ void gemm_lds_tile(const LuGroups& G, const GemmList& W, int64_t item,
+                                              int rowC, int colC, int colA, int rowB, int rowEnd,
+                                              int colEnd, int K, u32x4 (*As)[GL_BM * GL_BK / 2],
+                                              u32x4 (*Bs)[GL_BK * 64 * WJ / 2]) {
   constexpr int BN = 64 * WJ;
   constexpr int BW = GL_BK * BN / 2;            // 16-byte words of a B stage
-  __shared__ u32x4 As[2][GL_BM * GL_BK / 2], Bs[2][BW];
   // ---- work item -> (group, matrix, tile)
-  const int64_t total = W.start[G.ng];
-  const int64_t per = (total + 7) >> 3;
-  const int64_t item = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  if (item >= total) return;
   int gsel = 0;
 #pragma unroll
   for (int i = 1; i < kMaxGroups; ++i)
@@ -976,6 +978,42 @@ __global__ __launch_bounds__(256, 2) void gemm_c32_lds_kernel(LuGroups G, GemmLi
         if (row < M) C[row * ldi + col] = make_float2(c[v].x - dr, c[v].y - di);
       }
     }
+}
+
+template <bool M3, int WJ, bool PERSIST>
+__global__ __launch_bounds__(256, 2) void gemm_c32_lds_kernel(LuGroups G, GemmList W, int rowC,
+                                                              int colC, int colA, int rowB,
+                                                              int rowEnd, int colEnd, int K,
+                                                              uint32_t* queue) {
+  __shared__ u32x4 As[2][GL_BM * GL_BK / 2], Bs[2][GL_BK * 64 * WJ / 2];
+  const int64_t total = W.start[G.ng];
+  const int64_t per = (total + 7) >> 3;
+  const int x = blockIdx.x & 7;
+  if constexpr (!PERSIST) {
+    const int64_t item = (int64_t)x * per + (blockIdx.x >> 3);
+    if (item < total)
+      gemm_lds_tile<M3, WJ>(G, W, item, rowC, colC, colA, rowB, rowEnd, colEnd, K, As, Bs);
+    return;
+  }
+  __shared__ uint32_t ticket;
+  const int64_t lo = (int64_t)x * per, hi = min(total, lo + per);
+  for (;;) {
+    if (threadIdx.x == 0) ticket = atomicAdd(&queue[2 * x], 1u);
+    __syncthreads();
+    const int64_t item = lo + ticket;
+    // every thread has its ticket, and the previous tile's LDS reads are done
+    __syncthreads();
+    if (item >= hi) break;
+    gemm_lds_tile<M3, WJ>(G, W, item, rowC, colC, colA, rowB, rowEnd, colEnd, K, As, Bs);
+  }
+  if (threadIdx.x == 0) {
+    // all of range x's tickets are drawn once its gridDim.x / 8 workgroups
+    // have each drawn one past the end
+    if (atomicAdd(&queue[2 * x + 1], 1u) == (gridDim.x >> 3) - 1) {
+      atomicExch(&queue[2 * x], 0u);
+      atomicExch(&queue[2 * x + 1], 0u);
+    }
+  }
 }
 
 // ============================================================== GEMM f32 via bf16 split
@@ -1977,7 +2015,7 @@ struct Fac {
     if ((colA | colC | K) & 1) return false;
     for (int i = 0; i < G.ng; ++i)
       if (G.g[i].ld & 1) return false;
-    const bool narrow = N <= 64;
+    const bool narrow = N <= std::max(64, plan.gemm_narrow_max);
     const int BN = narrow ? 64 : 128;
     GemmList W{};
     W.start[0] = 0;
@@ -1991,23 +2029,34 @@ struct Fac {
     for (int i = G.ng + 1; i <= kMaxGroups; ++i) W.start[i] = W.start[G.ng];
     const int64_t total = W.start[G.ng];
     if (total <= 0) return true;
-    const int64_t grid = (total + 7) / 8 * 8;
+    // persistent form: the resident workgroups (two per CU) when the launch
+    // has more tiles than that
+    const int64_t resident = (int64_t)ctx->num_cus * 2 / 8 * 8;
+    const bool persist = plan.gemm_persistent && ctx->gemm_queue && total > resident;
+    const int64_t grid = persist ? resident : (total + 7) / 8 * 8;
+    uint32_t* queue = persist ? (uint32_t*)ctx->gemm_queue : nullptr;
     const bool m3 = gkind == kGemm3M;
     const char* kname = m3 ? (narrow ? "gemm_3m_narrow" : "gemm_3m")
                            : (narrow ? "gemm_c32_narrow" : "gemm_c32");
     const int pi = prof_begin(ctx, kname);
-    if (m3 && narrow)
-      hipLaunchKernelGGL((gemm_c32_lds_kernel<true, 1>), dim3((unsigned)grid), dim3(256), 0,
-                         ctx->stream, G, W, rowC, colC, colA, rowB, rowEnd, colEnd, K);
-    else if (m3)
-      hipLaunchKernelGGL((gemm_c32_lds_kernel<true, 2>), dim3((unsigned)grid), dim3(256), 0,
-                         ctx->stream, G, W, rowC, colC, colA, rowB, rowEnd, colEnd, K);
-    else if (narrow)
-      hipLaunchKernelGGL((gemm_c32_lds_kernel<false, 1>), dim3((unsigned)grid), dim3(256), 0,
-                         ctx->stream, G, W, rowC, colC, colA, rowB, rowEnd, colEnd, K);
-    else
-      hipLaunchKernelGGL((gemm_c32_lds_kernel<false, 2>), dim3((unsigned)grid), dim3(256), 0,
-                         ctx->stream, G, W, rowC, colC, colA, rowB, rowEnd, colEnd, K);
+    const dim3 gd((unsigned)grid), bd(256);
+#define BEM_GEMM_LDS(M3_, WJ_)                                                                   \
+  if (persist)                                                                                   \
+    hipLaunchKernelGGL((gemm_c32_lds_kernel<M3_, WJ_, true>), gd, bd, 0, ctx->stream, G, W, rowC, \
+                       colC, colA, rowB, rowEnd, colEnd, K, queue);                               \
+  else                                                                                           \
+    hipLaunchKernelGGL((gemm_c32_lds_kernel<M3_, WJ_, false>), gd, bd, 0, ctx->stream, G, W,      \
+                       rowC, colC, colA, rowB, rowEnd, colEnd, K, queue);
+    if (m3 && narrow) {
+      BEM_GEMM_LDS(true, 1)
+    } else if (m3) {
+      BEM_GEMM_LDS(true, 2)
+    } else if (narrow) {
+      BEM_GEMM_LDS(false, 1)
+    } else {
+      BEM_GEMM_LDS(false, 2)
+    }
+#undef BEM_GEMM_LDS
     gemm_prof(kname, pi, rowC, colC, rowEnd, colEnd, K);
     return true;
   }
@@ -2224,8 +2273,19 @@ int lu_default_nb(bem_prec prec, int n) {
 }
 
 int lu_plan_nb(bem_ctx* ctx, bem_prec prec, int gemm_kind, int n) {
-  const auto it = ctx->tuned_nb.find({(int)prec * 16 + gemm_kind, (n + 511) / 512 * 512});
-  return it != ctx->tuned_nb.end() ? it->second : lu_default_nb(prec, n);
+  const auto it = ctx->tuned.find({(int)prec * 16 + gemm_kind, (n + 511) / 512 * 512});
+  return it != ctx->tuned.end() ? it->second.nb : lu_default_nb(prec, n);
+}
+
+LuPlan lu_plan_for(bem_ctx* ctx, bem_prec prec, int gemm_kind, int n, int nb) {
+  LuPlan plan;
+  plan.nb = nb > 0 ? nb : lu_plan_nb(ctx, prec, gemm_kind, n);
+  const auto it = ctx->tuned.find({(int)prec * 16 + gemm_kind, (n + 511) / 512 * 512});
+  if (it != ctx->tuned.end()) {
+    plan.gemm_narrow_max = it->second.narrow_max;
+    plan.gemm_persistent = it->second.persistent;
+  }
+  return plan;
 }
 
 // Validate the sets and set up the driver: groups sorted by size, base panel
@@ -2356,12 +2416,21 @@ bem_status lu_autotune(bem_ctx* ctx, bem_prec prec, int n, int batch, int gemm_k
   BEM_HIP_TRY(ctx, hipEventCreate(&e1));
   const bool prof = ctx->profiling;
   ctx->profiling = false;
-  int best = 0;
+  // GEMM shapes tried with every block width: the float32 MFMA forms (4M,
+  // 3M) also try 128 x 64 tiles up to 128 columns and persistent launches
+  const bool lds_forms = prec == BEM_C64 && (gemm_kind == kGemm4M || gemm_kind == kGemm3M);
+  static const int kShapes[3][2] = {{64, 0}, {128, 0}, {64, 1}};
+  const int n_shapes = lds_forms ? 3 : 1;
+  int best = 0, best_narrow = 64, best_persist = 0;
   float bms = 0.f;
   bem_status st = BEM_OK;
-  for (int c = 0; cand[c] > 0 && st == BEM_OK; ++c) {
+  ctx->tune_log.clear();
+  for (int c = 0; cand[c] > 0 && st == BEM_OK; ++c)
+  for (int sh = 0; sh < n_shapes && st == BEM_OK; ++sh) {
     LuPlan plan;
     plan.nb = cand[c];
+    plan.gemm_narrow_max = kShapes[sh][0];
+    plan.gemm_persistent = kShapes[sh][1];
     float ms_min = 0.f;
     for (int rep = 0; rep < 2 && st == BEM_OK; ++rep) {
       const int64_t total = (int64_t)batch * stride;
@@ -2379,7 +2448,14 @@ bem_status lu_autotune(bem_ctx* ctx, bem_prec prec, int n, int batch, int gemm_k
       (void)hipEventElapsedTime(&ms, e0, e1);
       if (rep == 0 || ms < ms_min) ms_min = ms;
     }
-    if (st == BEM_OK && (best == 0 || ms_min < bms)) { best = cand[c]; bms = ms_min; }
+    if (st == BEM_OK)
+      ctx->tune_log.push_back({bem_ctx::TunedPlan{cand[c], kShapes[sh][0], kShapes[sh][1]}, ms_min});
+    if (st == BEM_OK && (best == 0 || ms_min < bms)) {
+      best = cand[c];
+      best_narrow = kShapes[sh][0];
+      best_persist = kShapes[sh][1];
+      bms = ms_min;
+    }
   }
   ctx->profiling = prof;
   (void)hipEventDestroy(e0);
@@ -2388,7 +2464,8 @@ bem_status lu_autotune(bem_ctx* ctx, bem_prec prec, int n, int batch, int gemm_k
   (void)hipFree(A);
   if (st != BEM_OK) return st;
   if (best == 0) return fail(ctx, BEM_EINVAL, "autotune: no candidate block width");
-  ctx->tuned_nb[{(int)prec * 16 + gemm_kind, (n + 511) / 512 * 512}] = best;
+  ctx->tuned[{(int)prec * 16 + gemm_kind, (n + 511) / 512 * 512}] =
+      bem_ctx::TunedPlan{best, best_narrow, best_persist};
   if (best_nb) *best_nb = best;
   if (best_ms) *best_ms = bms;
   return BEM_OK;
@@ -2402,7 +2479,8 @@ void drop_graphs(bem_ctx* ctx) {
 
 bem_status lu_factor_groups_graph(bem_ctx* ctx, bem_prec prec, const std::vector<LuMatrixSet>& sets,
                                   const LuPlan& plan, int gemm_kind) {
-  std::vector<int64_t> key{(int64_t)prec, plan.nb, plan.base, gemm_kind, (int64_t)sets.size()};
+  std::vector<int64_t> key{(int64_t)prec, plan.nb, plan.base, plan.gemm_narrow_max,
+                           plan.gemm_persistent, gemm_kind, (int64_t)sets.size()};
   for (const LuMatrixSet& m : sets) {
     key.push_back((int64_t)(intptr_t)m.A);
     key.push_back((int64_t)(intptr_t)m.piv);

@@ -27,7 +27,7 @@ EXPORTED = [
     "bem_ctx_set_profiling", "bem_ctx_set_profiling_filter", "bem_ctx_kernel_stats",
     "bem_mesh_counts", "bem_mesh_icosphere", "bem_mesh_bowl_counts", "bem_mesh_bowl", "bem_incident", "bem_assemble", "bem_residual",
     "bem_solve_opts_default", "bem_solve_batched", "bem_getrf_batched", "bem_getrs_batched",
-    "bem_autotune_lu",
+    "bem_autotune_lu", "bem_autotune_lu_results", "bem_lu_tuned_plan", "bem_lu_set_plan",
     "bem_split_unknowns", "bem_field_eval", "bem_field_eval_noalloc", "pulse_synthesize",
     "pulse_synthesize_sparse",
     "bem_pulse_coeffs", "bem_pulse_dominant",
@@ -135,6 +135,10 @@ def load(path: str = LIB_PATH):
                                       vp, vp, vp, vp], C.c_int),
         "bem_solve_chief": ([vp, C.POINTER(bem_surface), i32, vp, i32, vp, i32, vp, vp,
                              C.POINTER(bem_solve_info)], C.c_int),
+        "bem_autotune_lu_results": ([vp, i32, vp, vp, vp, vp], i32),
+        "bem_lu_tuned_plan": ([vp, C.c_int, i32, i32, C.POINTER(i32), C.POINTER(i32),
+                               C.POINTER(i32)], C.c_int),
+        "bem_lu_set_plan": ([vp, C.c_int, i32, i32, i32, i32, i32], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -284,6 +288,27 @@ def bem_solve_quadratic(ctx, qsurf, n_k, k, n_rhs, y, opts, x_out):
     _check(load().bem_solve_quadratic(ctx.handle, C.byref(qsurf), n_k, _ptr(k), n_rhs, _ptr(y),
                                       C.byref(opts), _ptr(x_out), info), ctx)
     return info
+
+
+def bem_autotune_lu_results(ctx):
+    """Every plan the last bem_autotune_lu tried: list of (nb, narrow_max, persistent, ms)."""
+    cnt = load().bem_autotune_lu_results(ctx.handle, 0, None, None, None, None)
+    nb, nw, ps = (C.c_int32 * max(cnt, 1))(), (C.c_int32 * max(cnt, 1))(), (C.c_int32 * max(cnt, 1))()
+    ms = (C.c_double * max(cnt, 1))()
+    load().bem_autotune_lu_results(ctx.handle, cnt, nb, nw, ps, ms)
+    return [(nb[i], nw[i], ps[i], ms[i]) for i in range(cnt)]
+
+
+def bem_lu_set_plan(ctx, prec, n, gemm_kind, nb, narrow_max=64, persistent=0):
+    _check(load().bem_lu_set_plan(ctx.handle, prec, n, gemm_kind, nb, narrow_max, persistent), ctx)
+
+
+def bem_lu_tuned_plan(ctx, prec, n, gemm_kind):
+    """(nb, narrow_max, persistent) kept by bem_autotune_lu for this size class."""
+    a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(load().bem_lu_tuned_plan(ctx.handle, prec, n, gemm_kind, C.byref(a), C.byref(b),
+                                    C.byref(c)), ctx)
+    return a.value, b.value, c.value
 
 
 def bem_solve_chief(ctx, surf, n_k, k, n_rhs, y, n_c, xc, x_out):

@@ -28,7 +28,7 @@ def lib():
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:bem_status|void|const char\*)\s+(\w+)\s*\(", src, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:bem_status|void|int32_t|const char\*)\s+(\w+)\s*\(", src, flags=re.M)))
 
 
 def test_exports_every_declared_symbol(lib):

@@ -199,3 +199,10 @@ def interior_points(bodies: List[Body], per_body: int = 8, seed: int = 0,
         out.append(np.asarray(b.center)[None, :] + u * np.array([b.radius, b.radius, b.radius * b.aspect]))
     return np.concatenate(out).astype(np.float64)
 
+
+# Interior Dirichlet eigenvalues k a of the unit sphere below 8: zeros of the
+# spherical Bessel functions j_0 (pi, 2 pi), j_1, j_2, j_3 (standard tables,
+# rounded to 4 decimals).  The surface equation of a sphere is nearly singular
+# at these wavenumbers.
+SPHERE_RESONANCES = (3.1416, 4.4934, 5.7635, 6.2832, 6.9879, 7.7253)
+
