@@ -706,7 +706,10 @@ __global__ __launch_bounds__(256) void gemm_c32_3m_kernel(LuGroups G, int rowC, 
 //   the 32 rows an MFMA block reads hit distinct banks.  B rows are stored as
 //   they are (consecutive lanes read consecutive columns).
 // * Edges: rows past M and columns past N load clamped addresses and are never
-//   stored; depth past K (the last stage when K is not a multiple of 16) is
+//   stored, and a wave skips the MFMAs of its 32 x 32 blocks that lie wholly
+//   past the edge (the partial tile row and column of an update whose size is
+//   not a multiple of 128: at n = 5124 every trailing update has a 4-wide
+//   one); depth past K (the last stage when K is not a multiple of 16) is
 //   zeroed on the way from LDS to the MFMA operands.
 // * Work list: every (matrix, tile) pair of the launch, over all size classes
 //   (each with its own tile counts), in matrix order, cut into eight
@@ -783,7 +786,7 @@ __device__ __forceinline__ void gemm_lds_tile(const LuGroups& G, const GemmList&
   GLOBAL float2* C = (GLOBAL float2*)Mat + (int64_t)rowC * ld + colC;
 
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wid = tid >> 6;
+  const int lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wid >> 1, wn = wid & 1;
   const int h = lane >> 5, l32 = lane & 31;
 
@@ -832,6 +835,13 @@ __device__ __forceinline__ void gemm_lds_tile(const LuGroups& G, const GemmList&
 
   const int arow0 = wm * 64 + l32;                   // + 32 i
   const int bcol0 = wn * 32 * WJ + l32;              // + 32 j
+  // MFMA blocks whose rows or columns all lie past the edge are skipped
+  // (wave-uniform: partial edge tiles do only the blocks they need)
+  bool live_i[2], live_j[WJ];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) live_i[i] = m0 + wm * 64 + 32 * i < M;
+#pragma unroll
+  for (int j = 0; j < WJ; ++j) live_j[j] = n0 + wn * 32 * WJ + 32 * j < N;
   const int sw = l32 & 7;
   // Operands of one group of 4 complex k (q4) in registers.  3M: lane half h
   // holds k = 4 q4 + 2h + p for MFMA p (A as one 16-byte word per block).
@@ -880,9 +890,11 @@ __device__ __forceinline__ void gemm_lds_tile(const LuGroups& G, const GemmList&
         for (int i = 0; i < 2; ++i)
 #pragma unroll
           for (int j = 0; j < WJ; ++j) {
-            acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i], br[j], acc[0][i][j], 0, 0, 0);
-            acc[1][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[i], bi[j], acc[1][i][j], 0, 0, 0);
-            acc[2][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(as[i], bs[j], acc[2][i][j], 0, 0, 0);
+            if (live_i[i] && live_j[j]) {
+              acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i], br[j], acc[0][i][j], 0, 0, 0);
+              acc[1][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[i], bi[j], acc[1][i][j], 0, 0, 0);
+              acc[2][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(as[i], bs[j], acc[2][i][j], 0, 0, 0);
+            }
           }
       }
     } else {
@@ -905,8 +917,10 @@ __device__ __forceinline__ void gemm_lds_tile(const LuGroups& G, const GemmList&
         for (int i = 0; i < 2; ++i)
 #pragma unroll
           for (int j = 0; j < WJ; ++j) {
-            acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], bre[j], acc[0][i][j], 0, 0, 0);
-            acc[1][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], bim[j], acc[1][i][j], 0, 0, 0);
+            if (live_i[i] && live_j[j]) {
+              acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], bre[j], acc[0][i][j], 0, 0, 0);
+              acc[1][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], bim[j], acc[1][i][j], 0, 0, 0);
+            }
           }
       }
     }
