@@ -90,7 +90,7 @@ def main():
                     help="1: time the space-time reconstruction (2048 solves, 1024^2 points, "
                          "4 pulses, T = 4096) after the headline")
     ap.add_argument("--workload", choices=["spheres", "surrogate", "uneven", "spacetime",
-                                           "truncation", "bowl", "chief"],
+                                           "truncation", "bowl", "chief", "quadratic"],
                     default="spheres",
                     help="spheres: the headline sweep; surrogate: the learned-fill gain "
                          "test (256 training / 4096 predicted wavenumbers, N = 5124); "
@@ -99,7 +99,8 @@ def main():
                          "truncation: the paper's soft sphere and pulse rebuilt from the "
                          "5/10/20 frequencies of largest amplitude vs all 63; "
                          "bowl: the hard acoustic bowl's focusing of a 6-cycle pulse; "
-                         "chief: interior-point rows against fictitious resonances")
+                         "chief: interior-point rows against fictitious resonances; "
+                         "quadratic: the paper's 500-element sphere, whole path")
     ap.add_argument("--tr-level", type=int, default=5,
                     help="icosphere level of the sphere for --workload truncation")
     ap.add_argument("--tr-grid", type=int, default=256,
@@ -118,7 +119,8 @@ def main():
                     help="with --gemm-narrow-max: 1 = persistent GEMM launches")
     ap.add_argument("--autotune", type=int, default=0,
                     help="measure the LU block width on this many matrices before the run")
-    ap.add_argument("--sur-epochs", type=int, default=300)
+    ap.add_argument("--sur-epochs", type=int, default=100,
+                    help="training epochs of the surrogate (100: the fit costs about what it saves)")
     ap.add_argument("--sur-sweeps", type=int, default=20)
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run one plain elementwise copy of 256 MiB (reads 256 MiB, "
@@ -150,6 +152,9 @@ def main():
         return
     if args.workload == "chief":
         run_chief(args)
+        return
+    if args.workload == "quadratic":
+        run_quadratic(args)
         return
 
     from paper_1706_07919_amd import DeviceSurface, native
@@ -586,6 +591,90 @@ def run_truncation(args):
                       "T": T, "points": m},
            "all_frequencies_s": t_full, "truncated": res,
            "table1_printed": {"5": [4.4, 4.9], "10": [1.6, 1.7], "20": [0.5, 0.6]}}
+    print(json.dumps(out))
+
+
+def run_quadratic(args):
+    """The paper's quadratic-element sphere (Sec. IV A: 500 six-node elements,
+    1002 nodes, sound-soft) under its pulse (2 N_c = 4, alpha = 0.1, w = 20.1,
+    63 frequencies, T = 128): incident data, element-quadrature assembly and
+    the float32 3M solve refined against the float64 operator, the field by
+    element quadrature on the paper's 80 x 80 grid over the 20 a square of the
+    x = 0 plane, and the synthesis.  Times the whole path (after one untimed
+    pass) and reports the assembly and field kernels' rates."""
+    import torch
+
+    from paper_1706_07919_amd import DeviceQuadSurface, native
+    from workloads import Body, SOFT, plane_grid
+
+    W, T, F = 20.1, 128, 63
+    dk = 2.0 * np.pi / W
+    body = Body((0.0, 0.0, 0.0), 1.0, 1.0, 0, SOFT)
+    qs = DeviceQuadSurface.from_body(body, 5)
+    n = qs.n
+    ctx = native.Context(0)
+    dev = torch.device("cuda:0")
+    # the nodal struct for incident data and the split of the unknowns (their
+    # kernels read no weights)
+    ns = native.surface_struct(n, qs.x, qs.nrm, qs.x, qs.bc)
+    k = dk * np.arange(1, F + 1)
+    kd = torch.as_tensor(k).to(dev)
+    pts = plane_grid(80)
+    xp = torch.as_tensor(pts).to(dev)
+    m = len(pts)
+    c = native.bem_pulse_coeffs("paper", [2.0, 0.1, W], dk, F, T, -(1.0 + W / 4))
+    cd = torch.as_tensor(c[None, :]).to(dev)
+    opts = native.bem_solve_opts_default()
+    opts.mode = native.BEM_FP32_IR_3M
+    y = torch.empty((F, 1, n), dtype=torch.complex128, device=dev)
+    x = torch.zeros_like(y)
+    phi, psi = torch.empty_like(y), torch.empty_like(y)
+    U = torch.empty((1, m, F), dtype=torch.complex128, device=dev)
+    U32 = torch.empty((1, m, F), dtype=torch.complex64, device=dev)
+    p = torch.empty((1, m, T), dtype=torch.float32, device=dev)
+    i0 = torch.empty(m, dtype=torch.int32, device=dev)
+    ins = torch.empty(m, dtype=torch.uint8, device=dev)
+    marks = {}
+
+    def run():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        native.bem_incident(ctx, ns, F, kd, (0.0, 0.0, 1.0), y)
+        info = native.bem_solve_quadratic(ctx, qs.struct, F, kd, 1, y, opts, x)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        native.bem_split_unknowns(ctx, ns, F, 1, x, y, phi, psi)
+        native.bem_field_eval_quadratic(ctx, qs.struct, F, kd, 1, phi, psi, m, xp, i0, ins, U)
+        U32.copy_(U)
+        native.pulse_synthesize(ctx, m, F, U32[0], 1, cd, T, 1, xp, dk, p)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        marks.update(solve=t1 - t0, rest=t2 - t1)
+        return info
+
+    run()
+    ctx.set_profiling_filter(("assemble_quad", "field_quad"))
+    ctx.set_profiling(True)
+    info = run()
+    fa = ctx.kernel_stats("assemble_quad")
+    ff = ctx.kernel_stats("field_quad")
+    ctx.set_profiling(False)
+    # about 60 float64 operations per kernel value (distance, sincos, G, dG/dn
+    # and the f, g terms of the diagonal integrals)
+    out = {"metric": "quadratic elements (500 el, 1002 nodes): whole-path time, 63 frequencies",
+           "value": marks["solve"] + marks["rest"], "unit": "s", "higher_is_better": False,
+           "data": "synthetic",
+           "dtype": "f64 element-quadrature assembly, c64 LU (3M on f32 MFMA) refined to f64, f64 field",
+           "config": {"workload": "paper soft sphere, quadratic elements nu = 5", "n": n,
+                      "elements": qs.n_elem, "n_k": F, "T": T, "points": m},
+           "solves_per_s": F / marks["solve"], "solve_s": marks["solve"],
+           "field_and_synthesis_s": marks["rest"],
+           "assemble_quad_ms": fa[2], "assemble_kernel_values_per_s": fa[0] / (fa[2] * 1e-3),
+           "assemble_f64_frac_est": 60.0 * fa[0] / (fa[2] * 1e-3) / 78.6e12,
+           "field_quad_ms": ff[2], "field_pt_freq_per_s": m * F / (ff[2] * 1e-3),
+           "ir_iters_max": max(info[q].iters for q in range(F)),
+           "ir_fallbacks": sum(info[q].used_fp64 for q in range(F)),
+           "max_rel_resid": max(info[q].rel_resid for q in range(F))}
     print(json.dumps(out))
 
 
