@@ -366,7 +366,12 @@ bem_status bem_split_unknowns(bem_ctx* ctx, const bem_surface* s, int32_t n_k, i
  *   k[n_k] [dev]; phi, psi [dev] c128 [n_k][n_rhs][n]; xp[m][3] [dev] float64
  *   i0[m] [dev] int32: output, or input when i0_given != 0
  *   inside[m] [dev] uint8 output
- *   U [dev] [n_rhs][m][n_k], c64 (float32 kernel) or c128 (float64 kernel) */
+ *   U [dev] [n_rhs][m][n_k], c64 (float32 kernel) or c128 (float64 kernel)
+ * Both kernels take the per-node sums S(x_i0) in float64.  The float32
+ * kernel sorts the outside points by i0 (counting sort), forms the brackets
+ * w_j u_j, w_j u'_j once per node i0 and node tile (float64, rounded to
+ * float32) and sums each point's terms in float32 in sixteen interleaved
+ * partial sums; P is assembled in float64. */
 bem_status bem_field_eval(bem_ctx* ctx, const bem_surface* s, int32_t n_k, const double* k,
                           int32_t n_rhs, const void* phi, const void* psi, int32_t m,
                           const double* xp, int32_t* i0, int32_t i0_given, uint8_t* inside,
@@ -375,12 +380,13 @@ bem_status bem_field_eval(bem_ctx* ctx, const bem_surface* s, int32_t n_k, const
 /* The same evaluation with no allocation: for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, hosts that
  * forbid hipMalloc).  It calls no hipMalloc / hipFree and creates no profiling
- * events; the per-node sums S(x_a) that bem_field_eval keeps in the context's
- * workspace go to a fixed 32 MiB device array of the library instead, so
- *   n_rhs * n_k * n * (8 bytes for BEM_C64, 16 for BEM_C128) <= 32 MiB
- * (e.g. n = 5124 nodes with up to 818 frequencies per call in c64), else
- * BEM_EINVAL.  Arguments, results and ordering are those of bem_field_eval
- * (same kernels, same results bit for bit).  Every context on a device shares
+ * events; the scratch that bem_field_eval takes from the context's workspace
+ * comes from a fixed 32 MiB device array of the library instead: the float64
+ * per-node sums S(x_a) (n_rhs * n_k * n * 16 bytes) and, for BEM_C64, the
+ * grouping of the points by closest node (about 4.5 m + 32 n bytes); calls
+ * needing more than 32 MiB return BEM_EINVAL before any launch (e.g. n = 5124
+ * nodes, one right-hand side: 409 frequencies with a few thousand points).  Arguments, results and ordering are those of
+ * bem_field_eval (same kernels, same results bit for bit).  Every context on a device shares
  * that device's array, which keeps the last call's contents (nothing in it
  * needs to start at zero): calls that overlap on one device (different
  * streams or threads) race and give undefined results.  Returns BEM_EHIP if

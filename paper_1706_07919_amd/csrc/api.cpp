@@ -969,10 +969,14 @@ bem_status field_eval_impl(bem_ctx* ctx, const char* name, const bem_surface* s,
       (prec != BEM_C64 && prec != BEM_C128))
     return fail(ctx, BEM_EINVAL, "%s: bad argument", name);
   if (n_rhs > 65535 || (n_k + 7) / 8 > 65535) return fail(ctx, BEM_EINVAL, "%s: n_k or n_rhs too large", name);
-  if (fixed_scratch && (prec == BEM_C128 ? 16 : 8) * (size_t)n_rhs * n_k * s->n > ctx->field_scratch_bytes)
+  if (fixed_scratch && prec == BEM_C128 && 16 * (size_t)n_rhs * n_k * s->n > ctx->field_scratch_bytes)
     return fail(ctx, BEM_EINVAL,
                 "%s: n_rhs * n_k * n = %lld node sums do not fit the %zu-byte fixed scratch", name,
                 (long long)n_rhs * n_k * s->n, ctx->field_scratch_bytes);
+  if (fixed_scratch && prec == BEM_C64 && field_group_bytes(s->n, m, n_k, n_rhs) > ctx->field_scratch_bytes)
+    return fail(ctx, BEM_EINVAL, "%s: the node sums and the grouping of %d points need %zu bytes, "
+                "more than the %zu-byte fixed scratch", name, m, field_group_bytes(s->n, m, n_k, n_rhs),
+                ctx->field_scratch_bytes);
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
   if (m == 0) return BEM_OK;
   if (!i0_given) {

@@ -207,6 +207,8 @@ bem_status launch_field(bem_ctx*, const bem_surface*, int n_k, const double* k, 
                         bool fixed_scratch = false);
 // take the device address of the field scratch for ctx (its device current)
 bem_status field_scratch_init(bem_ctx* ctx);
+// device bytes of the float32 field's node sums and point grouping
+size_t field_group_bytes(int n, int m, int n_k, int n_rhs);
 // m_index (device, or NULL for the dense grid m = 1..n_k): frequency index of
 // each column of U and c
 bem_status launch_synth(bem_ctx*, int m, int n_k, const void* U, const int32_t* m_index,

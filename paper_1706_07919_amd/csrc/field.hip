@@ -312,6 +312,306 @@ __global__ __launch_bounds__(kFT, sizeof(R) == 4 ? 3 : 1) void field_kernel(
   }
 }
 
+// ---------------------------------------------------------------- grouped field
+// The float32 field of points grouped by their closest node a.  For one
+// node, Eq. BRIEFdmn's brackets
+//   u_j = w_j (phi_j - phi_a g_aj - psi_a f_aj),  v_j = w_j (psi_j - phi_a g'_aj - psi_a f'_aj)
+// depend on (a, j, k) only, so a workgroup holding points of one node forms
+// them once per node tile and frequency chunk (float64, rounded to float32)
+// and every point's sum becomes S(x) = sum_{j != a} (u_j H^x_j - v_j G^x_j):
+// one phase and two complex multiply-adds per term.  The node sums S(x_a)
+// come from the float64 node pass (they are of the size of the surface data,
+// while far from the bodies S(x_p) and the field are much smaller), and
+//   P(x_p) = phi_a + (S(x_p) - S(x_a)) / (4 pi)
+// is formed in float64.  Points are sorted by closest node with a counting
+// sort; each node's points are cut into chunks of kGP = kPW (one workgroup
+// each).  Inside points are in no chunk and get 0.
+constexpr int kGP = kPW;
+
+// cnt[a] = number of outside points whose closest node is a (cnt zeroed)
+__global__ void group_count_kernel(int m, const int32_t* __restrict__ i0,
+                                   const uint8_t* __restrict__ inside, int32_t* __restrict__ cnt) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < m && !inside[p]) atomicAdd(&cnt[i0[p]], 1);
+}
+
+// one workgroup of 1024 threads: off = exclusive scan of cnt, choff =
+// exclusive scan of ceil(cnt / kGP), both with their totals at [n]
+__global__ __launch_bounds__(1024) void group_scan_kernel(int n, const int32_t* __restrict__ cnt,
+                                                          int32_t* __restrict__ off,
+                                                          int32_t* __restrict__ choff) {
+  __shared__ int32_t sa[1024], sb[1024];
+  __shared__ int32_t carry[2];
+  if (threadIdx.x == 0) carry[0] = carry[1] = 0;
+  __syncthreads();
+  for (int b0 = 0; b0 < n; b0 += 1024) {
+    const int i = b0 + threadIdx.x;
+    const int c = i < n ? cnt[i] : 0;
+    sa[threadIdx.x] = c;
+    sb[threadIdx.x] = (c + kGP - 1) / kGP;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {   // inclusive scans (Hillis-Steele)
+      const int va = threadIdx.x >= o ? sa[threadIdx.x - o] : 0;
+      const int vb = threadIdx.x >= o ? sb[threadIdx.x - o] : 0;
+      __syncthreads();
+      sa[threadIdx.x] += va;
+      sb[threadIdx.x] += vb;
+      __syncthreads();
+    }
+    if (i < n) {
+      off[i] = carry[0] + sa[threadIdx.x] - c;
+      choff[i] = carry[1] + sb[threadIdx.x] - (c + kGP - 1) / kGP;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      carry[0] += sa[1023];
+      carry[1] += sb[1023];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    off[n] = carry[0];
+    choff[n] = carry[1];
+  }
+}
+
+// perm: the outside points ordered by closest node (fill zeroed); the order
+// inside a node's range does not matter
+__global__ void group_scatter_kernel(int m, const int32_t* __restrict__ i0,
+                                     const uint8_t* __restrict__ inside,
+                                     const int32_t* __restrict__ off, int32_t* __restrict__ fill,
+                                     int32_t* __restrict__ perm) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= m || inside[p]) return;
+  const int a = i0[p];
+  perm[off[a] + atomicAdd(&fill[a], 1)] = p;
+}
+
+// chunks[c] = (node, first index into perm, points), kGP points at most
+__global__ void group_chunks_kernel(int n, const int32_t* __restrict__ cnt,
+                                    const int32_t* __restrict__ off,
+                                    const int32_t* __restrict__ choff, int4* __restrict__ chunks) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  const int c0 = choff[a], nc = choff[a + 1] - c0;
+  for (int c = 0; c < nc; ++c)
+    chunks[c0 + c] = make_int4(a, off[a] + c * kGP, min(kGP, cnt[a] - c * kGP), 0);
+}
+
+// U = 0 for inside points
+__global__ void zero_inside_kernel(int m, int n_k, int n_rhs, const uint8_t* __restrict__ inside,
+                                   float2* __restrict__ U) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)m * n_k * n_rhs) return;
+  const int p = (int)((t / n_k) % m);
+  if (inside[p]) U[t] = make_float2(0.f, 0.f);
+}
+
+template <int FCH, int NR>
+__global__ __launch_bounds__(kFT, 3) void field_grouped_kernel(
+    int n, const double* __restrict__ x, const double* __restrict__ nrm,
+    const double* __restrict__ w, const double* __restrict__ kv, int n_k, int n_rhs,
+    const double2* __restrict__ phi, const double2* __restrict__ psi, int m,
+    const double* __restrict__ xp, const int4* __restrict__ chunks,
+    const int32_t* __restrict__ nchunks, const int32_t* __restrict__ perm,
+    const double2* __restrict__ Snode, float2* __restrict__ U) {
+  __shared__ double sx[kNJ][3];
+  __shared__ float2 su[NR][FCH][kNJ], sv[NR][FCH][kNJ];
+  __shared__ float snrm[kNJ][3];
+  if ((int)blockIdx.x >= *nchunks) return;   // uniform
+  const int4 ch = chunks[blockIdx.x];
+  const int a = ch.x, start = ch.y, len = ch.z;
+  const int gi = threadIdx.x / kParts, part = threadIdx.x % kParts;
+  const bool valid = gi < len;
+  const int p = valid ? perm[start + gi] : -1;
+  const double ax = x[3 * a], ay = x[3 * a + 1], az = x[3 * a + 2];
+  const double anx = nrm[3 * a], any = nrm[3 * a + 1], anz = nrm[3 * a + 2];
+  const double px = p >= 0 ? xp[3 * p] : ax, py = p >= 0 ? xp[3 * p + 1] : ay,
+               pz = p >= 0 ? xp[3 * p + 2] : az;
+  const int m0 = blockIdx.y * FCH;
+  const int r0 = blockIdx.z * NR;
+  const int nrh = min(NR, n_rhs - r0);
+  const int nf = min(FCH, n_k - m0);
+  double kk[FCH];
+#pragma unroll
+  for (int f = 0; f < FCH; ++f) kk[f] = f < nf ? kv[m0 + f] : kv[m0];
+  const double dkk = nf > 1 ? (kk[nf - 1] - kk[0]) / (nf - 1) : 0.0;
+  bool uni = nf > 1;
+#pragma unroll
+  for (int f = 1; f < FCH; ++f)
+    if (f < nf && !(fabs(kk[f] - (kk[0] + f * dkk)) <= 4e-16 * fabs(kk[f]))) uni = false;
+  float2 S[NR][FCH], S1[NR][FCH];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int f = 0; f < FCH; ++f) S[r][f] = S1[r][f] = make_float2(0.f, 0.f);
+  for (int j0 = 0; j0 < n; j0 += kNJ) {
+    const int cnt = min(kNJ, n - j0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < cnt * 3; e += kFT) {
+      sx[e / 3][e % 3] = x[3 * j0 + e];
+      snrm[e / 3][e % 3] = (float)nrm[3 * j0 + e];
+    }
+    // the brackets u, v of the tile's nodes for the workgroup's node a
+    for (int e = threadIdx.x; e < NR * FCH * kNJ; e += kFT) {
+      const int r = e / (FCH * kNJ), f = (e / kNJ) % FCH, jj = e % kNJ;
+      float2 uu = make_float2(0.f, 0.f), vv = uu;
+      const int j = j0 + jj;
+      if (r < nrh && f < nf && jj < cnt && j != a) {
+        const double k = kk[f];
+        const double njx = nrm[3 * j], njy = nrm[3 * j + 1], njz = nrm[3 * j + 2];
+        const double sa = anx * (x[3 * j] - ax) + any * (x[3 * j + 1] - ay) + anz * (x[3 * j + 2] - az);
+        const double nn = anx * njx + any * njy + anz * njz;
+        double sn, cs;
+        sincos(k * sa, &sn, &cs);
+        const double g = cs, fv = sn / k, gp = -k * sn * nn, fp = cs * nn;
+        const int64_t va = ((int64_t)(m0 + f) * n_rhs + r0 + r) * n;
+        const double2 pa = phi[va + a], qa = psi[va + a], pj = phi[va + j], qj = psi[va + j];
+        const double wj = w[j];
+        uu = make_float2((float)(wj * (pj.x - pa.x * g - qa.x * fv)),
+                         (float)(wj * (pj.y - pa.y * g - qa.y * fv)));
+        vv = make_float2((float)(wj * (qj.x - pa.x * gp - qa.x * fp)),
+                         (float)(wj * (qj.y - pa.y * gp - qa.y * fp)));
+      }
+      su[r][f][jj] = uu;
+      sv[r][f][jj] = vv;
+    }
+    __syncthreads();
+    if (!valid) continue;
+    // the lane's nodes alternate between two partial sums (halving the
+    // length of each float32 chain)
+    auto term = [&](int jj, float2 (&Sh)[NR][FCH]) {
+      if (j0 + jj == a) return;   // its brackets vanish (and r = 0 for a point on the node)
+      const double dx = sx[jj][0] - px, dy = sx[jj][1] - py, dz = sx[jj][2] - pz;
+      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      const float rinv = __builtin_amdgcn_rcpf((float)r);
+      const float dn = ((float)dx * snrm[jj][0] + (float)dy * snrm[jj][1] + (float)dz * snrm[jj][2]) *
+                       (rinv * rinv * rinv);   // (d.n_j)/r^3
+      float es, ec, des = 0.f, dec = 1.f;
+      phase<float>(kk[0] * r, es, ec);
+      if (uni) phase<float>(dkk * r, des, dec);
+      const float rf = (float)r;
+#pragma unroll
+      for (int f = 0; f < FCH; ++f) {
+        if (f > 0) {
+          if (uni) {
+            const float e1 = ec * des + es * dec, e0 = ec * dec - es * des;
+            es = e1;
+            ec = e0;
+          } else {
+            phase<float>(kk[f] * r, es, ec);
+          }
+        }
+        // G = E / r ; H = E (ikr - 1) (d.n) / r^3
+        const float gr = ec * rinv, gi = es * rinv;
+        const float kr = (float)kk[f] * rf;
+        const float hr = (-ec - kr * es) * dn, hi = (kr * ec - es) * dn;
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr) {
+          if (rr >= nrh) break;   // uniform
+          const float2 u = su[rr][f][jj], v = sv[rr][f][jj];
+          Sh[rr][f].x += (u.x * hr - u.y * hi) - (v.x * gr - v.y * gi);
+          Sh[rr][f].y += (u.x * hi + u.y * hr) - (v.x * gi + v.y * gr);
+        }
+      }
+    };
+    for (int jj = part; jj < cnt; jj += 2 * kParts) {
+      term(jj, S);
+      if (jj + kParts < cnt) term(jj + kParts, S1);
+    }
+  }
+#pragma unroll
+  for (int rr = 0; rr < NR; ++rr)
+#pragma unroll
+    for (int f = 0; f < FCH; ++f) {
+      S[rr][f].x += S1[rr][f].x;
+      S[rr][f].y += S1[rr][f].y;
+    }
+#pragma unroll
+  for (int rr = 0; rr < NR; ++rr)
+#pragma unroll
+    for (int f = 0; f < FCH; ++f) {
+      S[rr][f].x = part_sum(S[rr][f].x);
+      S[rr][f].y = part_sum(S[rr][f].y);
+    }
+  if (p < 0) return;
+  const double inv4pi = 1.0 / kFourPi;
+#pragma unroll
+  for (int rr = 0; rr < NR; ++rr)
+#pragma unroll
+    for (int f = 0; f < FCH; ++f) {
+      if ((rr * FCH + f) % kParts != part || rr >= nrh || f >= nf) continue;
+      const double2 pa = phi[((int64_t)(m0 + f) * n_rhs + r0 + rr) * n + a];
+      const double2 sa = Snode[((int64_t)(r0 + rr) * n_k + m0 + f) * n + a];
+      U[((int64_t)(r0 + rr) * m + p) * n_k + m0 + f] =
+          make_float2((float)(pa.x + ((double)S[rr][f].x - sa.x) * inv4pi),
+                      (float)(pa.y + ((double)S[rr][f].y - sa.y) * inv4pi));
+    }
+}
+
+size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+
+// fixed: the fixed scratch (bem_field_eval_noalloc: no workspace, no
+// profiling events), else NULL
+template <int FCH, int NR>
+bem_status field_grouped(bem_ctx* ctx, const bem_surface* s, int n_k, const double* k, int n_rhs,
+                         const void* phi, const void* psi, int m, const double* xp,
+                         const int32_t* i0, const uint8_t* inside, void* U, void* fixed) {
+  const int n = s->n;
+  auto al = al256;
+  const size_t max_chunks = (size_t)(m + kGP - 1) / kGP + n;
+  const size_t bytes = field_group_bytes(n, m, n_k, n_rhs);
+  void* ws = fixed;
+  bem_status st = BEM_OK;
+  if (!ws && (st = workspace(ctx, bytes, &ws)) != BEM_OK) return st;
+  char* q = (char*)ws;
+  double2* Snode = (double2*)q; q += al(16 * (size_t)n_rhs * n_k * n);
+  int32_t* cnt = (int32_t*)q;   q += al(4 * (size_t)n);
+  int32_t* fill = (int32_t*)q;  q += al(4 * (size_t)n);
+  int32_t* off = (int32_t*)q;   q += al(4 * (size_t)(n + 1));
+  int32_t* choff = (int32_t*)q; q += al(4 * (size_t)(n + 1));
+  int32_t* perm = (int32_t*)q;  q += al(4 * (size_t)m);
+  int4* chunks = (int4*)q;
+  if ((st = fill_zero(ctx, cnt, 2 * al(4 * (size_t)n))) != BEM_OK) return st;   // cnt and fill
+  const int pi = fixed ? -1 : prof_begin(ctx, "field");
+  // float64 node sums S(x_a) of every node (the n x n_k x n terms of the node
+  // pass, about 1/200 of the points' terms at a million points)
+  {
+    const int fch = (n_k + 7) / 8;
+    const int nz = (n_rhs + NR - 1) / NR;
+    dim3 gnode((n + kPW - 1) / kPW, fch, nz);
+    if (NR == 1)
+      hipLaunchKernelGGL((field_kernel<double, 8, 0, 1>), gnode, dim3(kFT), 0, ctx->stream, n, s->x,
+                         s->nrm, s->w, k, n_k, n_rhs, (const double2*)phi, (const double2*)psi, n,
+                         s->x, (const int32_t*)nullptr, (const uint8_t*)nullptr, Snode,
+                         (double2*)nullptr);
+    else
+      hipLaunchKernelGGL((field_kernel<double, 4, 0, 4>), dim3((n + kPW - 1) / kPW, (n_k + 3) / 4, nz),
+                         dim3(kFT), 0, ctx->stream, n, s->x, s->nrm, s->w, k, n_k, n_rhs,
+                         (const double2*)phi, (const double2*)psi, n, s->x,
+                         (const int32_t*)nullptr, (const uint8_t*)nullptr, Snode, (double2*)nullptr);
+  }
+  hipLaunchKernelGGL(group_count_kernel, dim3((m + 255) / 256), dim3(256), 0, ctx->stream, m, i0,
+                     inside, cnt);
+  hipLaunchKernelGGL(group_scan_kernel, dim3(1), dim3(1024), 0, ctx->stream, n, cnt, off, choff);
+  hipLaunchKernelGGL(group_scatter_kernel, dim3((m + 255) / 256), dim3(256), 0, ctx->stream, m, i0,
+                     inside, off, fill, perm);
+  hipLaunchKernelGGL(group_chunks_kernel, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, n, cnt,
+                     off, choff, chunks);
+  const int64_t tot = (int64_t)m * n_k * n_rhs;
+  hipLaunchKernelGGL(zero_inside_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                     ctx->stream, m, n_k, n_rhs, inside, (float2*)U);
+  dim3 grid((unsigned)max_chunks, (n_k + FCH - 1) / FCH, (n_rhs + NR - 1) / NR);
+  hipLaunchKernelGGL((field_grouped_kernel<FCH, NR>), grid, dim3(kFT), 0, ctx->stream, n, s->x,
+                     s->nrm, s->w, k, n_k, n_rhs, (const double2*)phi, (const double2*)psi, m, xp,
+                     chunks, choff + n, perm, Snode, (float2*)U);
+  // kernel terms: one per (point or node, frequency, node, rhs)
+  if (!fixed)
+    prof_end(ctx, "field", pi, ((double)m + n) * n_k * n * n_rhs, 8.0 * (double)m * n_k * n_rhs);
+  BEM_CHECK_LAUNCH(ctx);
+  return BEM_OK;
+}
+
 // Snode_fixed: the fixed scratch (bem_field_eval_noalloc: no workspace, no
 // profiling events), or NULL for the context's workspace.
 template <typename R, int FCH, int NR>
@@ -386,8 +686,8 @@ bem_status launch_field(bem_ctx* ctx, const bem_surface* s, int n_k, const doubl
                         bool fixed_scratch) {
   if (m <= 0) return BEM_OK;
   void* fixed = nullptr;
-  if (fixed_scratch) {
-    const size_t need = (prec == BEM_C128 ? 16 : 8) * (size_t)n_rhs * n_k * s->n;
+  if (fixed_scratch && prec == BEM_C128) {
+    const size_t need = 16 * (size_t)n_rhs * n_k * s->n;
     if (!ctx->field_scratch)
       return fail(ctx, BEM_EHIP, "bem_field_eval_noalloc: no device address for the fixed scratch");
     if (need > ctx->field_scratch_bytes)
@@ -399,7 +699,14 @@ bem_status launch_field(bem_ctx* ctx, const bem_surface* s, int n_k, const doubl
   }
   if (prec == BEM_C128)
     return field_go<double>(ctx, s, n_k, k, n_rhs, phi, psi, m, xp, i0, inside, U, fixed);
-  return field_go<float>(ctx, s, n_k, k, n_rhs, phi, psi, m, xp, i0, inside, U, fixed);
+  // float32: points grouped by closest node (the bookkeeping in the fixed
+  // scratch for bem_field_eval_noalloc, whose caller checked its size)
+  void* gfixed = fixed_scratch ? ctx->field_scratch : nullptr;
+  if (fixed_scratch && field_group_bytes(s->n, m, n_k, n_rhs) > ctx->field_scratch_bytes)
+    return fail(ctx, BEM_EINVAL, "bem_field_eval_noalloc: point grouping does not fit the fixed scratch");
+  if (n_rhs == 1)
+    return field_grouped<8, 1>(ctx, s, n_k, k, n_rhs, phi, psi, m, xp, i0, inside, U, gfixed);
+  return field_grouped<4, 4>(ctx, s, n_k, k, n_rhs, phi, psi, m, xp, i0, inside, U, gfixed);
 }
 
 bem_status field_scratch_init(bem_ctx* ctx) {
@@ -414,6 +721,12 @@ bem_status field_scratch_init(bem_ctx* ctx) {
   ctx->field_scratch = ptr;
   ctx->field_scratch_bytes = kFieldScratchBytes;
   return BEM_OK;
+}
+
+size_t field_group_bytes(int n, int m, int n_k, int n_rhs) {
+  const size_t max_chunks = (size_t)(m + kGP - 1) / kGP + n;
+  return al256(16 * (size_t)n_rhs * n_k * n) + 2 * al256(4 * (size_t)n) +
+         2 * al256(4 * (size_t)(n + 1)) + al256(4 * (size_t)m) + al256(16 * max_chunks);
 }
 
 }  // namespace bem
