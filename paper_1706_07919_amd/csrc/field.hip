@@ -462,8 +462,11 @@ __global__ __launch_bounds__(kFT, 3) void field_grouped_kernel(
         const double njx = nrm[3 * j], njy = nrm[3 * j + 1], njz = nrm[3 * j + 2];
         const double sa = anx * (x[3 * j] - ax) + any * (x[3 * j + 1] - ay) + anz * (x[3 * j + 2] - az);
         const double nn = anx * njx + any * njy + anz * njz;
-        double sn, cs;
-        sincos(k * sa, &sn, &cs);
+        // the phase reduced in float64, its sine and cosine in float32 (the
+        // brackets are rounded to float32)
+        float fsn, fcs;
+        phase<float>(k * sa, fsn, fcs);
+        const double sn = fsn, cs = fcs;
         const double g = cs, fv = sn / k, gp = -k * sn * nn, fp = cs * nn;
         const int64_t va = ((int64_t)(m0 + f) * n_rhs + r0 + r) * n;
         const double2 pa = phi[va + a], qa = psi[va + a], pj = phi[va + j], qj = psi[va + j];
