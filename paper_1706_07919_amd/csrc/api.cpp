@@ -1329,12 +1329,13 @@ extern "C" bem_status bem_solve_chief(bem_ctx* ctx, const bem_surface* s, int32_
                                       const double* k, int32_t n_rhs, const void* y, int32_t n_c,
                                       const double* xc, void* x_out, bem_solve_info* info) {
   if (!ctx) return BEM_EINVAL;
-  if (!s || s->n <= 0 || !s->x || !s->nrm || !s->w || !s->bc || n_rhs <= 0 || n_rhs > 65535 ||
-      !y || !x_out || n_c <= 0 || n_c > 65535 || !xc)
+  bem_status st;
+  if (!surface_ok(ctx, s, &st)) return st;
+  if (n_rhs <= 0 || n_rhs > 65535 || !y || !x_out || n_c <= 0 || n_c > 65535 || !xc)
     return fail(ctx, BEM_EINVAL, "bem_solve_chief: bad argument");
   if (s->n > 12288) return fail(ctx, BEM_EUNSUPPORTED, "bem_solve_chief: n = %d > 12288", s->n);
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
-  bem_status st;
+  if ((st = check_surface_values(ctx, s)) != BEM_OK) return st;
   if ((st = check_k(ctx, n_k, k)) != BEM_OK) return st;
   const int n = s->n, nr = n_rhs, naug = n + nr;
   const int64_t ld = round_up(naug, 16);

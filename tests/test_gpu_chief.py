@@ -83,3 +83,26 @@ def test_chief_rejects_bad_arguments(ctx):
         native.bem_solve_chief(ctx, ds.struct, 1, k, 1, y, 0, xc, x)
     with pytest.raises(native.BemError):
         native.bem_solve_chief(ctx, ds.struct, 1, dev(np.array([-1.0])), 1, y, 1, xc, x)
+
+
+def test_chief_chunked_vs_oracle(ctx):
+    """A workspace limit that holds one wavenumber at a time: the least-squares
+    solve runs per wavenumber and equals the oracle's."""
+    body = Body((0.0, 0.0, 0.0), 1.0, 1.0, 2, HARD)
+    s = Surface([body])
+    ds = DeviceSurface.from_bodies([body])
+    xc = interior_points([body], 6, seed=2)
+    k = np.array([1.3, np.pi, 4.0])
+    y = seeded_complex(np.random.default_rng(4), (len(k), 2, s.n))
+    x = torch.zeros((len(k), 2, s.n), dtype=torch.complex128, device="cuda")
+    ld = (s.n + 2 + 15) // 16 * 16
+    ctx.set_workspace_limit(int(1.5 * (2 * s.n + len(xc) + 2) * ld * 16))
+    try:
+        native.bem_solve_chief(ctx, ds.struct, len(k), dev(k), 2, dev(y), len(xc), dev(xc), x)
+    finally:
+        ctx.set_workspace_limit(0)
+    xg = x.cpu().numpy()
+    for q, kq in enumerate(k):
+        _, _, xo = chief.solve(s, kq, y[q].T, xc)
+        for r in range(2):
+            assert rel(xg[q, r], xo[:, r]) < 1e-10, (kq, r)

@@ -146,3 +146,30 @@ def test_field_quadratic_vs_oracle(ctx):
             assert np.max(np.abs(U[r, :, q] - ref)) < 1e-11 * np.max(np.abs(ref))
             assert U[r, m - 2, q] == phi[q, r, 11]
             assert U[r, m - 1, q] == 0
+
+
+def test_solve_quadratic_chunked_several_rhs(ctx):
+    """A workspace limit that holds two wavenumbers at a time: the solve runs in
+    ragged chunks (2, 2, 1) with three right-hand sides each and still returns
+    the oracle's FP64 solutions."""
+    body = Body((0.2, 0.0, -0.1), 1.0, 1.25, 0, HARD)
+    qs = Q.QuadSurface(body, 3)
+    ds = DeviceQuadSurface.from_body(body, 3)
+    k = np.array([0.7, 1.9, 3.1, 4.4, 5.6])
+    nr = 3
+    y = seeded_complex(np.random.default_rng(21), (len(k), nr, qs.n))
+    x = torch.zeros((len(k), nr, qs.n), dtype=torch.complex128, device="cuda")
+    opts = native.bem_solve_opts_default()
+    opts.mode = native.BEM_FP32_IR_3M
+    per_k = 2 * qs.n * ((qs.n + 15) // 16 * 16) * 16
+    ctx.set_workspace_limit(int(2.5 * per_k))
+    try:
+        info = native.bem_solve_quadratic(ctx, ds.struct, len(k), dev(k), nr, dev(y), opts, x)
+    finally:
+        ctx.set_workspace_limit(0)
+    xg = x.cpu().numpy()
+    for q, kq in enumerate(k):
+        for r in range(nr):
+            _, _, xs = Q.solve(qs, kq, y[q, r])
+            assert rel(xg[q, r], xs) < 1e-8, (kq, r)
+            assert info[q * nr + r].converged == 1
