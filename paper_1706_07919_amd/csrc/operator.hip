@@ -94,7 +94,7 @@ __device__ inline void block_sum_2d(double (&v)[R][C]) {
 // wavenumber takes its own sincos.  The recurrence adds about one rounding
 // per step (relative error below 1e-15 over a chunk).
 constexpr int kKcResidual = 8;   // wavenumbers per workgroup, residual
-constexpr int kKcAssemble = 4;   // wavenumbers per workgroup, assembly (more accumulators)
+constexpr int kKcAssemble = 8;   // wavenumbers per workgroup, assembly
 
 template <int KC>
 struct KChunk {
@@ -116,7 +116,10 @@ __device__ inline KChunk<KC> load_chunk(const double* __restrict__ kv, int nk,
 #pragma unroll
   for (int q = 0; q < KC; ++q) c.k[q] = q < c.kc ? kv[kidx ? kidx[q0 + q] : q0 + q] : 0.0;
   c.uniform = c.kc > 1;
-  c.dk = c.kc > 1 ? (c.k[c.kc - 1] - c.k[0]) / (c.kc - 1) : 0.0;
+  // (the last wavenumber read again from memory: no dynamic index into c.k,
+  // which would put the array in scratch memory)
+  const int ql = q0 + c.kc - 1;
+  c.dk = c.kc > 1 ? (kv[kidx ? kidx[ql] : ql] - c.k[0]) / (c.kc - 1) : 0.0;
 #pragma unroll
   for (int q = 1; q < KC; ++q)
     if (q < c.kc && !(fabs(c.k[q] - (c.k[0] + q * c.dk)) <= 4e-16 * fabs(c.k[q]))) c.uniform = false;
@@ -149,105 +152,232 @@ struct Phase {
   }
 };
 
-// Assembly for one row and a chunk of wavenumbers, one right-hand side
-// (column rhs of y).  WRITE_A: write the matrix row and the diagonal
-// (first pass); later passes only form b for further right-hand sides.
-template <bool OUT128, bool WRITE_A>
-__global__ __launch_bounds__(kThreads, 3) void assemble_kc_kernel(
-    int n, const double* __restrict__ x, const double* __restrict__ nrm,
-    const double* __restrict__ w, const uint8_t* __restrict__ bc, const double* __restrict__ kv,
-    int nk, int n_rhs, int rhs, const double2* __restrict__ y, void* __restrict__ A, int64_t ld,
-    int64_t a_stride, double2* __restrict__ b, double2* __restrict__ diag64) {
-  const int i = blockIdx.x;
-  const KChunk<kKcAssemble> kc = load_chunk<kKcAssemble>(kv, nk, nullptr);
-  const int q0 = blockIdx.y * kKcAssemble;
-  double kinv[kKcAssemble];
+// ---------------------------------------------------------------- assembly
+// One workgroup owns row i and a chunk of kKcAssemble wavenumbers, for one
+// right-hand side (column rhs of y).  Thread t takes the columns
+// j = t + 256 m; per pair it forms the geometry and the starting phases once
+// and then, for each wavenumber of the chunk, the two kernels w G and w H,
+// their contributions to the two diagonal sums and to b, and the matrix entry
+// (WRITE_A: first pass; later passes only form b for further right-hand
+// sides).  The pair loop is instantiated per phase form: the recurrence on an
+// even grid or a sincos per wavenumber, both with the branch-free reduction
+// valid below 2^20 rad, and the library sincos for a row whose phases reach
+// beyond (taken only when a pair of the row needs it: the whole row is then
+// redone).  The per-thread sums are reduced across the workgroup once, at the
+// end.
+enum { kPhRec = 0, kPhNear = 1, kPhWide = 2 };
+
+// A wave-uniform double moved to scalar registers.
+__device__ inline double uniform_d(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+struct AsmRow {
+  int n, n_rhs, rhs, i, q0;
+  const double2* y;
+  void* A;
+  int64_t ld, a_stride;
+};
+
+template <int PH>
+__device__ inline double2 phase_e(double x) {
+  double sn, cs;
+  if (PH == kPhWide)
+    sincos(x, &sn, &cs);
+  else
+    phase_sincos_near(x, &sn, &cs);
+  return make_double2(cs, sn);
+}
+
+// Terms of pair (i, j) for the chunk's wavenumbers.  wr = w_j / r,
+// wq = w_j (d.n_j) / r^3, s0 = n_i.d, nn = n_i.n_j;
+// acc[q] = {Dphi re, im, Dpsi re, im, b re, im}.
+template <int KC, bool OUT128, bool WRITE_A, bool RHS, int PH>
+__device__ __forceinline__ void pair_terms(const AsmRow& p, const KChunk<KC>& kc,
+                                           const double (&kinv)[KC], int j, bool hard, double r,
+                                           double s0, double wr, double wq, double nn,
+                                           double (&acc)[KC][6]) {
+  double2 E = phase_e<PH>(kc.k[0] * r), F = phase_e<PH>(kc.k[0] * s0), dE, dF;
+  if (PH == kPhRec) {
+    dE = phase_e<PH>(kc.dk * r);
+    dF = phase_e<PH>(kc.dk * s0);
+  }
 #pragma unroll
-  for (int q = 0; q < kKcAssemble; ++q) kinv[q] = q < kc.kc ? 1.0 / kc.k[q] : 0.0;
+  for (int q = 0; q < KC; ++q) {
+    if (q >= kc.kc) break;   // workgroup-uniform
+    const double k = kc.k[q];
+    if (q > 0) {
+      if (PH == kPhRec) {
+        E = cmul(E, dE);
+        F = cmul(F, dF);
+      } else {
+        E = phase_e<PH>(k * r);
+        F = phase_e<PH>(k * s0);
+      }
+    }
+    const double kr = k * r;
+    // w G = w E / r,  w H = w E (ikr - 1)(d.n_j) / r^3
+    const double2 wG = make_double2(wr * E.x, wr * E.y);
+    const double2 wH = make_double2(wq * fma(-kr, E.y, -E.x), wq * fma(kr, E.x, -E.y));
+    // g = cos(k s0), f = sin(k s0)/k, g' = -k sin(k s0) nn, f' = cos(k s0) nn
+    const double g = F.x, f = F.y * kinv[q], gp = -(k * nn) * F.y, fp = F.x * nn;
+    acc[q][0] = fma(gp, wG.x, fma(-g, wH.x, acc[q][0]));
+    acc[q][1] = fma(gp, wG.y, fma(-g, wH.y, acc[q][1]));
+    acc[q][2] = fma(fp, wG.x, fma(-f, wH.x, acc[q][2]));
+    acc[q][3] = fma(fp, wG.y, fma(-f, wH.y, acc[q][3]));
+    // unknown coefficient a (M_phi = -w H for a hard node, M_psi = w G for a
+    // soft one) and known coefficient bb (the other)
+    const double2 mwH = make_double2(-wH.x, -wH.y);
+    const double2 a = hard ? mwH : wG, bb = hard ? wG : mwH;
+    const int64_t kq = p.q0 + q;
+    if (WRITE_A) {
+      if (OUT128)
+        reinterpret_cast<double2*>(p.A)[kq * p.a_stride + (int64_t)p.i * p.ld + j] = a;
+      else
+        reinterpret_cast<float2*>(p.A)[kq * p.a_stride + (int64_t)p.i * p.ld + j] =
+            make_float2((float)a.x, (float)a.y);
+    }
+    if (RHS) {
+      const double2 yy = p.y[(kq * p.n_rhs + p.rhs) * p.n + j];
+      acc[q][4] = fma(bb.x, yy.x, fma(-bb.y, yy.y, acc[q][4]));
+      acc[q][5] = fma(bb.x, yy.y, fma(bb.y, yy.x, acc[q][5]));
+    }
+  }
+}
+
+// The thread's columns of row p.i; returns whether a phase of one of its
+// pairs reaches 2^20 rad (the near forms are then invalid for the row).
+template <int KC, bool OUT128, bool WRITE_A, bool RHS, int PH>
+__device__ __forceinline__ bool row_terms(const AsmRow& p, const KChunk<KC>& kc,
+                                          const double (&kinv)[KC], double kmax,
+                                          const double* __restrict__ x,
+                                          const double* __restrict__ nrm,
+                                          const double* __restrict__ w,
+                                          const uint8_t* __restrict__ bc, double (&acc)[KC][6]) {
+  const int i = p.i;
   const double xi = x[3 * i], yi = x[3 * i + 1], zi = x[3 * i + 2];
   const double nix = nrm[3 * i], niy = nrm[3 * i + 1], niz = nrm[3 * i + 2];
-  // per wavenumber: Dphi (re, im), Dpsi (re, im), b (re, im)
-  double acc[kKcAssemble][6];
-#pragma unroll
-  for (int q = 0; q < kKcAssemble; ++q)
-#pragma unroll
-    for (int c = 0; c < 6; ++c) acc[q][c] = 0.0;
-  for (int j = threadIdx.x; j < n; j += kThreads) {
+  bool wide = false;
+  for (int j = threadIdx.x; j < p.n; j += kThreads) {
     if (j == i) continue;
     const double dx = x[3 * j] - xi, dy = x[3 * j + 1] - yi, dz = x[3 * j + 2] - zi;
     const double njx = nrm[3 * j], njy = nrm[3 * j + 1], njz = nrm[3 * j + 2];
     const double r = sqrt(dx * dx + dy * dy + dz * dz);
     const double rinv = 1.0 / r;
-    const double qn = (dx * njx + dy * njy + dz * njz) * (rinv * rinv * rinv);
+    const double wj = w[j];
+    const double wq = wj * ((dx * njx + dy * njy + dz * njz) * (rinv * rinv * rinv));
+    const double wr = wj * rinv;
     const double s0 = nix * dx + niy * dy + niz * dz;
     const double nn = nix * njx + niy * njy + niz * njz;
-    const double wj = w[j];
     const bool hard = bc[j] == BEM_BC_HARD;
-    Phase E, F;
-    E.start(kc, r);
-    F.start(kc, s0);
+    if (PH != kPhWide) wide |= !(kmax * fmax(r, fabs(s0)) < kPhaseNear);
+    pair_terms<KC, OUT128, WRITE_A, RHS, PH>(p, kc, kinv, j, hard, r, s0, wr, wq, nn, acc);
+  }
+  return wide;
+}
+
+// FIRST: the first pass over the right-hand sides (writes the diagonal and,
+// STORE_A, the matrix row); later passes only form b.  RHS: b is formed
+// (false only for a call without right-hand sides).
+template <bool OUT128, bool FIRST, bool STORE_A, bool RHS>
+__global__ __launch_bounds__(kThreads, 2) void assemble_kc_kernel(
+    int n, const double* __restrict__ x, const double* __restrict__ nrm,
+    const double* __restrict__ w, const uint8_t* __restrict__ bc, const double* __restrict__ kv,
+    int nk, int n_rhs, int rhs, const double2* __restrict__ y, void* __restrict__ A, int64_t ld,
+    int64_t a_stride, double2* __restrict__ b, double2* __restrict__ diag64) {
+  constexpr int KC = kKcAssemble, NW = kThreads / 64;
+  static_assert(KC == 8, "the reduction sums 8 wavenumbers per wave");
+  __shared__ double red[NW][6][KC];
+  const int i = blockIdx.x;
+  KChunk<KC> kc = load_chunk<KC>(kv, nk, nullptr);
+  kc.dk = uniform_d(kc.dk);
+  double kinv[KC];
 #pragma unroll
-    for (int q = 0; q < kKcAssemble; ++q) {
-      if (q < kc.kc) {
-        if (q > 0) {
-          E.next(kc, q, r);
-          F.next(kc, q, s0);
-        }
-        const double k = kc.k[q], kr = k * r;
-        const double2 G = make_double2(E.e.x * rinv, E.e.y * rinv);
-        // H = E (ikr - 1) (d.n_j) / r^3
-        const double2 H = make_double2(qn * (-E.e.x - kr * E.e.y), qn * (kr * E.e.x - E.e.y));
-        // g = cos(k s0), f = sin(k s0)/k, g' = -k sin(k s0) nn, f' = cos(k s0) nn
-        const double g = F.e.x, f = F.e.y * kinv[q], gp = -k * F.e.y * nn, fp = F.e.x * nn;
-        acc[q][0] += wj * (gp * G.x - g * H.x);
-        acc[q][1] += wj * (gp * G.y - g * H.y);
-        acc[q][2] += wj * (fp * G.x - f * H.x);
-        acc[q][3] += wj * (fp * G.y - f * H.y);
-        const double2 mphi = make_double2(-wj * H.x, -wj * H.y);
-        const double2 mpsi = make_double2(wj * G.x, wj * G.y);
-        const double2 a = hard ? mphi : mpsi;
-        const double2 bb = hard ? mpsi : mphi;
-        const int64_t kq = q0 + q;
-        if (WRITE_A && A) {
-          if (OUT128)
-            reinterpret_cast<double2*>(A)[kq * a_stride + (int64_t)i * ld + j] = a;
-          else
-            reinterpret_cast<float2*>(A)[kq * a_stride + (int64_t)i * ld + j] =
-                make_float2((float)a.x, (float)a.y);
-        }
-        const double2 yy = y[(kq * n_rhs + rhs) * n + j];
-        acc[q][4] += bb.x * yy.x - bb.y * yy.y;
-        acc[q][5] += bb.x * yy.y + bb.y * yy.x;
+  for (int q = 0; q < KC; ++q) kinv[q] = uniform_d(q < kc.kc ? 1.0 / kc.k[q] : 0.0);
+  double kmax = 0.0;
+#pragma unroll
+  for (int q = 0; q < KC; ++q) kmax = fmax(kmax, fabs(kc.k[q]));
+  const AsmRow p{n, n_rhs, rhs, i, (int)blockIdx.y * KC, y, A, ld, a_stride};
+  double acc[KC][6];
+#pragma unroll
+  for (int q = 0; q < KC; ++q)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[q][c] = 0.0;
+  constexpr bool WA = FIRST && STORE_A;
+  bool wide;
+  if (kc.uniform)
+    wide = row_terms<KC, OUT128, WA, RHS, kPhRec>(p, kc, kinv, kmax, x, nrm, w, bc, acc);
+  else
+    wide = row_terms<KC, OUT128, WA, RHS, kPhNear>(p, kc, kinv, kmax, x, nrm, w, bc, acc);
+  // workgroup sums: per component c, the wave sums of the 8 wavenumbers by
+  // recursive halving (lanes 8q..8q+7 end with wavenumber q), then the waves
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    double v8[KC];
+#pragma unroll
+    for (int q = 0; q < KC; ++q) v8[q] = acc[q][c];
+    const double v = wave_reduce8(v8);
+    if ((lane & 7) == 0) red[wid][c][lane >> 3] = v;
+  }
+  if (__syncthreads_or(wide)) {
+    // a phase of the row reaches past the near range: the row again, one
+    // wavenumber at a time with the library sincos; its entries and sums
+    // replace the first pass's
+    for (int q = 0; q < kc.kc; ++q) {
+      double a1[1][6] = {{0.0, 0.0, 0.0, 0.0, 0.0, 0.0}};
+      KChunk<1> k1;
+      k1.k[0] = kc.k[q];
+      k1.dk = 0.0;
+      k1.kc = 1;
+      k1.uniform = false;
+      const double kinv1[1] = {kinv[q]};
+      AsmRow p1 = p;
+      p1.q0 = p.q0 + q;
+      (void)row_terms<1, OUT128, WA, RHS, kPhWide>(p1, k1, kinv1, kmax, x, nrm, w, bc, a1);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const double v = wave_sum(a1[0][c]);
+        if (lane == 0) red[wid][c][q] = v;
       }
     }
   }
-  block_sum_2d(acc);
-  if (threadIdx.x == 0) {
-    const bool hard = bc[i] == BEM_BC_HARD;
+  __syncthreads();
+  const int q = threadIdx.x;
+  if (q < kc.kc) {
+    double s[6];
 #pragma unroll
-    for (int q = 0; q < kKcAssemble; ++q) {
-      if (q >= kc.kc) break;
-      const int64_t kq = q0 + q;
-      const double2 mphi = make_double2(kFourPi - acc[q][0], -acc[q][1]);
-      const double2 mpsi = make_double2(-acc[q][2], -acc[q][3]);
-      const double2 a = hard ? mphi : mpsi;
-      const double2 bb = hard ? mpsi : mphi;
-      if (WRITE_A) {
-        if (A) {
-          if (OUT128)
-            reinterpret_cast<double2*>(A)[kq * a_stride + (int64_t)i * ld + i] = a;
-          else
-            reinterpret_cast<float2*>(A)[kq * a_stride + (int64_t)i * ld + i] =
-                make_float2((float)a.x, (float)a.y);
-        }
-        if (diag64) {
-          diag64[(kq * n + i) * 2] = mphi;
-          diag64[(kq * n + i) * 2 + 1] = mpsi;
-        }
+    for (int c = 0; c < 6; ++c) {
+      s[c] = 0.0;
+#pragma unroll
+      for (int v = 0; v < NW; ++v) s[c] += red[v][c][q];
+    }
+    const bool hard = bc[i] == BEM_BC_HARD;
+    const int64_t kq = p.q0 + q;
+    const double2 mphi = make_double2(kFourPi - s[0], -s[1]);
+    const double2 mpsi = make_double2(-s[2], -s[3]);
+    const double2 a = hard ? mphi : mpsi;
+    const double2 bb = hard ? mpsi : mphi;
+    if (FIRST) {
+      if (STORE_A) {
+        if (OUT128)
+          reinterpret_cast<double2*>(A)[kq * a_stride + (int64_t)i * ld + i] = a;
+        else
+          reinterpret_cast<float2*>(A)[kq * a_stride + (int64_t)i * ld + i] =
+              make_float2((float)a.x, (float)a.y);
       }
+      if (diag64) {
+        diag64[(kq * n + i) * 2] = mphi;
+        diag64[(kq * n + i) * 2 + 1] = mpsi;
+      }
+    }
+    if (RHS) {
       const double2 yy = y[(kq * n_rhs + rhs) * n + i];
       const double2 t = cmul(bb, yy);
-      b[(kq * n_rhs + rhs) * n + i] = make_double2(-(acc[q][4] + t.x), -(acc[q][5] + t.y));
+      b[(kq * n_rhs + rhs) * n + i] = make_double2(-(s[4] + t.x), -(s[5] + t.y));
     }
   }
 }
@@ -526,29 +656,30 @@ bem_status launch_assemble(bem_ctx* ctx, const bem_surface* s, int n_k, const do
     for (int r = 0; r < std::max(n_rhs, 1); ++r) {
       const bool first = r == 0;
       const int pi = prof_begin(ctx, "assemble");
-      if (prec == BEM_C128) {
-        if (first)
-          hipLaunchKernelGGL((assemble_kc_kernel<true, true>), grid, dim3(kThreads), 0, ctx->stream,
-                             s->n, s->x, s->nrm, s->w, s->bc, k + k0, nk, n_rhs, r, yk, Ak, ld,
-                             a_stride, bk, dk);
-        else
-          hipLaunchKernelGGL((assemble_kc_kernel<true, false>), grid, dim3(kThreads), 0,
-                             ctx->stream, s->n, s->x, s->nrm, s->w, s->bc, k + k0, nk, n_rhs, r,
-                             yk, Ak, ld, a_stride, bk, dk);
+#define BEM_ASM(O, F, S, R)                                                                       \
+  hipLaunchKernelGGL((assemble_kc_kernel<O, F, S, R>), grid, dim3(kThreads), 0, ctx->stream,      \
+                     s->n, s->x, s->nrm, s->w, s->bc, k + k0, nk, n_rhs, r, yk, Ak, ld, a_stride, \
+                     bk, dk)
+      const bool c128 = prec == BEM_C128;
+      if (!first) {
+        if (c128) BEM_ASM(true, false, false, true); else BEM_ASM(false, false, false, true);
+      } else if (n_rhs == 0) {
+        // no right-hand side: the diagonal (and the matrix) only
+        if (Ak) {
+          if (c128) BEM_ASM(true, true, true, false); else BEM_ASM(false, true, true, false);
+        } else {
+          if (c128) BEM_ASM(true, true, false, false); else BEM_ASM(false, true, false, false);
+        }
+      } else if (Ak) {
+        if (c128) BEM_ASM(true, true, true, true); else BEM_ASM(false, true, true, true);
       } else {
-        if (first)
-          hipLaunchKernelGGL((assemble_kc_kernel<false, true>), grid, dim3(kThreads), 0,
-                             ctx->stream, s->n, s->x, s->nrm, s->w, s->bc, k + k0, nk, n_rhs, r,
-                             yk, Ak, ld, a_stride, bk, dk);
-        else
-          hipLaunchKernelGGL((assemble_kc_kernel<false, false>), grid, dim3(kThreads), 0,
-                             ctx->stream, s->n, s->x, s->nrm, s->w, s->bc, k + k0, nk, n_rhs, r,
-                             yk, Ak, ld, a_stride, bk, dk);
+        if (c128) BEM_ASM(true, true, false, true); else BEM_ASM(false, true, false, true);
       }
+#undef BEM_ASM
       // node pairs evaluated; bytes: matrix written (first pass) + b written
       const double pairs = (double)s->n * s->n * nk;
       prof_end(ctx, "assemble", pi, pairs,
-               (first && A ? (double)esz * s->n * s->n * nk : 0.0) + 16.0 * s->n * nk);
+               (first && A ? (double)esz * s->n * s->n * nk : 0.0) + (n_rhs ? 16.0 * s->n * nk : 0.0));
       BEM_CHECK_LAUNCH(ctx);
     }
   }

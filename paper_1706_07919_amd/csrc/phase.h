@@ -4,18 +4,19 @@
 // and a remainder) and |y| <= pi/4; sin y and cos y by their Taylor series to
 // y^15 and y^16 (the first omitted terms are below 7e-17 and 3e-18 on
 // [-pi/4, pi/4]); the quadrant n mod 4 permutes and signs them.  Larger
-// arguments take the library sincos.
+// arguments take the library sincos (phase_sincos), or are the caller's to
+// route elsewhere (phase_sincos_near, branch-free, for loops whose callers
+// check the range of their arguments up front).
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace bem {
 
-__device__ inline void phase_sincos(double x, double* s, double* c) {
-  if (!(fabs(x) < 1048576.0)) {
-    sincos(x, s, c);
-    return;
-  }
+constexpr double kPhaseNear = 1048576.0;   // 2^20
+
+// Valid for |x| < kPhaseNear only.
+__device__ inline void phase_sincos_near(double x, double* s, double* c) {
   const double n = rint(x * 0.6366197723675814);   // 2/pi
   double y = fma(-n, 1.5707963267341256, x);
   y = fma(-n, 6.077100506303966e-11, y);
@@ -42,6 +43,14 @@ __device__ inline void phase_sincos(double x, double* s, double* c) {
   const double sa = (q & 1) ? cy : sy, ca = (q & 1) ? sy : cy;
   *s = (q & 2) ? -sa : sa;
   *c = ((q + 1) & 2) ? -ca : ca;
+}
+
+__device__ inline void phase_sincos(double x, double* s, double* c) {
+  if (!(fabs(x) < kPhaseNear)) {
+    sincos(x, s, c);
+    return;
+  }
+  phase_sincos_near(x, s, c);
 }
 
 }  // namespace bem

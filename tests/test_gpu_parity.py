@@ -95,6 +95,37 @@ def test_assemble_c128_entries_diag_rhs(ctx, level, kset):
             assert rel(b[q, r], bref) < 1e-12
 
 
+@pytest.mark.parametrize("k", [[0.9, 3.0e5, 3.05e5], [4.0e5, 4.0e5 + 1.0, 4.0e5 + 2.0]],
+                         ids=["scattered", "grid"])
+def test_assemble_phases_past_near_range(ctx, k):
+    """Wavenumbers whose phases k r reach past 2^20 rad: the rows are redone
+    with the library sine and cosine, and the entries, diagonal sums and b
+    still match the oracle (to the phase's own rounding, k ulp(r))."""
+    bodies = mixed_bodies(1)
+    s = Surface(bodies)
+    ds = DeviceSurface.from_bodies(bodies)
+    n = s.n
+    k = np.array(k)
+    nk = len(k)
+    y = seeded_complex(np.random.default_rng(7), (nk, 2, n))
+    A = torch.zeros((nk, n, n), dtype=torch.complex128, device="cuda")
+    b = torch.zeros((nk, 2, n), dtype=torch.complex128, device="cuda")
+    dg = torch.zeros((nk, n, 2), dtype=torch.complex128, device="cuda")
+    native.bem_assemble(ctx, ds.struct, nk, dev(k), 2, dev(y), native.BEM_C128, A, n, b, dg)
+    A, b, dg = A.cpu().numpy(), b.cpu().numpy(), dg.cpu().numpy()
+    assert np.max(k) * np.max(np.linalg.norm(s.x[:, None] - s.x[None], axis=2)) > 2.0 ** 20
+    for q in range(nk):
+        Mphi, Mpsi = bie.operator_matrices(s, k[q])
+        Aref, _ = bie.system(s, k[q], y[q, 0])
+        scale = np.max(np.abs(Aref), axis=1, keepdims=True)
+        assert np.max(np.abs(A[q] - Aref) / scale) < 1e-8
+        assert np.max(np.abs(dg[q, :, 0] - np.diag(Mphi)) / scale[:, 0]) < 1e-6
+        assert np.max(np.abs(dg[q, :, 1] - np.diag(Mpsi)) / scale[:, 0]) < 1e-6
+        for r in range(2):
+            _, bref = bie.system(s, k[q], y[q, r])
+            assert rel(b[q, r], bref) < 1e-6
+
+
 def test_assemble_c64_is_rounded_fp64(ctx):
     bodies = mixed_bodies(2)
     s = Surface(bodies)
