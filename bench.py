@@ -397,7 +397,7 @@ def main():
                                       "24 MNK per complex update) over the HIP-event time of every "
                                       "launch of the run",
                      "traffic": measured_traffic(gname, args.nb or (tuned[0] if tuned else "default"),
-                                                 gl),
+                                                 gb / max(gl, 1)),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                      "scaled by a copy kernel)",
                      "algorithmic_bytes_per_launch": gb / max(gl, 1),
@@ -976,11 +976,12 @@ def kernel_source_sha256(kernel="gemm_3m"):
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
-def measured_traffic(kernel, block_width="default", launches=None, profiles=None):
+def measured_traffic(kernel, block_width="default", alg_bytes_per_launch=None, profiles=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, or None when there is none, the kernel's source changed since the
-    counters were taken, or the factorisation's block width or the number of
-    launches in the run differs (they set the mix of launch sizes)."""
+    counters were taken, or the factorisation's block width or the mix of
+    launch sizes differs (the mix is identified by the algorithmic bytes per
+    launch, which every step of the sweep repeats)."""
     path = os.path.join(profiles or os.path.join(ROOT, "profiles"),
                         f"pmc_{kernel}_two_spheres_N5124_nk512.txt")
     if not os.path.exists(path) or kernel not in KERNEL_SECTIONS:
@@ -993,8 +994,10 @@ def measured_traffic(kernel, block_width="default", launches=None, profiles=None
     if vals.get("kernel_source_sha256") != kernel_source_sha256(kernel) or \
             vals.get("block_width") != str(block_width) or "traffic_bytes_per_launch" not in vals:
         return None
-    if launches is not None and vals.get("launches_in_run") != str(launches):
-        return None
+    if alg_bytes_per_launch is not None:
+        ref = float(vals.get("algorithmic_bytes_per_launch", "nan"))
+        if not abs(alg_bytes_per_launch - ref) <= 1e-3 * ref:
+            return None
     return float(vals["traffic_bytes_per_launch"])
 
 

@@ -368,7 +368,8 @@ bem_status bem_split_unknowns(bem_ctx* ctx, const bem_surface* s, int32_t n_k, i
  *   inside[m] [dev] uint8 output
  *   U [dev] [n_rhs][m][n_k], c64 (float32 kernel) or c128 (float64 kernel)
  * Both kernels take the per-node sums S(x_i0) in float64.  The float32
- * kernel sorts the outside points by i0 (counting sort), forms the brackets
+ * kernel sorts the outside points by i0 (counting sort), takes the node sums
+ * of the nodes that are some point's i0 only, forms the brackets
  * w_j u_j, w_j u'_j once per node i0 and node tile (float64, rounded to
  * float32) and sums each point's terms in float32 in sixteen interleaved
  * partial sums; P is assembled in float64. */
@@ -383,9 +384,10 @@ bem_status bem_field_eval(bem_ctx* ctx, const bem_surface* s, int32_t n_k, const
  * events; the scratch that bem_field_eval takes from the context's workspace
  * comes from a fixed 32 MiB device array of the library instead: the float64
  * per-node sums S(x_a) (n_rhs * n_k * n * 16 bytes) and, for BEM_C64, the
- * grouping of the points by closest node (about 4.5 m + 32 n bytes); calls
+ * grouping of the points by closest node (about 4.5 m + 40 n bytes); calls
  * needing more than 32 MiB return BEM_EINVAL before any launch (e.g. n = 5124
- * nodes, one right-hand side: 409 frequencies with a few thousand points).  Arguments, results and ordering are those of
+ * nodes, one right-hand side, 4096 points: 409 frequencies for BEM_C128, 406 for
+ * BEM_C64).  Arguments, results and ordering are those of
  * bem_field_eval (same kernels, same results bit for bit).  Every context on a device shares
  * that device's array, which keeps the last call's contents (nothing in it
  * needs to start at zero): calls that overlap on one device (different

@@ -125,7 +125,9 @@ __device__ inline R part_sum(R v) {
   return v;
 }
 
-// MODE 0: write S(x_p) for points = nodes (raw, [rhs][n_k][n]).
+// MODE 0: write S(x_p) for points = nodes (raw, [rhs][n_k][n]); with a node
+// list (nlist, its length at *ncount), point p is node nlist[p] and only the
+// listed nodes are written.
 // MODE 1: write P(x_p) = phi_a + (S(x_p) - S(x_a)) / (4 pi) into U[rhs][m][n_k].
 // Right-hand sides blockIdx.z * NR + r, r < min(NR, n_rhs - blockIdx.z * NR).
 template <typename R, int FCH, int MODE, int NR>
@@ -135,8 +137,13 @@ __global__ __launch_bounds__(kFT, sizeof(R) == 4 ? 3 : 1) void field_kernel(
     const double2* __restrict__ phi, const double2* __restrict__ psi, int m,
     const double* __restrict__ xp, const int32_t* __restrict__ i0,
     const uint8_t* __restrict__ inside, typename CX<R>::T* __restrict__ Snode,
-    typename CX<R>::T* __restrict__ U) {
+    typename CX<R>::T* __restrict__ U, const int32_t* __restrict__ nlist = nullptr,
+    const int32_t* __restrict__ ncount = nullptr) {
   using C = typename CX<R>::T;
+  if (MODE == 0 && nlist) {
+    m = *ncount;
+    if ((int)blockIdx.x * kPW >= m) return;   // the whole workgroup
+  }
   __shared__ double sx[kNJ][3];
   __shared__ double sn[kNJ][3];
   __shared__ R sw[kNJ];
@@ -149,9 +156,10 @@ __global__ __launch_bounds__(kFT, sizeof(R) == 4 ? 3 : 1) void field_kernel(
   const int nrh = min(NR, n_rhs - r0);
   const int nf = min(FCH, n_k - m0);
   const bool valid = p < m && (MODE == 0 || !inside[p]);
-  const int a = p < m ? (MODE == 0 ? p : i0[p]) : 0;
-  const double px = p < m ? xp[3 * p] : 0.0, py = p < m ? xp[3 * p + 1] : 0.0,
-               pz = p < m ? xp[3 * p + 2] : 0.0;
+  const int a = p < m ? (MODE == 0 ? (nlist ? nlist[p] : p) : i0[p]) : 0;
+  const int pc = MODE == 0 ? a : p;   // the point's coordinates
+  const double px = p < m ? xp[3 * pc] : 0.0, py = p < m ? xp[3 * pc + 1] : 0.0,
+               pz = p < m ? xp[3 * pc + 2] : 0.0;
   const double ax = x[3 * a], ay = x[3 * a + 1], az = x[3 * a + 2];
   const double anx = nrm[3 * a], any = nrm[3 * a + 1], anz = nrm[3 * a + 2];
   double kk[FCH];
@@ -336,42 +344,51 @@ __global__ void group_count_kernel(int m, const int32_t* __restrict__ i0,
 }
 
 // one workgroup of 1024 threads: off = exclusive scan of cnt, choff =
-// exclusive scan of ceil(cnt / kGP), both with their totals at [n]
+// exclusive scan of ceil(cnt / kGP), uoff = exclusive scan of (cnt > 0), all
+// with their totals at [n]
 __global__ __launch_bounds__(1024) void group_scan_kernel(int n, const int32_t* __restrict__ cnt,
                                                           int32_t* __restrict__ off,
-                                                          int32_t* __restrict__ choff) {
-  __shared__ int32_t sa[1024], sb[1024];
-  __shared__ int32_t carry[2];
-  if (threadIdx.x == 0) carry[0] = carry[1] = 0;
+                                                          int32_t* __restrict__ choff,
+                                                          int32_t* __restrict__ uoff) {
+  __shared__ int32_t sa[1024], sb[1024], sc[1024];
+  __shared__ int32_t carry[3];
+  if (threadIdx.x == 0) carry[0] = carry[1] = carry[2] = 0;
   __syncthreads();
   for (int b0 = 0; b0 < n; b0 += 1024) {
     const int i = b0 + threadIdx.x;
     const int c = i < n ? cnt[i] : 0;
+    const int u = c > 0;
     sa[threadIdx.x] = c;
     sb[threadIdx.x] = (c + kGP - 1) / kGP;
+    sc[threadIdx.x] = u;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {   // inclusive scans (Hillis-Steele)
       const int va = threadIdx.x >= o ? sa[threadIdx.x - o] : 0;
       const int vb = threadIdx.x >= o ? sb[threadIdx.x - o] : 0;
+      const int vc = threadIdx.x >= o ? sc[threadIdx.x - o] : 0;
       __syncthreads();
       sa[threadIdx.x] += va;
       sb[threadIdx.x] += vb;
+      sc[threadIdx.x] += vc;
       __syncthreads();
     }
     if (i < n) {
       off[i] = carry[0] + sa[threadIdx.x] - c;
       choff[i] = carry[1] + sb[threadIdx.x] - (c + kGP - 1) / kGP;
+      uoff[i] = carry[2] + sc[threadIdx.x] - u;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
       carry[0] += sa[1023];
       carry[1] += sb[1023];
+      carry[2] += sc[1023];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     off[n] = carry[0];
     choff[n] = carry[1];
+    uoff[n] = carry[2];
   }
 }
 
@@ -387,12 +404,15 @@ __global__ void group_scatter_kernel(int m, const int32_t* __restrict__ i0,
   perm[off[a] + atomicAdd(&fill[a], 1)] = p;
 }
 
-// chunks[c] = (node, first index into perm, points), kGP points at most
+// chunks[c] = (node, first index into perm, points), kGP points at most;
+// used[uoff[a]] = a for the nodes that are some point's closest node
 __global__ void group_chunks_kernel(int n, const int32_t* __restrict__ cnt,
                                     const int32_t* __restrict__ off,
-                                    const int32_t* __restrict__ choff, int4* __restrict__ chunks) {
+                                    const int32_t* __restrict__ choff, int4* __restrict__ chunks,
+                                    const int32_t* __restrict__ uoff, int32_t* __restrict__ used) {
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= n) return;
+  if (cnt[a] > 0) used[uoff[a]] = a;
   const int c0 = choff[a], nc = choff[a + 1] - c0;
   for (int c = 0; c < nc; ++c)
     chunks[c0 + c] = make_int4(a, off[a] + c * kGP, min(kGP, cnt[a] - c * kGP), 0);
@@ -573,34 +593,38 @@ bem_status field_grouped(bem_ctx* ctx, const bem_surface* s, int n_k, const doub
   int32_t* fill = (int32_t*)q;  q += al(4 * (size_t)n);
   int32_t* off = (int32_t*)q;   q += al(4 * (size_t)(n + 1));
   int32_t* choff = (int32_t*)q; q += al(4 * (size_t)(n + 1));
+  int32_t* uoff = (int32_t*)q;  q += al(4 * (size_t)(n + 1));
+  int32_t* used = (int32_t*)q;  q += al(4 * (size_t)n);
   int32_t* perm = (int32_t*)q;  q += al(4 * (size_t)m);
   int4* chunks = (int4*)q;
   if ((st = fill_zero(ctx, cnt, 2 * al(4 * (size_t)n))) != BEM_OK) return st;   // cnt and fill
   const int pi = fixed ? -1 : prof_begin(ctx, "field");
-  // float64 node sums S(x_a) of every node (the n x n_k x n terms of the node
-  // pass, about 1/200 of the points' terms at a million points)
-  {
-    const int fch = (n_k + 7) / 8;
-    const int nz = (n_rhs + NR - 1) / NR;
-    dim3 gnode((n + kPW - 1) / kPW, fch, nz);
-    if (NR == 1)
-      hipLaunchKernelGGL((field_kernel<double, 8, 0, 1>), gnode, dim3(kFT), 0, ctx->stream, n, s->x,
-                         s->nrm, s->w, k, n_k, n_rhs, (const double2*)phi, (const double2*)psi, n,
-                         s->x, (const int32_t*)nullptr, (const uint8_t*)nullptr, Snode,
-                         (double2*)nullptr);
-    else
-      hipLaunchKernelGGL((field_kernel<double, 4, 0, 4>), dim3((n + kPW - 1) / kPW, (n_k + 3) / 4, nz),
-                         dim3(kFT), 0, ctx->stream, n, s->x, s->nrm, s->w, k, n_k, n_rhs,
-                         (const double2*)phi, (const double2*)psi, n, s->x,
-                         (const int32_t*)nullptr, (const uint8_t*)nullptr, Snode, (double2*)nullptr);
-  }
   hipLaunchKernelGGL(group_count_kernel, dim3((m + 255) / 256), dim3(256), 0, ctx->stream, m, i0,
                      inside, cnt);
-  hipLaunchKernelGGL(group_scan_kernel, dim3(1), dim3(1024), 0, ctx->stream, n, cnt, off, choff);
+  hipLaunchKernelGGL(group_scan_kernel, dim3(1), dim3(1024), 0, ctx->stream, n, cnt, off, choff,
+                     uoff);
+  hipLaunchKernelGGL(group_chunks_kernel, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, n, cnt,
+                     off, choff, chunks, uoff, used);
+  // float64 node sums S(x_a) of the nodes that are some point's closest node
+  // (their count uoff[n] stays on the device: the grid covers all n nodes and
+  // the workgroups past the count return at once)
+  {
+    const int nz = (n_rhs + NR - 1) / NR;
+    if (NR == 1)
+      hipLaunchKernelGGL((field_kernel<double, 8, 0, 1>),
+                         dim3((n + kPW - 1) / kPW, (n_k + 7) / 8, nz), dim3(kFT), 0, ctx->stream,
+                         n, s->x, s->nrm, s->w, k, n_k, n_rhs, (const double2*)phi,
+                         (const double2*)psi, n, s->x, (const int32_t*)nullptr,
+                         (const uint8_t*)nullptr, Snode, (double2*)nullptr, used, uoff + n);
+    else
+      hipLaunchKernelGGL((field_kernel<double, 4, 0, 4>),
+                         dim3((n + kPW - 1) / kPW, (n_k + 3) / 4, nz), dim3(kFT), 0, ctx->stream,
+                         n, s->x, s->nrm, s->w, k, n_k, n_rhs, (const double2*)phi,
+                         (const double2*)psi, n, s->x, (const int32_t*)nullptr,
+                         (const uint8_t*)nullptr, Snode, (double2*)nullptr, used, uoff + n);
+  }
   hipLaunchKernelGGL(group_scatter_kernel, dim3((m + 255) / 256), dim3(256), 0, ctx->stream, m, i0,
                      inside, off, fill, perm);
-  hipLaunchKernelGGL(group_chunks_kernel, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, n, cnt,
-                     off, choff, chunks);
   const int64_t tot = (int64_t)m * n_k * n_rhs;
   hipLaunchKernelGGL(zero_inside_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
                      ctx->stream, m, n_k, n_rhs, inside, (float2*)U);
@@ -608,9 +632,10 @@ bem_status field_grouped(bem_ctx* ctx, const bem_surface* s, int n_k, const doub
   hipLaunchKernelGGL((field_grouped_kernel<FCH, NR>), grid, dim3(kFT), 0, ctx->stream, n, s->x,
                      s->nrm, s->w, k, n_k, n_rhs, (const double2*)phi, (const double2*)psi, m, xp,
                      chunks, choff + n, perm, Snode, (float2*)U);
-  // kernel terms: one per (point or node, frequency, node, rhs)
+  // kernel terms: one per (point, frequency, node, rhs); the node pass adds
+  // as many per node used as some point's closest node
   if (!fixed)
-    prof_end(ctx, "field", pi, ((double)m + n) * n_k * n * n_rhs, 8.0 * (double)m * n_k * n_rhs);
+    prof_end(ctx, "field", pi, (double)m * n_k * n * n_rhs, 8.0 * (double)m * n_k * n_rhs);
   BEM_CHECK_LAUNCH(ctx);
   return BEM_OK;
 }
@@ -728,8 +753,8 @@ bem_status field_scratch_init(bem_ctx* ctx) {
 
 size_t field_group_bytes(int n, int m, int n_k, int n_rhs) {
   const size_t max_chunks = (size_t)(m + kGP - 1) / kGP + n;
-  return al256(16 * (size_t)n_rhs * n_k * n) + 2 * al256(4 * (size_t)n) +
-         2 * al256(4 * (size_t)(n + 1)) + al256(4 * (size_t)m) + al256(16 * max_chunks);
+  return al256(16 * (size_t)n_rhs * n_k * n) + 3 * al256(4 * (size_t)n) +
+         3 * al256(4 * (size_t)(n + 1)) + al256(4 * (size_t)m) + al256(16 * max_chunks);
 }
 
 }  // namespace bem

@@ -1,6 +1,7 @@
 """CPU checks of bench.py's command line: one GPU only, and the HBM-traffic
 figure is reported only while the profiled kernel's source, the block width
-and the number of launches in the run are those the counters were taken with."""
+and the mix of launch sizes (the algorithmic bytes per launch) are those the
+counters were taken with."""
 import os
 import subprocess
 import sys
@@ -15,20 +16,22 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr and r.stdout == ""
 
 
-def test_traffic_gated_by_source_hash_width_and_launch_count(tmp_path):
+def test_traffic_gated_by_source_hash_width_and_launch_mix(tmp_path):
     sys.path.insert(0, ROOT)
     import bench
     sha = bench.kernel_source_sha256("gemm_3m")
     assert len(sha) == 64
     (tmp_path / "pmc_gemm_3m_two_spheres_N5124_nk512.txt").write_text(
-        f"kernel_source_sha256: {sha}\nblock_width: default\nlaunches_in_run: 777\n"
+        f"kernel_source_sha256: {sha}\nblock_width: default\nalgorithmic_bytes_per_launch: 3.909e9\n"
         "traffic_bytes_per_launch: 1.5e9\n")
     d = str(tmp_path)
-    assert bench.measured_traffic("gemm_3m", "default", 777, profiles=d) == 1.5e9
-    assert bench.measured_traffic("gemm_3m", 256, 777, profiles=d) is None
-    assert bench.measured_traffic("gemm_3m", "default", 778, profiles=d) is None
-    assert bench.measured_traffic("gemm_c32", "default", 777, profiles=d) is None
+    assert bench.measured_traffic("gemm_3m", "default", 3.9093e9, profiles=d) == 1.5e9
+    assert bench.measured_traffic("gemm_3m", 256, 3.909e9, profiles=d) is None
+    assert bench.measured_traffic("gemm_3m", "default", 3.92e9, profiles=d) is None
+    assert bench.measured_traffic("gemm_c32", "default", 3.909e9, profiles=d) is None
     (tmp_path / "pmc_gemm_3m_two_spheres_N5124_nk512.txt").write_text(
-        "kernel_source_sha256: 00\nblock_width: default\nlaunches_in_run: 777\n"
+        "kernel_source_sha256: 00\nblock_width: default\nalgorithmic_bytes_per_launch: 3.909e9\n"
         "traffic_bytes_per_launch: 1.5e9\n")
-    assert bench.measured_traffic("gemm_3m", "default", 777, profiles=d) is None
+    assert bench.measured_traffic("gemm_3m", "default", 3.909e9, profiles=d) is None
+    # the committed summary applies to the default sweep's mix
+    assert bench.measured_traffic("gemm_3m", "default", 3.909040e9) is not None

@@ -126,6 +126,28 @@ def test_assemble_phases_past_near_range(ctx, k):
             assert rel(b[q, r], bref) < 1e-6
 
 
+def test_assemble_without_rhs(ctx):
+    """No right-hand side (y and b NULL): the matrix and the diagonal only,
+    equal to the oracle's; nothing reads y or writes b."""
+    bodies = mixed_bodies(1)
+    s = Surface(bodies)
+    ds = DeviceSurface.from_bodies(bodies)
+    n = s.n
+    k = K_SETS["grid"]
+    nk = len(k)
+    A = torch.zeros((nk, n, n), dtype=torch.complex128, device="cuda")
+    dg = torch.zeros((nk, n, 2), dtype=torch.complex128, device="cuda")
+    native.bem_assemble(ctx, ds.struct, nk, dev(k), 0, None, native.BEM_C128, A, n, None, dg)
+    A, dg = A.cpu().numpy(), dg.cpu().numpy()
+    for q in range(nk):
+        Mphi, Mpsi = bie.operator_matrices(s, k[q])
+        Aref = np.where((s.bc == HARD)[None, :], Mphi, Mpsi)
+        scale = np.max(np.abs(Aref), axis=1, keepdims=True)
+        assert np.max(np.abs(A[q] - Aref) / scale) < 1e-12
+        assert np.max(np.abs(dg[q, :, 0] - np.diag(Mphi))) < 1e-11
+        assert np.max(np.abs(dg[q, :, 1] - np.diag(Mpsi))) < 1e-11
+
+
 def test_assemble_c64_is_rounded_fp64(ctx):
     bodies = mixed_bodies(2)
     s = Surface(bodies)
