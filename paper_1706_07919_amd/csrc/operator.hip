@@ -197,10 +197,16 @@ __device__ inline double2 phase_e(double x) {
 // acc[q] = {Dphi re, im, Dpsi re, im, b re, im}.
 template <int KC, bool OUT128, bool WRITE_A, bool RHS, int PH>
 __device__ __forceinline__ void pair_terms(const AsmRow& p, const KChunk<KC>& kc,
-                                           const double (&kinv)[KC], int j, bool hard, double r,
+                                           int j, bool hard, double r,
                                            double s0, double wr, double wq, double nn,
                                            double (&acc)[KC][6]) {
   double2 E = phase_e<PH>(kc.k[0] * r), F = phase_e<PH>(kc.k[0] * s0), dE, dF;
+  // row bases of A and y for wavenumber q0 and their steps per wavenumber,
+  // made opaque here so that the per-wavenumber addresses are formed in the
+  // loop rather than held in scalar registers across it
+  int64_t abase = (int64_t)p.q0 * p.a_stride + (int64_t)p.i * p.ld, astep = p.a_stride;
+  int64_t ybase = ((int64_t)p.q0 * p.n_rhs + p.rhs) * p.n, ystep = (int64_t)p.n_rhs * p.n;
+  asm volatile("" : "+s"(abase), "+s"(astep), "+s"(ybase), "+s"(ystep));
   if (PH == kPhRec) {
     dE = phase_e<PH>(kc.dk * r);
     dF = phase_e<PH>(kc.dk * s0);
@@ -222,26 +228,27 @@ __device__ __forceinline__ void pair_terms(const AsmRow& p, const KChunk<KC>& kc
     // w G = w E / r,  w H = w E (ikr - 1)(d.n_j) / r^3
     const double2 wG = make_double2(wr * E.x, wr * E.y);
     const double2 wH = make_double2(wq * fma(-kr, E.y, -E.x), wq * fma(kr, E.x, -E.y));
-    // g = cos(k s0), f = sin(k s0)/k, g' = -k sin(k s0) nn, f' = cos(k s0) nn
-    const double g = F.x, f = F.y * kinv[q], gp = -(k * nn) * F.y, fp = F.x * nn;
+    // g = cos(k s0), f = sin(k s0)/k, g' = -k sin(k s0) nn, f' = cos(k s0) nn;
+    // the psi sums are accumulated times k (k f' wG - k f wH, divided by k at
+    // the end)
+    const double kn = k * nn;
+    const double g = F.x, gp = -kn * F.y, kfp = kn * F.x;
     acc[q][0] = fma(gp, wG.x, fma(-g, wH.x, acc[q][0]));
     acc[q][1] = fma(gp, wG.y, fma(-g, wH.y, acc[q][1]));
-    acc[q][2] = fma(fp, wG.x, fma(-f, wH.x, acc[q][2]));
-    acc[q][3] = fma(fp, wG.y, fma(-f, wH.y, acc[q][3]));
+    acc[q][2] = fma(kfp, wG.x, fma(-F.y, wH.x, acc[q][2]));
+    acc[q][3] = fma(kfp, wG.y, fma(-F.y, wH.y, acc[q][3]));
     // unknown coefficient a (M_phi = -w H for a hard node, M_psi = w G for a
     // soft one) and known coefficient bb (the other)
     const double2 mwH = make_double2(-wH.x, -wH.y);
     const double2 a = hard ? mwH : wG, bb = hard ? wG : mwH;
-    const int64_t kq = p.q0 + q;
     if (WRITE_A) {
       if (OUT128)
-        reinterpret_cast<double2*>(p.A)[kq * p.a_stride + (int64_t)p.i * p.ld + j] = a;
+        reinterpret_cast<double2*>(p.A)[abase + q * astep + j] = a;
       else
-        reinterpret_cast<float2*>(p.A)[kq * p.a_stride + (int64_t)p.i * p.ld + j] =
-            make_float2((float)a.x, (float)a.y);
+        reinterpret_cast<float2*>(p.A)[abase + q * astep + j] = make_float2((float)a.x, (float)a.y);
     }
     if (RHS) {
-      const double2 yy = p.y[(kq * p.n_rhs + p.rhs) * p.n + j];
+      const double2 yy = p.y[ybase + q * ystep + j];
       acc[q][4] = fma(bb.x, yy.x, fma(-bb.y, yy.y, acc[q][4]));
       acc[q][5] = fma(bb.x, yy.y, fma(bb.y, yy.x, acc[q][5]));
     }
@@ -252,7 +259,7 @@ __device__ __forceinline__ void pair_terms(const AsmRow& p, const KChunk<KC>& kc
 // pairs reaches 2^20 rad (the near forms are then invalid for the row).
 template <int KC, bool OUT128, bool WRITE_A, bool RHS, int PH>
 __device__ __forceinline__ bool row_terms(const AsmRow& p, const KChunk<KC>& kc,
-                                          const double (&kinv)[KC], double kmax,
+                                          double kmax,
                                           const double* __restrict__ x,
                                           const double* __restrict__ nrm,
                                           const double* __restrict__ w,
@@ -274,7 +281,7 @@ __device__ __forceinline__ bool row_terms(const AsmRow& p, const KChunk<KC>& kc,
     const double nn = nix * njx + niy * njy + niz * njz;
     const bool hard = bc[j] == BEM_BC_HARD;
     if (PH != kPhWide) wide |= !(kmax * fmax(r, fabs(s0)) < kPhaseNear);
-    pair_terms<KC, OUT128, WRITE_A, RHS, PH>(p, kc, kinv, j, hard, r, s0, wr, wq, nn, acc);
+    pair_terms<KC, OUT128, WRITE_A, RHS, PH>(p, kc, j, hard, r, s0, wr, wq, nn, acc);
   }
   return wide;
 }
@@ -294,9 +301,6 @@ __global__ __launch_bounds__(kThreads, 2) void assemble_kc_kernel(
   const int i = blockIdx.x;
   KChunk<KC> kc = load_chunk<KC>(kv, nk, nullptr);
   kc.dk = uniform_d(kc.dk);
-  double kinv[KC];
-#pragma unroll
-  for (int q = 0; q < KC; ++q) kinv[q] = uniform_d(q < kc.kc ? 1.0 / kc.k[q] : 0.0);
   double kmax = 0.0;
 #pragma unroll
   for (int q = 0; q < KC; ++q) kmax = fmax(kmax, fabs(kc.k[q]));
@@ -309,9 +313,9 @@ __global__ __launch_bounds__(kThreads, 2) void assemble_kc_kernel(
   constexpr bool WA = FIRST && STORE_A;
   bool wide;
   if (kc.uniform)
-    wide = row_terms<KC, OUT128, WA, RHS, kPhRec>(p, kc, kinv, kmax, x, nrm, w, bc, acc);
+    wide = row_terms<KC, OUT128, WA, RHS, kPhRec>(p, kc, kmax, x, nrm, w, bc, acc);
   else
-    wide = row_terms<KC, OUT128, WA, RHS, kPhNear>(p, kc, kinv, kmax, x, nrm, w, bc, acc);
+    wide = row_terms<KC, OUT128, WA, RHS, kPhNear>(p, kc, kmax, x, nrm, w, bc, acc);
   // workgroup sums: per component c, the wave sums of the 8 wavenumbers by
   // recursive halving (lanes 8q..8q+7 end with wavenumber q), then the waves
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -334,10 +338,9 @@ __global__ __launch_bounds__(kThreads, 2) void assemble_kc_kernel(
       k1.dk = 0.0;
       k1.kc = 1;
       k1.uniform = false;
-      const double kinv1[1] = {kinv[q]};
       AsmRow p1 = p;
       p1.q0 = p.q0 + q;
-      (void)row_terms<1, OUT128, WA, RHS, kPhWide>(p1, k1, kinv1, kmax, x, nrm, w, bc, a1);
+      (void)row_terms<1, OUT128, WA, RHS, kPhWide>(p1, k1, kmax, x, nrm, w, bc, a1);
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
         const double v = wave_sum(a1[0][c]);
@@ -357,8 +360,9 @@ __global__ __launch_bounds__(kThreads, 2) void assemble_kc_kernel(
     }
     const bool hard = bc[i] == BEM_BC_HARD;
     const int64_t kq = p.q0 + q;
+    const double kval = kv[kq];   // (the psi sums were accumulated times k)
     const double2 mphi = make_double2(kFourPi - s[0], -s[1]);
-    const double2 mpsi = make_double2(-s[2], -s[3]);
+    const double2 mpsi = make_double2(-s[2] / kval, -s[3] / kval);
     const double2 a = hard ? mphi : mpsi;
     const double2 bb = hard ? mpsi : mphi;
     if (FIRST) {
