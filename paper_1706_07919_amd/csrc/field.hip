@@ -508,19 +508,16 @@ __global__ __launch_bounds__(kFT, 3) void field_grouped_kernel(
       const double dx = sx[jj][0] - px, dy = sx[jj][1] - py, dz = sx[jj][2] - pz;
       const double r = sqrt(dx * dx + dy * dy + dz * dz);
       const float rinv = __builtin_amdgcn_rcpf((float)r);
-      const float dn = ((float)dx * snrm[jj][0] + (float)dy * snrm[jj][1] + (float)dz * snrm[jj][2]) *
-                       (rinv * rinv * rinv);   // (d.n_j)/r^3
+      // u H - v G = E' t with E' = -E / r (rotated like E) and
+      // t = c u (1 - ikr) + v, c = (d.n_j)/r^2
+      const float c = ((float)dx * snrm[jj][0] + (float)dy * snrm[jj][1] + (float)dz * snrm[jj][2]) *
+                      (rinv * rinv);
       float es, ec, des = 0.f, dec = 1.f;
       phase<float>(kk[0] * r, es, ec);
       if (uni) phase<float>(dkk * r, des, dec);
-      const float rf = (float)r;
-      // one right-hand side: u H - v G = E' t with E' = -E / r and
-      // t = c u (1 - ikr) + v, c = (d.n)/r^2; E' is rotated like E
-      const float c = dn * rf, cr = c * rf;
-      if constexpr (NR == 1) {
-        es *= -rinv;
-        ec *= -rinv;
-      }
+      const float cr = c * (float)r;
+      es *= -rinv;
+      ec *= -rinv;
 #pragma unroll
       for (int f = 0; f < FCH; ++f) {
         if (f > 0) {
@@ -530,32 +527,19 @@ __global__ __launch_bounds__(kFT, 3) void field_grouped_kernel(
             ec = e0;
           } else {
             phase<float>(kk[f] * r, es, ec);
-            if constexpr (NR == 1) {
-              es *= -rinv;
-              ec *= -rinv;
-            }
+            es *= -rinv;
+            ec *= -rinv;
           }
         }
-        if constexpr (NR == 1) {
-          const float cq = (float)kk[f] * cr;   // c k r
-          const float2 u = su[0][f][jj], v = sv[0][f][jj];
+        const float cq = (float)kk[f] * cr;   // c k r
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr) {
+          if (rr >= nrh) break;   // uniform
+          const float2 u = su[rr][f][jj], v = sv[rr][f][jj];
           const float tx = fmaf(c, u.x, fmaf(cq, u.y, v.x));
           const float ty = fmaf(c, u.y, fmaf(-cq, u.x, v.y));
-          Sh[0][f].x = fmaf(ec, tx, fmaf(-es, ty, Sh[0][f].x));
-          Sh[0][f].y = fmaf(ec, ty, fmaf(es, tx, Sh[0][f].y));
-        } else {
-          // G = E / r ; H = E (ikr - 1) (d.n) / r^3, shared by the
-          // right-hand sides
-          const float gr = ec * rinv, gi = es * rinv;
-          const float kr = (float)kk[f] * rf;
-          const float hr = (-ec - kr * es) * dn, hi = (kr * ec - es) * dn;
-#pragma unroll
-          for (int rr = 0; rr < NR; ++rr) {
-            if (rr >= nrh) break;   // uniform
-            const float2 u = su[rr][f][jj], v = sv[rr][f][jj];
-            Sh[rr][f].x += (u.x * hr - u.y * hi) - (v.x * gr - v.y * gi);
-            Sh[rr][f].y += (u.x * hi + u.y * hr) - (v.x * gi + v.y * gr);
-          }
+          Sh[rr][f].x = fmaf(ec, tx, fmaf(-es, ty, Sh[rr][f].x));
+          Sh[rr][f].y = fmaf(ec, ty, fmaf(es, tx, Sh[rr][f].y));
         }
       }
     };
