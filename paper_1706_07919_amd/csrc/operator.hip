@@ -158,13 +158,13 @@ struct Phase {
 // j = t + 256 m; per pair it forms the geometry and the starting phases once
 // and then, for each wavenumber of the chunk, the two kernels w G and w H,
 // their contributions to the two diagonal sums and to b, and the matrix entry
-// (WRITE_A: first pass; later passes only form b for further right-hand
-// sides).  The pair loop is instantiated per phase form: the recurrence on an
-// even grid or a sincos per wavenumber, both with the branch-free reduction
-// valid below 2^20 rad, and the library sincos for a row whose phases reach
-// beyond (taken only when a pair of the row needs it: the whole row is then
-// redone).  The per-thread sums are reduced across the workgroup once, at the
-// end.
+// (first pass over the right-hand sides; later passes only form b).  The pair
+// loop is instantiated per phase form: the recurrence on an even grid or a
+// sincos per wavenumber, both with the branch-free reduction valid below
+// 2^20 rad, and the library sincos for a row whose phases reach beyond (taken
+// only when a pair of the row needs it: the whole row is then redone, one
+// wavenumber at a time).  The per-thread sums are reduced across the
+// workgroup once, at the end.
 enum { kPhRec = 0, kPhNear = 1, kPhWide = 2 };
 
 // A wave-uniform double moved to scalar registers.
