@@ -71,8 +71,8 @@ class KernelTotals:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n-k", type=int, default=512)
     ap.add_argument("--field-grid", type=int, default=64, help="points per side on x = 0")
     ap.add_argument("--fp64-every", type=int, default=8,
