@@ -158,6 +158,7 @@ bem_status bem_assemble(bem_ctx* ctx, const bem_surface* s, int32_t n_k, const d
                         void* b, void* diag64);
 
 /* r = b - A x for the float64 operator regenerated on the fly (matrix-free):
+ *   k[n_k] [dev] (> 0, checked: BEM_EINVAL otherwise),
  *   x[n_k][n_rhs][n] c128 unknowns [dev], y as for bem_assemble,
  *   diag64 from bem_assemble [dev], r[n_k][n_rhs][n] c128 [dev] (output). */
 bem_status bem_residual(bem_ctx* ctx, const bem_surface* s, int32_t n_k, const double* k,
@@ -166,8 +167,8 @@ bem_status bem_residual(bem_ctx* ctx, const bem_surface* s, int32_t n_k, const d
 
 /* Relative residual of given unknowns: rel[q] = ||b - A x||_2 / ||b||_2 per
  * (wavenumber, rhs) with the float64 operator (the acceptance test of
- * predicted solutions).  x, y [dev] c128 [n_k][n_rhs][n]; rel [host]
- * double[n_k*n_rhs].  Synchronises the stream. */
+ * predicted solutions).  k [dev] (> 0, checked); x, y [dev] c128
+ * [n_k][n_rhs][n]; rel [host] double[n_k*n_rhs].  Synchronises the stream. */
 bem_status bem_residual_check(bem_ctx* ctx, const bem_surface* s, int32_t n_k, const double* k,
                               int32_t n_rhs, const void* y, const void* x, double* rel);
 
@@ -342,8 +343,9 @@ bem_status bem_lu_tuned_plan(bem_ctx* ctx, bem_prec prec, int32_t n, int32_t gem
  * dense frequency grid, starting from a predicted solution.
  *   LU [dev] c64 factors from bem_getrf_batched, n_fac sets of [n][ld] with
  *   stride; piv [dev] [n_fac][n]; fac_index [dev] int32[n_k] factor set used
- *   for each wavenumber; x [dev] c128 [n_k][n_rhs][n] initial guess, refined
- *   in place; info [host] [n_k*n_rhs] or NULL.  Synchronises the stream. */
+ *   for each wavenumber; k [dev] (> 0, checked); x [dev] c128
+ *   [n_k][n_rhs][n] initial guess, refined in place; info [host] [n_k*n_rhs]
+ *   or NULL.  Synchronises the stream. */
 bem_status bem_refine_batched(bem_ctx* ctx, const bem_surface* s, int32_t n_k, const double* k,
                               int32_t n_rhs, const void* y, const void* LU, int32_t ld,
                               int64_t stride, const int32_t* piv, int32_t n_fac,

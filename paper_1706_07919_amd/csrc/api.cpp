@@ -366,6 +366,7 @@ extern "C" bem_status bem_residual(bem_ctx* ctx, const bem_surface* s, int32_t n
   if (n_k <= 0 || !k || n_rhs <= 0 || !y || !x || !diag64 || !r)
     return fail(ctx, BEM_EINVAL, "bem_residual: bad argument");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
+  if ((st = check_k(ctx, n_k, k)) != BEM_OK) return st;
   return launch_residual(ctx, s, n_k, k, n_rhs, y, x, diag64, r);
 }
 
@@ -378,6 +379,7 @@ extern "C" bem_status bem_residual_check(bem_ctx* ctx, const bem_surface* s, int
   if (n_k <= 0 || !k || n_rhs <= 0 || !y || !x || !rel)
     return fail(ctx, BEM_EINVAL, "bem_residual_check: bad argument");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
+  if ((st = check_k(ctx, n_k, k)) != BEM_OK) return st;
   const int n = s->n;
   const int kc = std::min(n_k, 1024);
   const size_t v = (size_t)kc * n_rhs * n;
@@ -850,6 +852,7 @@ extern "C" bem_status bem_refine_batched(bem_ctx* ctx, const bem_surface* s, int
       n_fac <= 0 || !fac_index || !(tol_step >= 0.0) || max_iter < 1 || !x)
     return fail(ctx, BEM_EINVAL, "bem_refine_batched: bad argument");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BEM_EHIP, "hipSetDevice");
+  if ((st = check_k(ctx, n_k, k)) != BEM_OK) return st;
   {
     std::vector<int32_t> fi(n_k);
     BEM_HIP_TRY(ctx, hipMemcpyAsync(fi.data(), fac_index, 4 * (size_t)n_k, hipMemcpyDeviceToHost, ctx->stream));

@@ -164,6 +164,23 @@ def test_assemble_c64_is_rounded_fp64(ctx):
     assert rel(b.cpu().numpy()[0, 0], bref) < 1e-12
 
 
+def test_residual_entry_points_reject_nonpositive_k(ctx):
+    """k <= 0 is rejected before any launch by every entry point that
+    regenerates the operator (the diagonal sums divide by k)."""
+    bodies = mixed_bodies(1)
+    ds = DeviceSurface.from_bodies(bodies)
+    n = ds.n
+    k = dev(np.array([1.0, 0.0]))
+    z = torch.zeros((2, 1, n), dtype=torch.complex128, device="cuda")
+    dg = torch.zeros((2, n, 2), dtype=torch.complex128, device="cuda")
+    with pytest.raises(native.BemError):
+        native.bem_residual_check(ctx, ds.struct, 2, k, 1, z, z)
+    with pytest.raises(native.BemError):
+        native.bem_residual(ctx, ds.struct, 2, k, 1, z, z, dg, z)
+    with pytest.raises(native.BemError):
+        native.bem_assemble(ctx, ds.struct, 2, k, 1, z, native.BEM_C128, None, n, z, dg)
+
+
 @pytest.mark.parametrize("kset", ["scattered", "grid"])
 def test_residual_matrix_free(ctx, kset):
     bodies = mixed_bodies(2)
