@@ -101,6 +101,8 @@ def main():
                          "bowl: the hard acoustic bowl's focusing of a 6-cycle pulse; "
                          "chief: interior-point rows against fictitious resonances; "
                          "quadratic: the paper's 500-element sphere, whole path")
+    ap.add_argument("--bowl-rings", type=int, default=48,
+                    help="bowl: rings of the meridian (twice as many nodes per ring)")
     ap.add_argument("--tr-level", type=int, default=5,
                     help="icosphere level of the sphere for --workload truncation")
     ap.add_argument("--tr-grid", type=int, default=256,
@@ -760,7 +762,8 @@ def run_bowl(args):
     W, T, F = 20.1, 128, 63
     dk = 2.0 * np.pi / W
     tilt = 0.15 * np.pi
-    x, nrm, w, _ = native.bem_mesh_bowl(48, 96, 1.0, tilt, (0.0, 0.0, 0.0))
+    nr_ = args.bowl_rings
+    x, nrm, w, _ = native.bem_mesh_bowl(nr_, 2 * nr_, 1.0, tilt, (0.0, 0.0, 0.0))
     bc = np.zeros(len(x), dtype=np.uint8)
     ctx = native.Context(0)
     dev = torch.device("cuda:0")
@@ -814,7 +817,7 @@ def run_bowl(args):
     out = {"metric": "hard acoustic bowl: space-time focusing gain (max |p| / incident peak)",
            "value": gain, "unit": "x incident peak", "higher_is_better": True,
            "data": "synthetic", "dtype": "c64 factors refined to f64, c64 field, f32 synthesis",
-           "config": {"workload": "paper acoustic bowl, 48 x 96 rings, tilt 0.15 pi", "n": n,
+           "config": {"workload": f"paper acoustic bowl, {nr_} x {2 * nr_} rings, tilt 0.15 pi", "n": n,
                       "n_k": F, "T": T, "points": m},
            "paper_gain": 4.5, "whole_path_s": dt, "solves_per_s": F / dt,
            "ir_iters_max": max(info[q].iters for q in range(F)),
