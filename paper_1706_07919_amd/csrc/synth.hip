@@ -10,7 +10,8 @@
 // whose output z_n gives p_{2n} = Re z_n, p_{2n+1} = Im z_n.
 //
 // Layout of the work: a workgroup takes groups of G = max(2048, H) / H points
-// in turn (its twiddle table e^{2 pi i j/T}, j < H, built once), reads their
+// in turn (its twiddle table e^{2 pi i j/T}, j < H/2, built once: the other
+// quarter turn is i times it), reads their
 // rows of U once into registers, and for every pulse packs W in pairs (m, H - m),
 // runs the FFT in place in one LDS buffer of G H values, and writes the pulse
 // as T contiguous floats per point.  The FFT is a Stockham autosort
@@ -136,7 +137,15 @@ __device__ inline void fft_stage(float2* buf, const float2* tw, float* __restric
     if constexpr (LOGNS > 0) {
       // twiddles w^r, w = e^{2 pi i jm / (Ns R)} = e^{2 pi i (jm 2^{LOGT - LOGNS - LR}) / T}:
       // w from the table (its index is below T / R <= H), its powers by products
-      const float2 w1 = tw[jm << (LOGT - LOGNS - LR)];
+      float2 w1;
+      if constexpr (R == 2) {
+        // index below H: the second quarter turn is i times the first
+        const int ix = jm << (LOGT - LOGNS - LR);
+        const float2 tq = tw[ix & (H / 2 - 1)];
+        w1 = (ix & (H / 2)) ? ci(tq) : tq;
+      } else {
+        w1 = tw[jm << (LOGT - LOGNS - LR)];   // index below T / 4 = H / 2
+      }
       v[i][1] = cm(v[i][1], w1);
       if constexpr (R >= 4) {
         const float2 w2 = cm(w1, w1), w3 = cm(w2, w1);
@@ -198,7 +207,7 @@ __device__ inline float2 wpack(float2 ya, float2 yb, float2 t) {
   return cadd(e, cm(ci(t), o));                             // + i t o
 }
 
-// LDS: tw[H]; buf[SLOTS + SLOTS / 8] (padded); (sparse) col[H + 1]: column
+// LDS: tw[H / 2] (a quarter turn); buf[SLOTS + SLOTS / 8] (padded); (sparse) col[H + 1]: column
 // of bin m, or -1.  Thread item i (i < NW) of a group is the pair of bins
 // (mm, H - mm), mm = (tid + i * 256) mod H/2, of point p0 + (tid + i * 256) /
 // (H/2), with (H, H/2) in place of (0, H): the thread loads exactly the two
@@ -207,7 +216,7 @@ __device__ inline float2 wpack(float2 ya, float2 yb, float2 t) {
 // without a column then gives Y_j = 0 from any finite X, and no load or
 // product needs a condition.
 template <bool Sparse, int LOGH>
-__global__ __launch_bounds__(kST, LOGH < 12 ? 4 : 1) void synth_kernel(
+__global__ __launch_bounds__(kST, LOGH < 12 ? 5 : 1) void synth_kernel(
     int m, int n_k, const float2* __restrict__ U, const int32_t* __restrict__ midx, int n_pulse,
     const float2* __restrict__ cbin, int add_incident, const double* __restrict__ xp, double dk,
     float* __restrict__ out) {
@@ -217,11 +226,11 @@ __global__ __launch_bounds__(kST, LOGH < 12 ? 4 : 1) void synth_kernel(
   constexpr int G = SLOTS / H;   // points per group
   constexpr int halfH = H >> 1;
   constexpr int NW = SLOTS / 2 / kST;   // pair items per thread
-  float2* tw = lds;
-  float2* buf = tw + H;
+  float2* tw = lds;   // e^{2 pi i j / T}, j < H / 2 (a quarter turn)
+  float2* buf = tw + halfH;
   int* col = reinterpret_cast<int*>(buf + SLOTS + SLOTS / 8);
   int tid = threadIdx.x;
-  for (int j = tid; j < H; j += kST) {
+  for (int j = tid; j < halfH; j += kST) {
     float s, co;
     sincospif(2.0f * (float)j / (float)T, &s, &co);
     tw[j] = make_float2(co, s);
@@ -306,8 +315,12 @@ __global__ __launch_bounds__(kST, LOGH < 12 ? 4 : 1) void synth_kernel(
         const float2 f1 = z0 ? make_float2(0.f, 0.f) : ya;
         const float2 f2 = z0 ? make_float2(ya.x, 0.f) : yb;
         const int pos2 = z0 ? halfH : H - mm;
-        buf[pad(w + mm)] = wpack(f1, f2, tw[mm]);
-        buf[pad(w + pos2)] = wpack(yb, z0 ? yb : ya, tw[pos2]);
+        // twiddles of bins mm (< H/2, in the table) and H - mm (-conj of
+        // mm's) or H/2 (i)
+        const float2 t1 = tw[mm];
+        const float2 t2 = z0 ? make_float2(0.f, 1.f) : make_float2(-t1.x, t1.y);
+        buf[pad(w + mm)] = wpack(f1, f2, t1);
+        buf[pad(w + pos2)] = wpack(yb, z0 ? yb : ya, t2);
       }
       // the next pulse's coefficients (the same for every point: with one
       // pulse they stay)
@@ -383,7 +396,7 @@ bem_status launch_synth(bem_ctx* ctx, int m, int n_k, const void* U, const int32
   const bool sparse = m_index != nullptr;
   const int slots = H > 2048 ? H : 2048;
   const int G = slots / H;
-  const size_t lds = sizeof(float2) * (size_t)(H + slots + slots / 8) +
+  const size_t lds = sizeof(float2) * (size_t)(H / 2 + slots + slots / 8) +
                      (sparse ? sizeof(int) * (size_t)(H + 1) : 0);
   if (lds > 160 * 1024)
     return fail(ctx, BEM_EUNSUPPORTED, "pulse synthesis: T = %d with %d frequencies needs %zu B of LDS",
@@ -395,10 +408,10 @@ bem_status launch_synth(bem_ctx* ctx, int m, int n_k, const void* U, const int32
   if (st != BEM_OK) return st;
   hipLaunchKernelGGL(coeff_bins_kernel, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0,
                      ctx->stream, n_pulse, n_k, H, (const double2*)c, m_index, (float2*)ws);
-  // whole rounds of resident workgroups (LDS-limited; at most 4 of 256
-  // threads per CU), each taking groups in turn
+  // whole rounds of resident workgroups (LDS-limited; at most 5 of 256
+  // threads per CU, which the registers allow), each taking groups in turn
   const int ngroups = (m + G - 1) / G;
-  const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / lds)));
+  const int per_cu = std::max(1, std::min(5, (int)((160 * 1024) / lds)));
   const int resident = ctx->num_cus * per_cu;
   const dim3 grid(ngroups < 4 * resident ? ngroups : 4 * resident);
   const float2* cbin = (const float2*)ws;

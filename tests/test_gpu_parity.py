@@ -731,7 +731,10 @@ def test_closest_node_ties_on_symmetry_plane(ctx):
 
 
 # ------------------------------------------------------------------ S9
-@pytest.mark.parametrize("T,n_k,add", [(64, 32, 0), (128, 64, 1), (512, 200, 1), (4096, 2048, 0)])
+# transform lengths T/2 = 2^5 .. 2^11: radix-8 stages ending in a radix-8,
+# radix-4 or radix-2 stage (T = 256 and 2048 end in radix 2)
+@pytest.mark.parametrize("T,n_k,add", [(64, 32, 0), (128, 64, 1), (256, 100, 0), (512, 200, 1),
+                                       (2048, 1024, 1), (4096, 2048, 0)])
 def test_synthesis_vs_oracle(ctx, T, n_k, add):
     rng = np.random.default_rng(T)
     m = 37
