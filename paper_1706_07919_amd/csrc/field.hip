@@ -518,11 +518,25 @@ __global__ __launch_bounds__(kFT, 3) void field_grouped_kernel(
       const float cr = c * (float)r;
       es *= -rinv;
       ec *= -rinv;
+      // on an even chunk the phase advances by the three-term recurrence
+      // E'_{f+1} = 2 cos(dk r) E'_f - E'_{f-1} (two multiply-adds a step; a
+      // rounding at step f grows at most f-fold over the chunk)
+      const float tc = 2.f * dec;
+      float esp = 0.f, ecp = 0.f;
 #pragma unroll
       for (int f = 0; f < FCH; ++f) {
         if (f > 0) {
           if (uni) {
-            const float e1 = ec * des + es * dec, e0 = ec * dec - es * des;
+            float e1, e0;
+            if (f == 1) {
+              e1 = ec * des + es * dec;
+              e0 = ec * dec - es * des;
+            } else {
+              e1 = fmaf(tc, es, -esp);
+              e0 = fmaf(tc, ec, -ecp);
+            }
+            esp = es;
+            ecp = ec;
             es = e1;
             ec = e0;
           } else {
