@@ -200,7 +200,8 @@ __device__ __forceinline__ void pair_terms(const AsmRow& p, const KChunk<KC>& kc
                                            int j, bool hard, double r,
                                            double s0, double wr, double wq, double nn,
                                            double (&acc)[KC][6]) {
-  double2 E = phase_e<PH>(kc.k[0] * r), F = phase_e<PH>(kc.k[0] * s0), dE, dF;
+  double2 E = phase_e<PH>(kc.k[0] * r), F = phase_e<PH>(kc.k[0] * s0), dE, dF, Ep, Fp;
+  double tE = 0.0, tF = 0.0;
   // row bases of A and y for wavenumber q0 and their steps per wavenumber,
   // made opaque here so that the per-wavenumber addresses are formed in the
   // loop rather than held in scalar registers across it
@@ -208,8 +209,12 @@ __device__ __forceinline__ void pair_terms(const AsmRow& p, const KChunk<KC>& kc
   int64_t ybase = ((int64_t)p.q0 * p.n_rhs + p.rhs) * p.n, ystep = (int64_t)p.n_rhs * p.n;
   asm volatile("" : "+s"(abase), "+s"(astep), "+s"(ybase), "+s"(ystep));
   if (PH == kPhRec) {
+    // the three-term recurrence e^{i(q+1)t} = 2 cos(t) e^{iqt} - e^{i(q-1)t}
+    // after the first step (a rounding at step q grows at most q-fold)
     dE = phase_e<PH>(kc.dk * r);
     dF = phase_e<PH>(kc.dk * s0);
+    tE = 2.0 * dE.x;
+    tF = 2.0 * dF.x;
   }
 #pragma unroll
   for (int q = 0; q < KC; ++q) {
@@ -217,8 +222,18 @@ __device__ __forceinline__ void pair_terms(const AsmRow& p, const KChunk<KC>& kc
     const double k = kc.k[q];
     if (q > 0) {
       if (PH == kPhRec) {
-        E = cmul(E, dE);
-        F = cmul(F, dF);
+        double2 En, Fn;
+        if (q == 1) {
+          En = cmul(E, dE);
+          Fn = cmul(F, dF);
+        } else {
+          En = make_double2(fma(tE, E.x, -Ep.x), fma(tE, E.y, -Ep.y));
+          Fn = make_double2(fma(tF, F.x, -Fp.x), fma(tF, F.y, -Fp.y));
+        }
+        Ep = E;
+        Fp = F;
+        E = En;
+        F = Fn;
       } else {
         E = phase_e<PH>(k * r);
         F = phase_e<PH>(k * s0);
