@@ -479,22 +479,20 @@ constexpr int kSweepKc = 4;
 constexpr int kReanchor = 64;
 constexpr int kSweepSlots = 6;   // columns per thread and part
 
-// Part p = blockIdx.y covers the columns j = t + kSweepThreads (p JPT + s);
-// part 0 writes r = b - a_ii x_i - (its sum), part p > 0 writes its sum to
-// part_out[p - 1] (subtracted by residual_parts_kernel).
+// Part p = blockIdx.y covers the columns j = t + kSweepThreads (p JPT + s)
+// and writes its sums to part_out[p]; residual_parts_kernel then forms
+// r = b - a_ii x_i - (the sum of the parts).
 template <int JPT>
 __global__ __launch_bounds__(kSweepThreads) void residual_sweep_kernel(
     int n, const double* __restrict__ x, const double* __restrict__ nrm,
     const double* __restrict__ w, const uint8_t* __restrict__ bc, const double* __restrict__ kv,
-    double dk, int nk, int n_rhs, int rhs, const double2* __restrict__ bvec,
-    const double2* __restrict__ xs, const double2* __restrict__ diag64, double2* __restrict__ r_out,
+    double dk, int nk, int n_rhs, int rhs, const double2* __restrict__ xs,
     double2* __restrict__ part_out) {
   constexpr int KC = kSweepKc, NW = kSweepThreads / 64;
   __shared__ double red[2][NW][KC][2];
   const int i = blockIdx.x, part = blockIdx.y;
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   const int64_t plane = (int64_t)nk * n_rhs * n;
-  const bool hard_i = bc[i] == BEM_BC_HARD;
   // per slot: r, the coefficient factor cf (coefficient = cf E for a soft node,
   // cf (-E.x - kr E.y, kr E.x - E.y) for a hard one; 0 for j = i and j >= n),
   // the clamped column, and the phase state
@@ -582,40 +580,39 @@ __global__ __launch_bounds__(kSweepThreads) void residual_sweep_kernel(
       }
     }
     __syncthreads();
-    if (t == 0) {
+    // lane q stores wavenumber q's sum (stores only: no wave waits on memory
+    // here); residual_parts_kernel forms r from the parts
+    if (t < kc) {
+      double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-      for (int q = 0; q < KC; ++q) {
-        if (q >= kc) break;
-        double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-        for (int v = 0; v < NW; ++v) { s0 += red[buf][v][q][0]; s1 += red[buf][v][q][1]; }
-        const int64_t kq = c0 + q;
-        const int64_t o = (kq * n_rhs + rhs) * n + i;
-        if (part > 0) {
-          part_out[(part - 1) * plane + o] = make_double2(s0, s1);
-        } else {
-          const double2 aii = diag64[(kq * n + i) * 2 + (hard_i ? 0 : 1)];
-          const double2 u = xs[o], bb = bvec[o];
-          const double2 au = cmul(aii, u);
-          r_out[o] = make_double2(bb.x - (s0 + au.x), bb.y - (s1 + au.y));
-        }
-      }
+      for (int v = 0; v < NW; ++v) { s0 += red[buf][v][t][0]; s1 += red[buf][v][t][1]; }
+      const int64_t o = ((int64_t)(c0 + t) * n_rhs + rhs) * n + i;
+      part_out[part * plane + o] = make_double2(s0, s1);
     }
   }
 }
 
-// r -= sum of the partial sums of parts 1..nparts-1
-__global__ void residual_parts_kernel(int64_t plane, int nparts, const double2* __restrict__ part_out,
+// r = b - a_ii x_i - (the sums of the parts), entry o = (k n_rhs + rhs) n + i
+__global__ void residual_parts_kernel(int64_t plane, int nparts, int n, int n_rhs,
+                                      const uint8_t* __restrict__ bc,
+                                      const double2* __restrict__ diag64,
+                                      const double2* __restrict__ xs,
+                                      const double2* __restrict__ bvec,
+                                      const double2* __restrict__ part_out,
                                       double2* __restrict__ r_out) {
   const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= plane) return;
-  double2 v = r_out[o];
-  for (int p = 1; p < nparts; ++p) {
-    const double2 s = part_out[(int64_t)(p - 1) * plane + o];
-    v.x -= s.x;
-    v.y -= s.y;
+  const int i = (int)(o % n);
+  const int64_t kq = o / ((int64_t)n * n_rhs);
+  const double2 aii = diag64[(kq * n + i) * 2 + (bc[i] == BEM_BC_HARD ? 0 : 1)];
+  const double2 au = cmul(aii, xs[o]), bb = bvec[o];
+  double sx = 0.0, sy = 0.0;
+  for (int p = 0; p < nparts; ++p) {
+    const double2 s = part_out[(int64_t)p * plane + o];
+    sx += s.x;
+    sy += s.y;
   }
-  r_out[o] = v;
+  r_out[o] = make_double2(bb.x - (sx + au.x), bb.y - (sy + au.y));
 }
 
 __global__ void incident_kernel(int n, const double* __restrict__ x, const double* __restrict__ nrm,
@@ -763,7 +760,7 @@ int residual_parts(int n) { return (n + kSweepSlots * kSweepThreads - 1) / (kSwe
 
 size_t residual_parts_bytes(int n, int n_k, int n_rhs) {
   if (n < 1024) return 0;
-  return (size_t)(residual_parts(n) - 1) * n_k * n_rhs * n * 16;
+  return (size_t)residual_parts(n) * n_k * n_rhs * n * 16;
 }
 
 bem_status launch_residual_b(bem_ctx* ctx, const bem_surface* s, int n_k, const double* k,
@@ -771,20 +768,19 @@ bem_status launch_residual_b(bem_ctx* ctx, const bem_surface* s, int n_k, const 
                              const void* diag64, void* r, void* parts) {
   if (s->n < 1024 || !(dk > 0.0)) return launch_residual(ctx, s, n_k, k, n_rhs, y, x, diag64, r);
   const int np = residual_parts(s->n);
-  if (np > 65535 || (np > 1 && !parts))
+  if (np > 65535 || !parts)
     return fail(ctx, BEM_EINVAL, "residual: %d parts need a staging buffer", np);
   const int64_t plane = (int64_t)n_k * n_rhs * s->n;
   const int pi = prof_begin(ctx, "residual");
   for (int rh = 0; rh < n_rhs; ++rh)
     hipLaunchKernelGGL((residual_sweep_kernel<kSweepSlots>), dim3(s->n, np), dim3(kSweepThreads), 0,
                        ctx->stream, s->n, s->x, s->nrm, s->w, s->bc, k, dk, n_k, n_rhs, rh,
-                       reinterpret_cast<const double2*>(b), reinterpret_cast<const double2*>(x),
-                       reinterpret_cast<const double2*>(diag64), reinterpret_cast<double2*>(r),
-                       reinterpret_cast<double2*>(parts));
-  if (np > 1)
-    hipLaunchKernelGGL(residual_parts_kernel, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0,
-                       ctx->stream, plane, np, reinterpret_cast<const double2*>(parts),
-                       reinterpret_cast<double2*>(r));
+                       reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(parts));
+  hipLaunchKernelGGL(residual_parts_kernel, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0,
+                     ctx->stream, plane, np, s->n, n_rhs, s->bc,
+                     reinterpret_cast<const double2*>(diag64), reinterpret_cast<const double2*>(x),
+                     reinterpret_cast<const double2*>(b), reinterpret_cast<const double2*>(parts),
+                     reinterpret_cast<double2*>(r));
   // one complex multiply-add per pair; x read once per pair from L2
   prof_end(ctx, "residual", pi, 8.0 * s->n * s->n * (double)n_k * n_rhs,
            16.0 * s->n * s->n * (double)n_k * n_rhs);
