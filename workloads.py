@@ -179,10 +179,6 @@ def mlp_initial_weights(sizes, seed: int = 0):
     return out
 
 
-SURROGATE_OCTAVES = 8      # Fourier features sin/cos(2^l pi k / 12), l = 0..7
-SURROGATE_HIDDEN = (512, 512, 512, 512)
-
-
 def interior_points(bodies: List[Body], per_body: int = 8, seed: int = 0,
                     frac=(0.2, 0.6)) -> np.ndarray:
     """Random points strictly inside each body (seeded): a direction uniform on
