@@ -208,6 +208,21 @@ __device__ __forceinline__ void pair_terms(const AsmRow& p, const KChunk<KC>& kc
   int64_t abase = (int64_t)p.q0 * p.a_stride + (int64_t)p.i * p.ld, astep = p.a_stride;
   int64_t ybase = ((int64_t)p.q0 * p.n_rhs + p.rhs) * p.n, ystep = (int64_t)p.n_rhs * p.n;
   asm volatile("" : "+s"(abase), "+s"(astep), "+s"(ybase), "+s"(ystep));
+  // the known data of column j for the chunk, loaded before any store of the
+  // row (the stores to A could otherwise alias them and hold each load back
+  // until its use) so that the loads are in flight during the phases
+  double2 yv[KC];
+  if (RHS && PH == kPhRec) {
+#pragma unroll
+    for (int q = 0; q < KC; ++q) yv[q] = p.y[ybase + q * ystep + j];
+  }
+  double kr_s = 0.0, kn_s = 0.0, dkr = 0.0, dkn = 0.0;
+  if (PH == kPhRec) {
+    kr_s = kc.k[0] * r;
+    kn_s = kc.k[0] * nn;
+    dkr = kc.dk * r;
+    dkn = kc.dk * nn;
+  }
   if (PH == kPhRec) {
     // the three-term recurrence e^{i(q+1)t} = 2 cos(t) e^{iqt} - e^{i(q-1)t}
     // after the first step (a rounding at step q grows at most q-fold)
@@ -218,8 +233,18 @@ __device__ __forceinline__ void pair_terms(const AsmRow& p, const KChunk<KC>& kc
   }
 #pragma unroll
   for (int q = 0; q < KC; ++q) {
-    if (q >= kc.kc) break;   // workgroup-uniform
+    // workgroup-uniform; the recurrence runs on whole chunks only, so its
+    // loop has no exits
+    if (PH != kPhRec && q >= kc.kc) break;
     const double k = kc.k[q];
+    if (PH == kPhRec) {
+      // k r and k (n_i.n_j) stepped along the chunk (the wavenumbers are then
+      // not held across the pair loop)
+      if (q > 0) {
+        kr_s += dkr;
+        kn_s += dkn;
+      }
+    }
     if (q > 0) {
       if (PH == kPhRec) {
         double2 En, Fn;
@@ -239,14 +264,14 @@ __device__ __forceinline__ void pair_terms(const AsmRow& p, const KChunk<KC>& kc
         F = phase_e<PH>(k * s0);
       }
     }
-    const double kr = k * r;
+    const double kr = PH == kPhRec ? kr_s : k * r;
     // w G = w E / r,  w H = w E (ikr - 1)(d.n_j) / r^3
     const double2 wG = make_double2(wr * E.x, wr * E.y);
     const double2 wH = make_double2(wq * fma(-kr, E.y, -E.x), wq * fma(kr, E.x, -E.y));
     // g = cos(k s0), f = sin(k s0)/k, g' = -k sin(k s0) nn, f' = cos(k s0) nn;
     // the psi sums are accumulated times k (k f' wG - k f wH, divided by k at
     // the end)
-    const double kn = k * nn;
+    const double kn = PH == kPhRec ? kn_s : k * nn;
     const double g = F.x, gp = -kn * F.y, kfp = kn * F.x;
     acc[q][0] = fma(gp, wG.x, fma(-g, wH.x, acc[q][0]));
     acc[q][1] = fma(gp, wG.y, fma(-g, wH.y, acc[q][1]));
@@ -263,7 +288,7 @@ __device__ __forceinline__ void pair_terms(const AsmRow& p, const KChunk<KC>& kc
         reinterpret_cast<float2*>(p.A)[abase + q * astep + j] = make_float2((float)a.x, (float)a.y);
     }
     if (RHS) {
-      const double2 yy = p.y[ybase + q * ystep + j];
+      const double2 yy = PH == kPhRec ? yv[q] : p.y[ybase + q * ystep + j];
       acc[q][4] = fma(bb.x, yy.x, fma(-bb.y, yy.y, acc[q][4]));
       acc[q][5] = fma(bb.x, yy.y, fma(bb.y, yy.x, acc[q][5]));
     }
@@ -283,18 +308,39 @@ __device__ __forceinline__ bool row_terms(const AsmRow& p, const KChunk<KC>& kc,
   const double xi = x[3 * i], yi = x[3 * i + 1], zi = x[3 * i + 2];
   const double nix = nrm[3 * i], niy = nrm[3 * i + 1], niz = nrm[3 * i + 2];
   bool wide = false;
+  // the node data of the thread's next column is loaded one column ahead (the
+  // index clamped to the last node), so its latency falls on the current pair
+  struct Node {
+    double x0, x1, x2, n0, n1, n2, w;
+    uint8_t bc;
+  };
+  auto node = [&](int j) {
+    Node d;
+    d.x0 = x[3 * j];
+    d.x1 = x[3 * j + 1];
+    d.x2 = x[3 * j + 2];
+    d.n0 = nrm[3 * j];
+    d.n1 = nrm[3 * j + 1];
+    d.n2 = nrm[3 * j + 2];
+    d.w = w[j];
+    d.bc = bc[j];
+    return d;
+  };
+  Node nx = node(min((int)threadIdx.x, p.n - 1));
   for (int j = threadIdx.x; j < p.n; j += kThreads) {
+    const Node c = nx;
+    nx = node(min(j + kThreads, p.n - 1));
     if (j == i) continue;
-    const double dx = x[3 * j] - xi, dy = x[3 * j + 1] - yi, dz = x[3 * j + 2] - zi;
-    const double njx = nrm[3 * j], njy = nrm[3 * j + 1], njz = nrm[3 * j + 2];
+    const double dx = c.x0 - xi, dy = c.x1 - yi, dz = c.x2 - zi;
+    const double njx = c.n0, njy = c.n1, njz = c.n2;
     const double r = sqrt(dx * dx + dy * dy + dz * dz);
     const double rinv = 1.0 / r;
-    const double wj = w[j];
+    const double wj = c.w;
     const double wq = wj * ((dx * njx + dy * njy + dz * njz) * (rinv * rinv * rinv));
     const double wr = wj * rinv;
     const double s0 = nix * dx + niy * dy + niz * dz;
     const double nn = nix * njx + niy * njy + niz * njz;
-    const bool hard = bc[j] == BEM_BC_HARD;
+    const bool hard = c.bc == BEM_BC_HARD;
     if (PH != kPhWide) wide |= !(kmax * fmax(r, fabs(s0)) < kPhaseNear);
     pair_terms<KC, OUT128, WRITE_A, RHS, PH>(p, kc, j, hard, r, s0, wr, wq, nn, acc);
   }
@@ -327,7 +373,7 @@ __global__ __launch_bounds__(kThreads, 2) void assemble_kc_kernel(
     for (int c = 0; c < 6; ++c) acc[q][c] = 0.0;
   constexpr bool WA = FIRST && STORE_A;
   bool wide;
-  if (kc.uniform)
+  if (kc.uniform && kc.kc == KC)
     wide = row_terms<KC, OUT128, WA, RHS, kPhRec>(p, kc, kmax, x, nrm, w, bc, acc);
   else
     wide = row_terms<KC, OUT128, WA, RHS, kPhNear>(p, kc, kmax, x, nrm, w, bc, acc);
