@@ -20,6 +20,8 @@
 // partial sums are combined by a butterfly at the end: the float32 sums then
 // run over n / kParts terms each, which bounds their rounding error kParts
 // times tighter than one chain over all n nodes.
+#include <type_traits>
+
 #include "common.h"
 
 namespace bem {
@@ -262,7 +264,7 @@ __global__ __launch_bounds__(kFT, sizeof(R) == 4 ? 3 : 1) void field_kernel(
         const R hr = ec * wh2 - es * hb, hi = ec * hb + es * wh2;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-          if (r >= nrh) break;   // uniform
+          if (NR > 1 && r >= nrh) break;   // uniform (one right-hand side: nrh = 1)
           const C ph = sphi[r][f][jj], ps = spsi[r][f][jj];
           A1[r][f].x += (ph.x * hr - ph.y * hi) - (ps.x * gr - ps.y * gi);
           A1[r][f].y += (ph.x * hi + ph.y * hr) - (ps.x * gi + ps.y * gr);
@@ -503,7 +505,10 @@ __global__ __launch_bounds__(kFT, 3) void field_grouped_kernel(
     if (!valid) continue;
     // the lane's nodes alternate between two partial sums (halving the
     // length of each float32 chain)
-    auto term = [&](int jj, float2 (&Sh)[NR][FCH]) {
+    // uni_c: std::true_type / std::false_type (the test folded away) or a
+    // runtime bool
+    auto term = [&](int jj, float2 (&Sh)[NR][FCH], auto uni_c) {
+      const bool UNI = static_cast<bool>(uni_c);
       if (j0 + jj == a) return;   // its brackets vanish (and r = 0 for a point on the node)
       const double dx = sx[jj][0] - px, dy = sx[jj][1] - py, dz = sx[jj][2] - pz;
       const double r = sqrt(dx * dx + dy * dy + dz * dz);
@@ -514,7 +519,7 @@ __global__ __launch_bounds__(kFT, 3) void field_grouped_kernel(
                       (rinv * rinv);
       float es, ec, des = 0.f, dec = 1.f;
       phase<float>(kk[0] * r, es, ec);
-      if (uni) phase<float>(dkk * r, des, dec);
+      if (UNI) phase<float>(dkk * r, des, dec);
       const float cr = c * (float)r;
       es *= -rinv;
       ec *= -rinv;
@@ -526,7 +531,7 @@ __global__ __launch_bounds__(kFT, 3) void field_grouped_kernel(
 #pragma unroll
       for (int f = 0; f < FCH; ++f) {
         if (f > 0) {
-          if (uni) {
+          if (UNI) {
             float e1, e0;
             if (f == 1) {
               e1 = ec * des + es * dec;
@@ -548,7 +553,7 @@ __global__ __launch_bounds__(kFT, 3) void field_grouped_kernel(
         const float cq = (float)kk[f] * cr;   // c k r
 #pragma unroll
         for (int rr = 0; rr < NR; ++rr) {
-          if (rr >= nrh) break;   // uniform
+          if (NR > 1 && rr >= nrh) break;   // uniform (one right-hand side: nrh = 1)
           const float2 u = su[rr][f][jj], v = sv[rr][f][jj];
           const float tx = fmaf(c, u.x, fmaf(cq, u.y, v.x));
           const float ty = fmaf(c, u.y, fmaf(-cq, u.x, v.y));
@@ -557,9 +562,22 @@ __global__ __launch_bounds__(kFT, 3) void field_grouped_kernel(
         }
       }
     };
-    for (int jj = part; jj < cnt; jj += 2 * kParts) {
-      term(jj, S);
-      if (jj + kParts < cnt) term(jj + kParts, S1);
+    auto nodes = [&](auto uni_c) {
+      for (int jj = part; jj < cnt; jj += 2 * kParts) {
+        term(jj, S, uni_c);
+        if (jj + kParts < cnt) term(jj + kParts, S1, uni_c);
+      }
+    };
+    // one right-hand side: the even-chunk test is hoisted out of the node loop
+    // (no per-frequency branch inside it); with several, the two loop bodies
+    // would not fit the register budget, so the test stays inside
+    if constexpr (NR == 1) {
+      if (uni)
+        nodes(std::true_type{});
+      else
+        nodes(std::false_type{});
+    } else {
+      nodes(uni);
     }
   }
 #pragma unroll
