@@ -12,6 +12,8 @@
 #include <algorithm>
 #include <climits>
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace bem {
@@ -869,7 +871,10 @@ __device__ __forceinline__ void gemm_lds_tile(const LuGroups& G, const GemmList&
         o.b[j][e] = Bf[kk * BN + bcol0 + 32 * j];
       }
   };
-  auto mma = [&](const Ops& o) {
+  // ALL: every MFMA block of the wave is live (interior tiles), so the
+  // block loop carries no per-block branch
+  auto mma = [&](const Ops& o, auto all_live) {
+    constexpr bool ALL = decltype(all_live)::value;
     if constexpr (M3) {
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
@@ -890,7 +895,7 @@ __device__ __forceinline__ void gemm_lds_tile(const LuGroups& G, const GemmList&
         for (int i = 0; i < 2; ++i)
 #pragma unroll
           for (int j = 0; j < WJ; ++j) {
-            if (live_i[i] && live_j[j]) {
+            if (ALL || (live_i[i] && live_j[j])) {
               acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i], br[j], acc[0][i][j], 0, 0, 0);
               acc[1][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[i], bi[j], acc[1][i][j], 0, 0, 0);
               acc[2][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(as[i], bs[j], acc[2][i][j], 0, 0, 0);
@@ -917,7 +922,7 @@ __device__ __forceinline__ void gemm_lds_tile(const LuGroups& G, const GemmList&
         for (int i = 0; i < 2; ++i)
 #pragma unroll
           for (int j = 0; j < WJ; ++j) {
-            if (live_i[i] && live_j[j]) {
+            if (ALL || (live_i[i] && live_j[j])) {
               acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], bre[j], acc[0][i][j], 0, 0, 0);
               acc[1][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], bim[j], acc[1][i][j], 0, 0, 0);
             }
@@ -940,31 +945,42 @@ __device__ __forceinline__ void gemm_lds_tile(const LuGroups& G, const GemmList&
       if ((q * 256 + tt) / (BN / 2) >= kvalid) Bs[cur][q * 256 + tt] = z;
   };
 
-  load_stage(0);
-  for (int s = 0; s < S; ++s) {
-    // stage s has landed, and every wave is past its reads of stage s - 1,
-    // whose buffer the next load reuses
-    asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
-    const int cur = s & 1;
-    const int kvalid = K - s * GL_BK;
-    if (kvalid < GL_BK) {
-      zero_tail(cur, kvalid);
-      __syncthreads();
-    }
-    if (s + 1 < S) load_stage(s + 1);
-    // the next group's operands are read while the current group's MFMAs run
-    const u32x4* Ab = &As[cur][0];
-    const float2* Bf = (const float2*)&Bs[cur][0];
-    Ops o[2];
-    read_ops(Ab, Bf, 0, o[0]);
+  auto kloop = [&](auto all_live) {
+    load_stage(0);
+    for (int s = 0; s < S; ++s) {
+      // stage s has landed, and every wave is past its reads of stage s - 1,
+      // whose buffer the next load reuses
+      asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+      const int cur = s & 1;
+      const int kvalid = K - s * GL_BK;
+      if (kvalid < GL_BK) {
+        zero_tail(cur, kvalid);
+        __syncthreads();
+      }
+      if (s + 1 < S) load_stage(s + 1);
+      // the next group's operands are read while the current group's MFMAs run
+      const u32x4* Ab = &As[cur][0];
+      const float2* Bf = (const float2*)&Bs[cur][0];
+      Ops o[2];
+      read_ops(Ab, Bf, 0, o[0]);
 #pragma unroll
-    for (int q4 = 0; q4 < 4; ++q4) {
-      if (q4 + 1 < 4) read_ops(Ab, Bf, q4 + 1, o[(q4 + 1) & 1]);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(o[q4 & 1]);
-      __builtin_amdgcn_sched_barrier(0);
+      for (int q4 = 0; q4 < 4; ++q4) {
+        if (q4 + 1 < 4) read_ops(Ab, Bf, q4 + 1, o[(q4 + 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(o[q4 & 1], all_live);
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
-  }
+  };
+  bool all = true;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) all = all && live_i[i];
+#pragma unroll
+  for (int j = 0; j < WJ; ++j) all = all && live_j[j];
+  if (all)
+    kloop(std::true_type{});
+  else
+    kloop(std::false_type{});
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
