@@ -47,6 +47,11 @@ template <typename C> __device__ inline C cmul(C a, C b) {
   return cmk<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 template <typename C> __device__ inline C csub(C a, C b) { return cmk<C>(a.x - b.x, a.y - b.y); }
+// s - a b as four fused multiply-adds (one rounding per real product-sum
+// instead of a rounded product then a subtraction)
+template <typename C> __device__ inline C cfms(C s, C a, C b) {
+  return cmk<C>(fma(-a.x, b.x, fma(a.y, b.y, s.x)), fma(-a.x, b.y, fma(-a.y, b.x, s.y)));
+}
 template <typename C> __device__ inline C crecip(C a) {
   // 1/a with scaling to avoid overflow (Smith's method)
   using R = decltype(C::x);
@@ -244,7 +249,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_kernel(LuGroups G, int c0
         const C l = cmul(a[q][c], inv);
         a[q][c] = l;
 #pragma unroll
-        for (int cc = c + 1; cc < W; ++cc) a[q][cc] = csub(a[q][cc], cmul(l, u[cc]));
+        for (int cc = c + 1; cc < W; ++cc) a[q][cc] = cfms(a[q][cc], l, u[cc]);
       }
     }
   }
@@ -413,7 +418,7 @@ __global__ __launch_bounds__(256) void trsm_kernel(LuGroups G, int r0, int m1_al
       C s = x[i];
 #pragma unroll
       for (int j = 0; j < 32; ++j)
-        if (j < i) s = csub(s, cmul(L[i][j], x[j]));
+        if (j < i) s = cfms(s, L[i][j], x[j]);
       x[i] = s;
     }
   }
