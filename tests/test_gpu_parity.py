@@ -56,14 +56,16 @@ def test_incident_known_data(ctx):
 
 
 # ------------------------------------------------------------------ S3/S4
-# wavenumber sets: scattered values (one sincos per wavenumber) and an evenly
+# wavenumber sets: scattered values (one sincos per wavenumber), an evenly
 # spaced grid with a ragged last chunk whose tail breaks the spacing (phase
-# recurrence inside the uniform chunks, direct evaluation in the rest)
+# recurrence inside the uniform chunks, direct evaluation in the rest), and an
+# evenly spaced grid whose last chunk is evenly spaced but partial (13 = 8 + 5)
 K_SETS = {"scattered": np.array([0.7, 3.1, 9.4]),
-          "grid": np.concatenate([0.75 * np.arange(1, 10), [7.9, 11.3]])}
+          "grid": np.concatenate([0.75 * np.arange(1, 10), [7.9, 11.3]]),
+          "even13": 0.5 * np.arange(1, 14)}
 
 
-@pytest.mark.parametrize("kset", ["scattered", "grid"])
+@pytest.mark.parametrize("kset", ["scattered", "grid", "even13"])
 @pytest.mark.parametrize("level", [1, 2])
 def test_assemble_c128_entries_diag_rhs(ctx, level, kset):
     bodies = mixed_bodies(level)
@@ -181,7 +183,7 @@ def test_residual_entry_points_reject_nonpositive_k(ctx):
         native.bem_assemble(ctx, ds.struct, 2, k, 1, z, native.BEM_C128, None, n, z, dg)
 
 
-@pytest.mark.parametrize("kset", ["scattered", "grid"])
+@pytest.mark.parametrize("kset", ["scattered", "grid", "even13"])
 def test_residual_matrix_free(ctx, kset):
     bodies = mixed_bodies(2)
     s = Surface(bodies)
