@@ -43,11 +43,14 @@ DOMINANT = {
                              "bf16, operands pre-split)", 3.0, PEAK_BF16_MFMA),
 }
 MODES = None     # filled on first use (needs the binding)
-# flops per field term: the compiled inner loop of field_kernel (c64) issues
-# 304 VALU instructions per node and 8 frequencies plus about 60 per node for
-# the float64 geometry and phases, i.e. about 47 single-precision operations
-# per (point, frequency, node) term
-FIELD_FLOPS_PER_TERM = 47.0
+# VALU instructions per field term: the compiled node loop of
+# field_grouped_kernel<8, 1> issues 289 per pass over two nodes and a chunk of
+# 8 frequencies (the float64 geometry and phases of the pair included), i.e.
+# about 18 per (point, frequency, node) term, one lane each
+FIELD_VALU_PER_TERM = 289.0 / 16.0
+# non-packed VALU issue: 256 CUs x 4 SIMDs x 16 lanes per cycle at 2.4 GHz (a
+# wave64 instruction every 4 cycles per SIMD); packed float32 is not used
+PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 
 class KernelTotals:
@@ -496,9 +499,10 @@ def run_spacetime(args, ctx=None, mode=None):
                       "T": T},
            "solve_s": t1 - t0, "solves_per_s": nk / (t1 - t0), "field_s": t2 - t1,
            "field_terms_per_s": terms / (t2 - t1),
-           "field_alu_frac": terms * FIELD_FLOPS_PER_TERM / (t2 - t1) / PEAK_F32_MFMA,
-           "field_alu_note": f"{FIELD_FLOPS_PER_TERM:g} float32 operations per term against the "
-                             "157.3 TFLOP/s FP32 vector peak",
+           "field_alu_frac": terms * FIELD_VALU_PER_TERM / (t2 - t1) / PEAK_VALU_LANE_OPS,
+           "field_alu_note": f"{FIELD_VALU_PER_TERM:.1f} issued VALU instructions per term (one lane "
+                             "each) against the non-packed VALU issue rate of 3.93e13 lane "
+                             "instructions/s (256 CUs x 64 lanes x 2.4 GHz)",
            "inside_points": int(ins.sum().item()),
            "synthesis_s": t3 - t2, "synthesis_GBps": syn_bytes / (t3 - t2) / 1e9,
            "synthesis_hbm_frac": syn_bytes / (t3 - t2) / PEAK_HBM,
