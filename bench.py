@@ -48,9 +48,10 @@ MODES = None     # filled on first use (needs the binding)
 # 8 frequencies (the float64 geometry and phases of the pair included), i.e.
 # about 18 per (point, frequency, node) term, one lane each
 FIELD_VALU_PER_TERM = 289.0 / 16.0
-# non-packed VALU issue: 256 CUs x 4 SIMDs x 16 lanes per cycle at 2.4 GHz (a
-# wave64 instruction every 4 cycles per SIMD); packed float32 is not used
-PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# the FP32 vector peak (157.3 TFLOP/s) as lane instructions, one multiply-add
+# each: 7.87e13/s (the SIMDs issue float32 instructions faster than one per 4
+# cycles per wave64, as the VALU counters of the field kernel show)
+PEAK_VALU_LANE_OPS = 157.3e12 / 2
 
 
 class KernelTotals:
@@ -501,8 +502,8 @@ def run_spacetime(args, ctx=None, mode=None):
            "field_terms_per_s": terms / (t2 - t1),
            "field_alu_frac": terms * FIELD_VALU_PER_TERM / (t2 - t1) / PEAK_VALU_LANE_OPS,
            "field_alu_note": f"{FIELD_VALU_PER_TERM:.1f} issued VALU instructions per term (one lane "
-                             "each) against the non-packed VALU issue rate of 3.93e13 lane "
-                             "instructions/s (256 CUs x 64 lanes x 2.4 GHz)",
+                             "each) against the FP32 vector peak as lane multiply-adds "
+                             "(157.3 TFLOP/s / 2 = 7.87e13/s)",
            "inside_points": int(ins.sum().item()),
            "synthesis_s": t3 - t2, "synthesis_GBps": syn_bytes / (t3 - t2) / 1e9,
            "synthesis_hbm_frac": syn_bytes / (t3 - t2) / PEAK_HBM,
