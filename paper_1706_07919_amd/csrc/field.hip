@@ -511,8 +511,13 @@ __global__ __launch_bounds__(kFT, 3) void field_grouped_kernel(
       const bool UNI = static_cast<bool>(uni_c);
       if (j0 + jj == a) return;   // its brackets vanish (and r = 0 for a point on the node)
       const double dx = sx[jj][0] - px, dy = sx[jj][1] - py, dz = sx[jj][2] - pz;
-      const double r = sqrt(dx * dx + dy * dy + dz * dz);
-      const float rinv = __builtin_amdgcn_rcpf((float)r);
+      // r from the float32 reciprocal square root of r^2 and one Newton step in
+      // float64 (relative error ~1e-14, ample for the float64 phase k r);
+      // that reciprocal is also the kernel's float32 1/r
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const float rinv = __builtin_amdgcn_rsqf((float)r2);
+      double r = r2 * (double)rinv;
+      r = fma(fma(-r, r, r2), 0.5 * (double)rinv, r);
       // u H - v G = E' t with E' = -E / r (rotated like E) and
       // t = c u (1 - ikr) + v, c = (d.n_j)/r^2
       const float c = ((float)dx * snrm[jj][0] + (float)dy * snrm[jj][1] + (float)dz * snrm[jj][2]) *
