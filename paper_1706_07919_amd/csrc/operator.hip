@@ -24,6 +24,18 @@ __device__ inline double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// r and 1/r from r^2 > 0 in float64: the float32 reciprocal square root
+// refined by two Newton steps y <- y (3 - r^2 y^2) / 2 (each squares the
+// relative error: ~1e-7, ~1e-14, then float64 rounding), without the
+// library's square root and division sequences
+__device__ inline void dist_and_inverse(double r2, double& r, double& rinv) {
+  double y = (double)__builtin_amdgcn_rsqf((float)r2);
+  y *= fma(-0.5 * r2, y * y, 1.5);
+  y *= fma(-0.5 * r2, y * y, 1.5);
+  rinv = y;
+  r = r2 * y;
+}
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -333,8 +345,8 @@ __device__ __forceinline__ bool row_terms(const AsmRow& p, const KChunk<KC>& kc,
     if (j == i) continue;
     const double dx = c.x0 - xi, dy = c.x1 - yi, dz = c.x2 - zi;
     const double njx = c.n0, njy = c.n1, njz = c.n2;
-    const double r = sqrt(dx * dx + dy * dy + dz * dz);
-    const double rinv = 1.0 / r;
+    double r, rinv;
+    dist_and_inverse(dx * dx + dy * dy + dz * dz, r, rinv);
     const double wj = c.w;
     const double wq = wj * ((dx * njx + dy * njy + dz * njz) * (rinv * rinv * rinv));
     const double wr = wj * rinv;
