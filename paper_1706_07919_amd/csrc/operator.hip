@@ -551,12 +551,12 @@ __global__ __launch_bounds__(kSweepThreads) void residual_sweep_kernel(
   const int i = blockIdx.x, part = blockIdx.y;
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   const int64_t plane = (int64_t)nk * n_rhs * n;
-  // per slot: r, the coefficient factor cf (coefficient = cf E for a soft node,
-  // cf (-E.x - kr E.y, kr E.x - E.y) for a hard one; 0 for j = i and j >= n),
-  // the clamped column, and the phase state
-  double rr[JPT], cf[JPT];
+  // per slot: r, the coefficient of the unknown as E (ca + i k cb) (a soft node:
+  // ca = w/r, cb = 0; a hard one: -w H = E (ca + i k cb) with ca = w (d.n)/r^3,
+  // cb = -w (d.n)/r^2; all 0 for j = i and j >= n), the clamped column, and the
+  // phase state
+  double rr[JPT], ca[JPT], cb[JPT];
   int jj[JPT];
-  unsigned hmask = 0;
   double2 e[JPT], d[JPT];
   {
     const double xi = x[3 * i], yi = x[3 * i + 1], zi = x[3 * i + 2];
@@ -565,18 +565,20 @@ __global__ __launch_bounds__(kSweepThreads) void residual_sweep_kernel(
       const int j = t + (part * JPT + sl) * kSweepThreads;
       jj[sl] = min(j, n - 1);
       rr[sl] = 0.0;
-      cf[sl] = 0.0;
+      ca[sl] = 0.0;
+      cb[sl] = 0.0;
       if (j < n && j != i) {
         const double dx = x[3 * j] - xi, dy = x[3 * j + 1] - yi, dz = x[3 * j + 2] - zi;
         const double r = sqrt(dx * dx + dy * dy + dz * dz);
         const double rinv = 1.0 / r;
         rr[sl] = r;
         if (bc[j] == BEM_BC_HARD) {
-          hmask |= 1u << sl;
-          cf[sl] = -w[j] * (dx * nrm[3 * j] + dy * nrm[3 * j + 1] + dz * nrm[3 * j + 2]) *
-                   (rinv * rinv * rinv);
+          const double cf = -w[j] * (dx * nrm[3 * j] + dy * nrm[3 * j + 1] + dz * nrm[3 * j + 2]) *
+                            (rinv * rinv * rinv);
+          ca[sl] = -cf;
+          cb[sl] = cf * r;
         } else {
-          cf[sl] = w[j] * rinv;
+          ca[sl] = w[j] * rinv;
         }
       }
     }
@@ -605,19 +607,17 @@ __global__ __launch_bounds__(kSweepThreads) void residual_sweep_kernel(
       }
 #pragma clang loop unroll(full)
       for (int sl = 0; sl < JPT; ++sl) {
-        const double r = rr[sl];
         double2 u[KC];
 #pragma unroll
         for (int q = 0; q < KC; ++q)
           u[q] = xs[((int64_t)(q < kc ? c0 + q : c0) * n_rhs + rhs) * n + jj[sl]];
-        const bool hard = (hmask >> sl) & 1u;
 #pragma unroll
         for (int q = 0; q < KC; ++q) {
           const double2 E = e[sl];
           e[sl] = cmul(e[sl], d[sl]);
-          const double kr = kk[q] * r;
-          const double2 P = hard ? make_double2(-E.x - kr * E.y, kr * E.x - E.y) : E;
-          const double ax = cf[sl] * P.x, ay = cf[sl] * P.y;
+          // the coefficient E (ca + i k cb): no select between the node kinds
+          const double bk = cb[sl] * kk[q];
+          const double ax = fma(E.x, ca[sl], -E.y * bk), ay = fma(E.x, bk, E.y * ca[sl]);
           acc[q][0] += ax * u[q].x - ay * u[q].y;
           acc[q][1] += ax * u[q].y + ay * u[q].x;
         }
