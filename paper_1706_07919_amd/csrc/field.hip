@@ -111,6 +111,13 @@ __device__ inline void phase<float>(double theta, float& s, float& c) {
   s = __builtin_amdgcn_sinf(tf);   // argument in revolutions
   c = __builtin_amdgcn_cosf(tf);
 }
+// the same from the phase in revolutions (t = theta / 2 pi)
+__device__ inline void phase_rev(double t, float& s, float& c) {
+  t -= rint(t);
+  const float tf = (float)t;
+  s = __builtin_amdgcn_sinf(tf);
+  c = __builtin_amdgcn_cosf(tf);
+}
 template <>
 __device__ inline void phase<double>(double theta, double& s, double& c) {
   sincos(theta, &s, &c);
@@ -462,6 +469,7 @@ __global__ __launch_bounds__(kFT, 3) void field_grouped_kernel(
 #pragma unroll
   for (int f = 1; f < FCH; ++f)
     if (f < nf && !(fabs(kk[f] - (kk[0] + f * dkk)) <= 4e-16 * fabs(kk[f]))) uni = false;
+  const double k0rev = kk[0] * kInv2Pi, dkrev = dkk * kInv2Pi;
   float2 S[NR][FCH], S1[NR][FCH];
 #pragma unroll
   for (int r = 0; r < NR; ++r)
@@ -523,8 +531,9 @@ __global__ __launch_bounds__(kFT, 3) void field_grouped_kernel(
       const float c = ((float)dx * snrm[jj][0] + (float)dy * snrm[jj][1] + (float)dz * snrm[jj][2]) *
                       (rinv * rinv);
       float es, ec, des = 0.f, dec = 1.f;
-      phase<float>(kk[0] * r, es, ec);
-      if (UNI) phase<float>(dkk * r, des, dec);
+      // (the wavenumbers carry the 1 / 2 pi of the reduction)
+      phase_rev(k0rev * r, es, ec);
+      if (UNI) phase_rev(dkrev * r, des, dec);
       const float cr = c * (float)r;
       es *= -rinv;
       ec *= -rinv;
