@@ -44,10 +44,10 @@ DOMINANT = {
 }
 MODES = None     # filled on first use (needs the binding)
 # VALU instructions per field term: the compiled node loop of
-# field_grouped_kernel<8, 1> issues 265 per pass over two nodes and a chunk of
+# field_grouped_kernel<8, 1> issues 261 per pass over two nodes and a chunk of
 # 8 frequencies (the float64 geometry and phases of the pair included), i.e.
-# about 16.6 per (point, frequency, node) term, one lane each
-FIELD_VALU_PER_TERM = 265.0 / 16.0
+# about 16.3 per (point, frequency, node) term, one lane each
+FIELD_VALU_PER_TERM = 261.0 / 16.0
 # the FP32 vector peak (157.3 TFLOP/s) as lane instructions, one multiply-add
 # each: 7.87e13/s (the SIMDs issue float32 instructions faster than one per 4
 # cycles per wave64, as the VALU counters of the field kernel show)
