@@ -447,6 +447,10 @@ __global__ __launch_bounds__(kFT, 3) void field_grouped_kernel(
   __shared__ double sx[kNJ][3];
   __shared__ float2 su[NR][FCH][kNJ], sv[NR][FCH][kNJ];
   __shared__ float snrm[kNJ][3];
+  // per chunk frequency f: k, 1/k, and phi, psi of node a per right-hand side
+  // (looked up by the bracket loop, whose f varies per thread)
+  __shared__ double skk[FCH], skinv[FCH];
+  __shared__ double2 spa[NR][FCH], sqa[NR][FCH];
   if ((int)blockIdx.x >= *nchunks) return;   // uniform
   const int4 ch = chunks[blockIdx.x];
   const int a = ch.x, start = ch.y, len = ch.z;
@@ -469,6 +473,23 @@ __global__ __launch_bounds__(kFT, 3) void field_grouped_kernel(
 #pragma unroll
   for (int f = 1; f < FCH; ++f)
     if (f < nf && !(fabs(kk[f] - (kk[0] + f * dkk)) <= 4e-16 * fabs(kk[f]))) uni = false;
+  if (threadIdx.x < FCH) {
+    const double kf0 = kv[m0 + min((int)threadIdx.x, nf - 1)];
+    skk[threadIdx.x] = kf0;
+    skinv[threadIdx.x] = 1.0 / kf0;
+  }
+  if (threadIdx.x < NR * FCH) {
+    const int r = threadIdx.x / FCH, f = threadIdx.x % FCH;
+    double2 pa = make_double2(0.0, 0.0), qa = pa;
+    if (r < nrh && f < nf) {
+      const int64_t va = ((int64_t)(m0 + f) * n_rhs + r0 + r) * n;
+      pa = phi[va + a];
+      qa = psi[va + a];
+    }
+    spa[r][f] = pa;
+    sqa[r][f] = qa;
+  }
+  // (the node loop's first barrier publishes these tables)
   const double k0rev = kk[0] * kInv2Pi, dkrev = dkk * kInv2Pi;
   float2 S[NR][FCH], S1[NR][FCH];
 #pragma unroll
@@ -488,7 +509,7 @@ __global__ __launch_bounds__(kFT, 3) void field_grouped_kernel(
       float2 uu = make_float2(0.f, 0.f), vv = uu;
       const int j = j0 + jj;
       if (r < nrh && f < nf && jj < cnt && j != a) {
-        const double k = kk[f];
+        const double k = skk[f];
         const double njx = nrm[3 * j], njy = nrm[3 * j + 1], njz = nrm[3 * j + 2];
         const double sa = anx * (x[3 * j] - ax) + any * (x[3 * j + 1] - ay) + anz * (x[3 * j + 2] - az);
         const double nn = anx * njx + any * njy + anz * njz;
@@ -497,9 +518,9 @@ __global__ __launch_bounds__(kFT, 3) void field_grouped_kernel(
         float fsn, fcs;
         phase<float>(k * sa, fsn, fcs);
         const double sn = fsn, cs = fcs;
-        const double g = cs, fv = sn / k, gp = -k * sn * nn, fp = cs * nn;
+        const double g = cs, fv = sn * skinv[f], gp = -k * sn * nn, fp = cs * nn;
         const int64_t va = ((int64_t)(m0 + f) * n_rhs + r0 + r) * n;
-        const double2 pa = phi[va + a], qa = psi[va + a], pj = phi[va + j], qj = psi[va + j];
+        const double2 pa = spa[r][f], qa = sqa[r][f], pj = phi[va + j], qj = psi[va + j];
         const double wj = w[j];
         uu = make_float2((float)(wj * (pj.x - pa.x * g - qa.x * fv)),
                          (float)(wj * (pj.y - pa.y * g - qa.y * fv)));
